@@ -1,0 +1,7 @@
+"""CPU oracle for the pseudo-spectral Navier-Stokes step (test infrastructure).
+
+Only the tests, the package's smoke check and the benchmark's CPU-baseline leg
+may import this package.  The GPU library never imports, links or calls it.
+"""
+from .spectral_ns import *  # noqa: F401,F403
+from .spectral_ns import __all__  # noqa: F401

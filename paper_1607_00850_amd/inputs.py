@@ -1,0 +1,220 @@
+"""Seeded synthetic velocity fields in the canonical spectral layout.
+
+This module is the only code shared by the CPU oracle's tests and the GPU path.
+It draws inputs and nothing else: no transform, curl, cross product, projection
+or time stepping lives here.  Every array it returns is a half-spectrum
+``uhat[3][kx][ky][kz]`` (complex128, kz in 0..N/2, kx and ky in FFT order), the
+layout of the spectral field of Sec. 3.3 on a single rank.
+
+Families (value ranges follow the Taylor-Green case of Sec. 4: velocities of
+order one, kinetic energy 1/8):
+
+* ``taylor_green``  -- the initial condition of Sec. 4, written out exactly as
+  its eight Fourier modes (no transform needed).
+* ``smooth_random`` -- "R1": a random solenoidal field with energy spectrum
+  shaped as |k|^4 exp(-2|k|^2/9) (peak near |k| = 3), band-limited to
+  |k_i| <= 16 so that the same seed gives the same physical field at every
+  N >= 49, scaled to E = 1/8.
+* ``rough_random``  -- "R2": random solenoidal field that fills every retained
+  mode with equal expected energy, scaled to E = 1/8 (stress case).
+* ``beltrami``      -- random helical field on one shell |k|^2 = K2.  Its
+  vorticity is parallel to it, so the nonlinear term vanishes (used for exact
+  decay checks).
+
+Randomness: numpy.random.default_rng(seed) (PCG64), drawn in an order that
+does not depend on N where stated.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "signed_index",
+    "taylor_green",
+    "taylor_green_physical",
+    "smooth_random",
+    "rough_random",
+    "beltrami",
+    "kinetic_energy",
+]
+
+
+def signed_index(N: int) -> np.ndarray:
+    """Wavenumber of FFT index j on an axis of length N (Eq. wavemesh): j for
+    j <= N/2, j - N above (so index N/2 carries +N/2)."""
+    j = np.arange(N)
+    return np.where(j <= N // 2, j, j - N)
+
+
+def _half_shape(N):
+    return (3, N, N, N // 2 + 1)
+
+
+def taylor_green(N: int) -> np.ndarray:
+    """Exact half-spectrum of u = sin x cos y cos z, v = -cos x sin y cos z,
+    w = 0 (Sec. 4) under the unnormalised forward transform of Eq. ffteq.
+
+    Expanding the trigonometric products gives 8 modes (+-1, +-1, +-1); the
+    u-coefficient of mode (sx, sy, sz) is N^3 * sx / (8i), the v-coefficient
+    N^3 * (-sy) / (8i).  Only sz = +1 is stored in the half-spectrum.
+    """
+    if N < 4 or N % 2:
+        raise ValueError("N must be even and >= 4")
+    uh = np.zeros(_half_shape(N), dtype=np.complex128)
+    n3 = float(N) ** 3
+    for sx in (-1, 1):
+        for sy in (-1, 1):
+            ix, iy = sx % N, sy % N
+            uh[0, ix, iy, 1] = n3 * sx / 8j
+            uh[1, ix, iy, 1] = n3 * (-sy) / 8j
+    return uh
+
+
+def taylor_green_physical(N: int) -> np.ndarray:
+    """The same field sampled on the mesh of Eq. realmesh, shape (3, N, N, N)."""
+    x = 2 * np.pi * np.arange(N) / N
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    return np.stack([
+        np.sin(X) * np.cos(Y) * np.cos(Z),
+        -np.cos(X) * np.sin(Y) * np.cos(Z),
+        np.zeros_like(X),
+    ])
+
+
+def kinetic_energy(uh: np.ndarray) -> float:
+    """E = <|u|^2>/2 from a half-spectrum (Parseval with the 1/N^3 of Eq.
+    ffteq): E = sum_half w |uhat|^2 / (2 N^6), w = 1 on the kz = 0 and kz = N/2
+    planes and 2 elsewhere.  Used only to scale generated fields."""
+    N = uh.shape[1]
+    w = np.full(uh.shape[-1], 2.0)
+    w[0] = 1.0
+    if N % 2 == 0:
+        w[-1] = 1.0
+    return float(np.sum(w * np.sum(np.abs(uh) ** 2, axis=(0, 1, 2))) / (2.0 * float(N) ** 6))
+
+
+def _plane_basis(k: np.ndarray):
+    """Two orthonormal vectors spanning the plane perpendicular to each row of
+    k (shape (..., 3), k != 0).  Geometry for sampling only."""
+    kf = k.astype(np.float64)
+    kn = np.linalg.norm(kf, axis=-1, keepdims=True)
+    khat = kf / kn
+    # reference direction: the coordinate axis least aligned with k
+    ref = np.zeros_like(kf)
+    ax = np.argmin(np.abs(khat), axis=-1)
+    np.put_along_axis(ref, ax[..., None], 1.0, axis=-1)
+    e1 = np.cross(ref, khat)
+    e1 /= np.linalg.norm(e1, axis=-1, keepdims=True)
+    e2 = np.cross(khat, e1)
+    return e1, e2
+
+
+def _place_band(N, kvec, amp, keep):
+    """Scatter band-limited complex vectors amp[m] (m over kvec rows) into a
+    half-spectrum of size N, making it Hermitian on kz = 0.  Rows whose
+    wavenumber is not representable/retained (``keep`` false) are dropped."""
+    uh = np.zeros(_half_shape(N), dtype=np.complex128)
+    kx, ky, kz = kvec[:, 0], kvec[:, 1], kvec[:, 2]
+    sel = keep & (kz >= 0)
+    # upper half (kz > 0): store directly
+    up = sel & (kz > 0)
+    uh[:, kx[up] % N, ky[up] % N, kz[up]] = amp[up].T
+    # kz = 0 plane: make u(-k) = conj(u(k)) by averaging the two draws
+    z0 = sel & (kz == 0)
+    plane = np.zeros((3, N, N), dtype=np.complex128)
+    plane[:, kx[z0] % N, ky[z0] % N] = amp[z0].T
+    neg = np.conj(plane[:, (-np.arange(N)) % N][:, :, (-np.arange(N)) % N])
+    uh[:, :, :, 0] = 0.5 * (plane + neg)
+    return uh
+
+
+def _band_vectors(kmax: int):
+    r = np.arange(-kmax, kmax + 1)
+    KX, KY, KZ = np.meshgrid(r, r, r, indexing="ij")
+    k = np.stack([KX.ravel(), KY.ravel(), KZ.ravel()], axis=-1)
+    return k
+
+
+def _retained(N, k, dealias):
+    """Which integer wavenumbers are stored and kept at size N: the 2/3 rule
+    (3|k_i| < N on every axis) or all but the Nyquist planes."""
+    a = np.abs(k)
+    if dealias == "two_thirds":
+        return np.all(3 * a < N, axis=-1)
+    if dealias == "none":
+        return np.all(a < N // 2, axis=-1)
+    raise ValueError(dealias)
+
+
+def smooth_random(N: int, seed: int, dealias: str = "two_thirds", band: int = 16) -> np.ndarray:
+    """R1: random solenoidal field, spectrum |k|^4 exp(-2|k|^2/9), band-limited
+    to |k_i| <= band, E = 1/8.  The draws cover the whole band cube in a fixed
+    order, so the field does not depend on N (beyond truncation)."""
+    rng = np.random.default_rng(seed)
+    k = _band_vectors(band)
+    a1 = rng.standard_normal(len(k)) + 1j * rng.standard_normal(len(k))
+    a2 = rng.standard_normal(len(k)) + 1j * rng.standard_normal(len(k))
+    nz = np.any(k != 0, axis=-1)
+    k2 = np.sum(k * k, axis=-1).astype(np.float64)
+    shape = np.where(nz, k2 * np.exp(-k2 / 9.0), 0.0)
+    amp = np.zeros((len(k), 3), dtype=np.complex128)
+    e1, e2 = _plane_basis(k[nz])
+    amp[nz] = (a1[nz, None] * e1 + a2[nz, None] * e2) * shape[nz, None]
+    uh = _place_band(N, k, amp, _retained(N, k, dealias) & nz)
+    E = kinetic_energy(uh)
+    return uh * np.sqrt(0.125 / E) if E > 0 else uh
+
+
+def rough_random(N: int, seed: int, dealias: str = "two_thirds") -> np.ndarray:
+    """R2: random solenoidal field on every retained mode (flat spectrum in
+    expectation), E = 1/8.  Drawn over the retained cube of this N."""
+    if dealias == "two_thirds":
+        kmax = (N - 1) // 3
+    else:
+        kmax = N // 2 - 1
+    rng = np.random.default_rng(seed)
+    r = np.arange(-kmax, kmax + 1)
+    rz = np.arange(0, kmax + 1)
+    KX, KY, KZ = np.meshgrid(r, r, rz, indexing="ij")
+    k = np.stack([KX.ravel(), KY.ravel(), KZ.ravel()], axis=-1)
+    n = len(k)
+    a1 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    a2 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    nz = np.any(k != 0, axis=-1)
+    amp = np.zeros((n, 3), dtype=np.complex128)
+    e1, e2 = _plane_basis(k[nz])
+    amp[nz] = a1[nz, None] * e1 + a2[nz, None] * e2
+    uh = _place_band(N, k, amp, nz)
+    E = kinetic_energy(uh)
+    return uh * np.sqrt(0.125 / E)
+
+
+def beltrami(N: int, K2: int, seed: int, sign: int = 1) -> np.ndarray:
+    """Random field on the shell |k|^2 = K2 built from helical vectors
+    h = (e1 + i*sign*e2)/sqrt(2), for which i k x h = sign*|k| h, so the
+    vorticity is sign*sqrt(K2) times the velocity and u x omega = 0.
+    Scaled to E = 1/8.  Requires the shell to survive the 2/3 rule."""
+    kmax = int(np.floor(np.sqrt(K2)))
+    k = _band_vectors(kmax)
+    on = np.sum(k * k, axis=-1) == K2
+    k = k[on]
+    if len(k) == 0:
+        raise ValueError("empty shell")
+    if not np.all(_retained(N, k, "two_thirds")):
+        raise ValueError("shell not retained at this N")
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(len(k)) + 1j * rng.standard_normal(len(k))
+    e1, e2 = _plane_basis(k)
+    # right-handed pair: e1 x e2 = k/|k|  (true by construction of _plane_basis)
+    h = (e1 + 1j * sign * e2) / np.sqrt(2.0)
+    amp = a[:, None] * h
+    # Hermitian pairing u(-k) = conj(u(k)) keeps the helicity sign; enforce it
+    # on the whole shell before placing so the kz=0 averaging is exact.
+    idx = {tuple(v): m for m, v in enumerate(k)}
+    paired = amp.copy()
+    for m, v in enumerate(k):
+        mm = idx[tuple(-v)]
+        paired[m] = 0.5 * (amp[m] + np.conj(amp[mm]))
+    uh = _place_band(N, k, paired, np.ones(len(k), bool))
+    E = kinetic_energy(uh)
+    return uh * np.sqrt(0.125 / E)
