@@ -1,0 +1,184 @@
+"""Benchmark: classical RK4 steps of the pseudo-spectral Navier-Stokes
+right-hand side (Eq. NSfinal) on one 1024^3 field in FP32, through libhot.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 1024] [--dtype f32]
+
+Prints ONE JSON line.  A "step" is one RK4 step (four right-hand sides: curl,
+6 inverse and 3 forward real 3D FFTs, cross product, 2/3 dealiasing,
+projection, viscous term, stage update) of one N^3 field; the W warm-up and
+K timed steps each run as one hot_run call (inputs resident in HBM).
+
+Extra fields:
+  roofline      dominant pass: algorithmic bytes per launch / mean launch
+                time (HIP events on the run stream) against 8 TB/s HBM;
+                traffic from the committed rocprofv3 counter summary when its
+                source hash matches the kernels built now, else null.
+  cpu_baseline  the CPU oracle timed on a bounded sample (RK4 steps at a
+                smaller N on one core), scaled to this workload's unit.
+"""
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NU = 1.0 / 1600.0  # Re = 1600 (Sec. 4)
+DT = 1e-3          # Sec. 4
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1607_00850_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_counters(kernel, workload):
+    """HBM traffic per launch from profiles/counters.json, if it was taken
+    with the kernels that are built now."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    rec = d.get(workload, {}).get(kernel)
+    if not rec or rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def device_field(N, dtype, seed=0):
+    """R1 (smooth random solenoidal field, E = 1/8) scattered on the GPU."""
+    import torch
+    from paper_1607_00850_amd import inputs
+
+    ix, iy, iz, vals = inputs.smooth_random_modes(N, seed)
+    cdt = torch.complex64 if dtype == "f32" else torch.complex128
+    x = torch.zeros((3, N, N, N // 2 + 1), dtype=cdt, device="cuda")
+    idx = [torch.from_numpy(a).long().cuda() for a in (ix, iy, iz)]
+    x[:, idx[0], idx[1], idx[2]] = torch.from_numpy(vals).to(cdt).cuda()
+    return x
+
+
+def cpu_baseline(N_work, seconds=12.0):
+    """Time the CPU oracle (one core) on RK4 steps at N = 128 and scale to
+    instances/s of an N_work^3 step by the FFT cost N^3 log2 N."""
+    import numpy as np
+
+    import oracle
+    from paper_1607_00850_amd import inputs
+
+    try:
+        os.sched_setaffinity(0, {min(os.sched_getaffinity(0))})
+    except (AttributeError, OSError):
+        pass
+    n = 128
+    uh = inputs.smooth_random(n, 0)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        uh = oracle.rk4_step(uh, NU, DT)
+        steps += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    el = time.perf_counter() - t0
+    pps = n**3 * steps / el
+    scale = (np.log2(N_work) / np.log2(n))
+    inst = pps / scale / float(N_work) ** 3
+    return {
+        "value": inst,
+        "unit": "instances/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} RK4 steps of the FP64 oracle at N={n} (R1 seed 0) in {el:.1f} s on 1 core = "
+                  f"{pps:.3g} point-steps/s; scaled to N={N_work} by log2(N) ({scale:.3f}x per point)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    a = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU slab decomposition is a design note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1607_00850_amd import binding
+
+    N, dtype = a.n, a.dtype
+    x = device_field(N, dtype)
+    y = torch.empty_like(x)
+    plan, wsb = binding.hot_plan(N, "rk4", dtype, "two_thirds", NU, DT)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    try:
+        binding.hot_run(plan, [x], [y], ws, a.warmup, stream)
+        torch.cuda.synchronize()
+        binding.hot_profile_enable(plan, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        binding.hot_run(plan, [x], [y], ws, a.steps, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = binding.hot_profile_read(plan)
+        binding.hot_profile_enable(plan, False)
+        pass_bytes = {k: binding.hot_pass_bytes(plan, 0, k) for k in prof}
+    finally:
+        binding.hot_destroy(plan)
+
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    inst_s = 1e3 / ms_step
+    dom = max(prof, key=lambda k: prof[k][0])
+    tot_ms, launches = prof[dom]
+    avg_s = tot_ms / launches / 1e3
+    achieved = pass_bytes[dom] / avg_s / 1e9
+    workload = f"rk4_step_{N}^3_{dtype}"
+    traffic = load_counters(dom, workload)
+    passes = {k: {"ms_per_launch": prof[k][0] / prof[k][1], "launches": prof[k][1],
+                  "GBps": pass_bytes[k] / (prof[k][0] / prof[k][1] / 1e3) / 1e9,
+                  "model_bytes_per_launch": pass_bytes[k]} for k in sorted(prof)}
+    step_bytes = sum(pass_bytes[k] * prof[k][1] for k in prof) / a.steps
+    line = {
+        "metric": "instances/sec",
+        "value": inst_s,
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (R1: seeded smooth random solenoidal field, E=1/8)",
+        "config": {"workload": workload, "N": N, "instances_per_launch": 1, "nu": NU, "dt": DT,
+                   "dealias": "two_thirds", "steps_per_call": a.steps},
+        "elements_per_sec": float(N) ** 3 * inst_s,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (ms_step / 1e3) / 1e9,
+                          "frac": step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "passes": passes,
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(N, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

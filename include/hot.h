@@ -1,0 +1,133 @@
+/*
+ * libhot -- one classical RK4 time step of the Fourier-Galerkin
+ * Navier-Stokes right-hand side on a triply periodic N^3 grid, on one
+ * MI355X (gfx950).
+ *
+ * The method (Mortensen, arXiv 1607.00850):
+ *   du_k/dt = (u x w)^_k - nu |k|^2 u_k - k (k . (u x w)^_k) / |k|^2
+ * (Eq. NSfinal, pressure eliminated by Eq. pressure, w = curl u), evaluated
+ * pseudo-spectrally with the transform pair of Eq. ffteq on the mesh of
+ * Eq. realmesh and the wavenumbers of Eq. wavemesh, dealiased with the 2/3
+ * rule, and advanced with classical fourth-order Runge-Kutta (Sec. 2).
+ *
+ * Layouts (all device memory, row-major, contiguous):
+ *   spectral  uhat[3][N][N][N/2+1]  complex (interleaved re, im), index
+ *             [c][kx][ky][kz]; kx, ky in FFT order (index j <-> k = j for
+ *             j <= N/2, j - N above), kz = 0..N/2.  This is the spectral
+ *             array of the slab transform (Sec. 3.3) on a single rank.
+ *   physical  u[3][N][N][N] real, index [c][x][y][z] at x_i = 2 pi i / N.
+ *   element type: double (HOT_F64) or float (HOT_F32).
+ *
+ * Ownership: the caller allocates inputs, outputs and the workspace (e.g.
+ * torch tensors); the library never allocates or frees device memory and
+ * never synchronises inside hot_run, which only enqueues kernels on the
+ * given stream.  All device pointers must be 256-byte aligned.
+ *
+ * Thread safety: a plan may be used from one host thread at a time.  Two
+ * hot_run calls that share a workspace must be ordered on one stream.
+ */
+#ifndef HOT_H
+#define HOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOT_ABI_VERSION 1
+
+/* Return codes. */
+#define HOT_OK 0
+#define HOT_E_INVALID (-1)     /* bad argument (null, odd N, nu < 0, dt <= 0, bad enum, ...) */
+#define HOT_E_UNSUPPORTED (-2) /* valid request this build does not implement (e.g. an N) */
+#define HOT_E_WORKSPACE (-3)   /* workspace pointer null or misaligned */
+#define HOT_E_HIP (-4)         /* a HIP call failed; hot_last_hip_error() has the code */
+
+/* Element type. */
+#define HOT_F64 0
+#define HOT_F32 1
+
+/* Dealiasing (Sec. 4 names the technique only as Tarang's; read as the
+ * 2/3 rule): TWO_THIRDS keeps mode k iff 3|k_i| < N on every axis.
+ * NONE keeps every mode except the Nyquist planes (|k_i| = N/2). */
+#define HOT_DEALIAS_TWO_THIRDS 0
+#define HOT_DEALIAS_NONE 1
+
+/* Operations.
+ *  R2C  physical u -> spectral uhat_k = sum_x u(x) e^{-i k.x}
+ *       (Eq. ffteq, forward, unnormalised; every mode kept, no dealiasing).
+ *  C2R  spectral -> physical u(x) = N^-3 sum_k uhat_k e^{i k.x} (Eq. ffteq,
+ *       inverse; the imaginary parts of the kz = 0 and N/2 coefficients
+ *       are ignored, as for any real inverse transform).
+ *  RHS  spectral uhat -> spectral du/dt of Eq. NSfinal.  The input is first
+ *       projected onto the retained modes (the Galerkin space of the
+ *       dealiased method); the output is zero outside them.
+ *  RK4  spectral uhat -> spectral uhat after nsteps classical RK4 steps of
+ *       size dt (Sec. 2), input projected as for RHS.  in == out allowed. */
+#define HOT_OP_R2C 0
+#define HOT_OP_C2R 1
+#define HOT_OP_RHS 2
+#define HOT_OP_RK4 3
+
+typedef struct hot_desc {
+  int32_t abi_version; /* HOT_ABI_VERSION */
+  int32_t batch;       /* number of instances, >= 1 */
+  const int32_t* n;    /* host array [batch]: points per axis of each instance */
+  double nu;           /* kinematic viscosity (>= 0); Sec. 4 uses Re = 1600 -> nu = 1/1600 */
+  double dt;           /* RK4 step (> 0, RK4 only); Sec. 4 uses 0.001 */
+  int32_t dtype;       /* HOT_F64 or HOT_F32 */
+  int32_t dealias;     /* HOT_DEALIAS_* (RHS and RK4) */
+  int32_t op;          /* HOT_OP_* */
+  int32_t flags;       /* reserved, must be 0 */
+} hot_desc;
+
+typedef struct hot_plan_s* hot_plan_t;
+
+/* Supported sizes: N in {8, 16, 32, 64, 128, 256, 512, 1024}. */
+
+/* Validate d, build a plan and report the workspace size in bytes.
+ * The plan copies d->n.  On error *out is set to NULL.
+ * Errors: HOT_E_INVALID, HOT_E_UNSUPPORTED. */
+int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes);
+
+/* Enqueue the planned operation on stream (a hipStream_t; NULL = default).
+ * in[i], out[i]: device pointers of instance i (layouts above; R2C reads
+ * physical and writes spectral, C2R the reverse, RHS/RK4 spectral both).
+ * workspace: device buffer of at least the planned size.  nsteps: RK4 steps
+ * (>= 0; ignored by other ops).  Asynchronous; inputs must stay valid until
+ * the stream reaches the end of the call.
+ * Errors: HOT_E_INVALID (null plan/pointer, nsteps < 0), HOT_E_WORKSPACE,
+ * HOT_E_HIP (launch failure; the plan keeps the HIP error code). */
+int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps, void* stream);
+
+/* Release the plan's host state (waits for its pending profiling events).
+ * NULL is accepted and ignored. */
+int hot_destroy(hot_plan_t p);
+
+/* Text for a return code (static storage). */
+const char* hot_error_string(int code);
+
+/* HIP error code recorded by the last failing call on this plan, 0 if none. */
+int hot_last_hip_error(hot_plan_t p);
+
+/* Per-pass timing.  When enabled, hot_run brackets every kernel launch with
+ * HIP events on the run stream.  hot_profile_read waits for those events,
+ * writes for each pass id (< max_passes) the summed milliseconds and the
+ * number of launches, then clears the record.  Returns the number of pass
+ * ids, or a negative error code. */
+int hot_profile_enable(hot_plan_t p, int enable);
+int hot_profile_read(hot_plan_t p, int32_t max_passes, double* ms, int64_t* launches);
+
+/* Name of pass id (static storage), and the algorithmic HBM bytes one launch
+ * of that pass moves for instance i of the plan (each retained input and
+ * output value read or written once; 0 if the pass is unused by the op). */
+const char* hot_pass_name(int32_t pass);
+int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOT_H */

@@ -1,0 +1,177 @@
+"""ctypes binding of libhot (include/hot.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libhot.so; this module converts
+Python values and torch tensors into the C ABI's plain pointers and sizes.
+Importing it fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from .build import LIB
+
+HOT_ABI_VERSION = 1
+HOT_OK = 0
+HOT_E_INVALID = -1
+HOT_E_UNSUPPORTED = -2
+HOT_E_WORKSPACE = -3
+HOT_E_HIP = -4
+
+HOT_F64, HOT_F32 = 0, 1
+HOT_DEALIAS_TWO_THIRDS, HOT_DEALIAS_NONE = 0, 1
+HOT_OP_R2C, HOT_OP_C2R, HOT_OP_RHS, HOT_OP_RK4 = 0, 1, 2, 3
+
+DTYPES = {"f64": HOT_F64, "f32": HOT_F32}
+DEALIAS = {"two_thirds": HOT_DEALIAS_TWO_THIRDS, "none": HOT_DEALIAS_NONE}
+OPS = {"r2c": HOT_OP_R2C, "c2r": HOT_OP_C2R, "rhs": HOT_OP_RHS, "rk4": HOT_OP_RK4}
+
+
+class HotDesc(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
+        ("n", ctypes.POINTER(ctypes.c_int32)),
+        ("nu", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("dtype", ctypes.c_int32),
+        ("dealias", ctypes.c_int32),
+        ("op", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class HotError(RuntimeError):
+    def __init__(self, code, where, hip=0):
+        self.code = code
+        self.hip = hip
+        msg = f"{where}: {_lib().hot_error_string(code).decode()} ({code})"
+        if hip:
+            msg += f", HIP error {hip}"
+        super().__init__(msg)
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} is missing: build it with `python -m paper_1607_00850_amd.build`")
+        lib = ctypes.CDLL(LIB)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        lib.hot_plan.argtypes = [ctypes.POINTER(HotDesc), ctypes.POINTER(vp), ctypes.POINTER(sz)]
+        lib.hot_plan.restype = ctypes.c_int
+        lib.hot_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32, vp]
+        lib.hot_run.restype = ctypes.c_int
+        lib.hot_destroy.argtypes = [vp]
+        lib.hot_destroy.restype = ctypes.c_int
+        lib.hot_error_string.argtypes = [ctypes.c_int]
+        lib.hot_error_string.restype = ctypes.c_char_p
+        lib.hot_last_hip_error.argtypes = [vp]
+        lib.hot_last_hip_error.restype = ctypes.c_int
+        lib.hot_profile_enable.argtypes = [vp, ctypes.c_int]
+        lib.hot_profile_enable.restype = ctypes.c_int
+        lib.hot_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        lib.hot_profile_read.restype = ctypes.c_int
+        lib.hot_pass_name.argtypes = [i32]
+        lib.hot_pass_name.restype = ctypes.c_char_p
+        lib.hot_pass_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
+        lib.hot_pass_bytes.restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library object."""
+    return _lib()
+
+
+def hot_plan(n, op, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0):
+    """Plan an operation; returns (handle, workspace_bytes).  n: int or list."""
+    ns = [int(n)] if isinstance(n, int) else [int(v) for v in n]
+    arr = (ctypes.c_int32 * len(ns))(*ns)
+    d = HotDesc(HOT_ABI_VERSION, len(ns), arr, float(nu), float(dt), DTYPES[dtype], DEALIAS[dealias], OPS[op], 0)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    rc = _lib().hot_plan(ctypes.byref(d), ctypes.byref(h), ctypes.byref(ws))
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_plan")
+    return h, ws.value
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def hot_run(plan, ins, outs, workspace, nsteps=0, stream=None):
+    """Enqueue the planned op.  ins/outs: sequences of device tensors (or raw
+    pointers), one per instance; workspace: device tensor or pointer;
+    stream: a torch.cuda.Stream, a raw hipStream_t, or None for torch's
+    current stream."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    elif not isinstance(stream, int):
+        stream = stream.cuda_stream
+    n = len(ins)
+    pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
+    pout = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
+    rc = _lib().hot_run(plan, pin, pout, _ptr(workspace), int(nsteps), stream)
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_run", _lib().hot_last_hip_error(plan))
+
+
+def hot_destroy(plan):
+    _lib().hot_destroy(plan)
+
+
+def hot_profile_enable(plan, enable=True):
+    rc = _lib().hot_profile_enable(plan, 1 if enable else 0)
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_profile_enable")
+
+
+def hot_profile_read(plan, max_passes=32):
+    """Returns {pass_name: (total_ms, launches)} for passes that ran."""
+    ms = (ctypes.c_double * max_passes)()
+    cnt = (ctypes.c_int64 * max_passes)()
+    n = _lib().hot_profile_read(plan, max_passes, ms, cnt)
+    if n < 0:
+        raise HotError(n, "hot_profile_read", _lib().hot_last_hip_error(plan))
+    out = {}
+    for i in range(min(n, max_passes)):
+        if cnt[i]:
+            out[_lib().hot_pass_name(i).decode()] = (ms[i], cnt[i])
+    return out
+
+
+def hot_pass_bytes(plan, instance, pass_name):
+    lib = _lib()
+    for i in range(64):
+        name = lib.hot_pass_name(i).decode()
+        if not name:
+            break
+        if name == pass_name:
+            b = ctypes.c_double()
+            rc = lib.hot_pass_bytes(plan, instance, i, ctypes.byref(b))
+            if rc != HOT_OK:
+                raise HotError(rc, "hot_pass_bytes")
+            return b.value
+    raise KeyError(pass_name)
+
+
+def pass_names():
+    lib = _lib()
+    names = []
+    for i in range(64):
+        s = lib.hot_pass_name(i).decode()
+        if not s:
+            break
+        names.append(s)
+    return names

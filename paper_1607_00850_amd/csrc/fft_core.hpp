@@ -1,0 +1,316 @@
+// Device FFT core for gfx950: complex type, compile-time roots of unity,
+// in-register small DFTs and a Stockham line engine that exchanges through LDS.
+//
+// A line of length N is held by Tl = N/R threads, R complex values each.
+// Thread j always holds positions j + s*Tl (s = 0..R-1) on entry and on exit,
+// in natural order, so a pass loads and stores lines with the same pattern.
+// Stage k of radix r (span Ns = product of earlier radices) runs N/r virtual
+// butterflies; real thread j runs jj = j + m*Tl for m < R/r.  Butterfly jj
+// reads positions jj + q*N/r, scales by w^((jj mod Ns) q / (Ns r)), does an
+// r-point DFT and writes positions (jj/Ns)*Ns*r + (jj mod Ns) + q*Ns
+// (the self-sorting Stockham order), so no bit reversal is needed.
+//
+// Transform sign: DIR = -1 is the forward transform exp(-i k.x) of Eq. ffteq,
+// DIR = +1 the inverse (unnormalised; callers apply 1/N^3 once).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace hot {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+// multiply by i
+template <typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
+
+// ---------------------------------------------------------------------------
+// compile-time roots of unity
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Taylor series on |x| <= pi/4 (terms decay below 1e-20 after n = 12).
+constexpr double ct_sin(double x) {
+  double x2 = x * x, t = x, s = x;
+  for (int n = 1; n <= 12; ++n) {
+    t = -t * x2 / double((2 * n) * (2 * n + 1));
+    s += t;
+  }
+  return s;
+}
+constexpr double ct_cos(double x) {
+  double x2 = x * x, t = 1.0, s = 1.0;
+  for (int n = 1; n <= 12; ++n) {
+    t = -t * x2 / double((2 * n - 1) * (2 * n));
+    s += t;
+  }
+  return s;
+}
+
+struct cs_pair {
+  double c, s;
+};
+
+// cos and sin of 2*pi*m/n; the quadrant and the half-quadrant fold are done in
+// integers so the series only ever sees an angle in [0, pi/4].
+constexpr cs_pair unit_root(long m, long n) {
+  m %= n;
+  if (m < 0) m += n;
+  const long q = (4 * m) / n;   // quadrant
+  const long r = 4 * m - q * n; // remainder, angle within quadrant = (pi/2) r/n
+  double c0 = 0, s0 = 0;
+  if (2 * r <= n) {
+    const double a = (kPi / 2) * double(r) / double(n);
+    c0 = ct_cos(a);
+    s0 = ct_sin(a);
+  } else {
+    const double a = (kPi / 2) * double(n - r) / double(n);
+    c0 = ct_sin(a);
+    s0 = ct_cos(a);
+  }
+  switch (q) {
+    case 0: return {c0, s0};
+    case 1: return {-s0, c0};
+    case 2: return {-c0, -s0};
+    default: return {s0, -c0};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// compile-time loops
+// ---------------------------------------------------------------------------
+template <int I, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < E) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(f);
+  }
+}
+
+// v * exp(DIR * 2 pi i E / R) with E, R compile-time; trivial angles are
+// special-cased so no multiply by an exact 0 or 1 is emitted.
+template <int E, int R, int DIR, typename T>
+__device__ __forceinline__ cx<T> rot(cx<T> v) {
+  constexpr int e = ((E % R) + R) % R;
+  if constexpr (e == 0) {
+    return v;
+  } else if constexpr (2 * e == R) {
+    return {-v.x, -v.y};
+  } else if constexpr (4 * e == R) {  // exp(DIR i pi/2) = DIR i
+    return DIR > 0 ? cx<T>{-v.y, v.x} : cx<T>{v.y, -v.x};
+  } else if constexpr (4 * e == 3 * R) {  // exp(DIR i 3pi/2) = -DIR i
+    return DIR > 0 ? cx<T>{v.y, -v.x} : cx<T>{-v.y, v.x};
+  } else {
+    constexpr cs_pair w = unit_root(e, R);
+    constexpr T c = T(w.c);
+    constexpr T s = T(DIR * w.s);
+    return {v.x * c - v.y * s, v.x * s + v.y * c};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// in-register DFT of compile-time size R (natural order in and out)
+// ---------------------------------------------------------------------------
+template <int R, int DIR, typename T>
+struct Dft;
+
+template <int DIR, typename T>
+struct Dft<1, DIR, T> {
+  __device__ __forceinline__ static void run(cx<T>*) {}
+};
+
+template <int DIR, typename T>
+struct Dft<2, DIR, T> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    const cx<T> t = a[0];
+    a[0] = t + a[1];
+    a[1] = t - a[1];
+  }
+};
+
+template <int DIR, typename T>
+struct Dft<3, DIR, T> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    // X0 = a0+a1+a2; X1,2 = a0 - (a1+a2)/2 +- DIR i (sqrt3/2)(a1-a2)
+    constexpr T h = T(0.86602540378443864676372317075293618);
+    const cx<T> s = a[1] + a[2];
+    const cx<T> d = a[1] - a[2];
+    const cx<T> m = {a[0].x - T(0.5) * s.x, a[0].y - T(0.5) * s.y};
+    const cx<T> id = DIR > 0 ? cx<T>{-d.y * h, d.x * h} : cx<T>{d.y * h, -d.x * h};
+    a[0] = a[0] + s;
+    a[1] = m + id;
+    a[2] = m - id;
+  }
+};
+
+template <int DIR, typename T>
+struct Dft<4, DIR, T> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    const cx<T> s0 = a[0] + a[2], d0 = a[0] - a[2];
+    const cx<T> s1 = a[1] + a[3], d1 = a[1] - a[3];
+    const cx<T> jd1 = rot<1, 4, DIR>(d1);
+    a[0] = s0 + s1;
+    a[2] = s0 - s1;
+    a[1] = d0 + jd1;
+    a[3] = d0 - jd1;
+  }
+};
+
+template <int R>
+constexpr int first_factor() {
+  if constexpr (R % 4 == 0 && R != 4) return 4;
+  else if constexpr (R % 2 == 0) return 2;
+  else if constexpr (R % 3 == 0) return 3;
+  else return R;
+}
+
+// Composite R = P*Q: n = Q n1 + n2, k = k1 + P k2,
+// X[k1 + P k2] = sum_n2 W_R^(n2 k1) W_Q^(n2 k2) sum_n1 x[Q n1 + n2] W_P^(n1 k1).
+template <int R, int DIR, typename T>
+struct Dft {
+  static constexpr int P = first_factor<R>();
+  static constexpr int Q = R / P;
+  static_assert(P > 1 && Q > 1, "unsupported DFT size");
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    cx<T> y[R];
+    static_for<0, Q>([&](auto n2) {
+      cx<T> b[P];
+      static_for<0, P>([&](auto n1) { b[n1] = a[Q * n1 + n2]; });
+      Dft<P, DIR, T>::run(b);
+      static_for<0, P>([&](auto k1) { y[n2 * P + k1] = rot<n2 * k1, R, DIR>(b[k1]); });
+    });
+    static_for<0, P>([&](auto k1) {
+      cx<T> c[Q];
+      static_for<0, Q>([&](auto n2) { c[n2] = y[n2 * P + k1]; });
+      Dft<Q, DIR, T>::run(c);
+      static_for<0, Q>([&](auto k2) { a[k1 + P * k2] = c[k2]; });
+    });
+  }
+};
+
+// ---------------------------------------------------------------------------
+// twiddle tables: w[m] = exp(-2 pi i m / NT), FP64 values rounded once
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+struct TwTable {
+  cx<T> w[NT];
+};
+
+template <typename T, int NT>
+constexpr TwTable<T, NT> make_twiddles() {
+  TwTable<T, NT> t{};
+  for (int m = 0; m < NT; ++m) {
+    const cs_pair p = unit_root(m, NT);
+    t.w[m].x = T(p.c);
+    t.w[m].y = T(-p.s);
+  }
+  return t;
+}
+
+// Table size for a line length N: 1024 serves every power of two up to 1024,
+// 1728 = 2^6 3^3 every 2^a 3^b (a <= 6, b <= 3).  A length-N twiddle
+// w_N^e is entry e * (tw_size(N) / N).
+template <int N>
+constexpr int tw_size() {
+  static_assert(1024 % N == 0 || 1728 % N == 0, "no twiddle table for this length");
+  return (1024 % N == 0) ? 1024 : 1728;
+}
+
+// Stage twiddle for DIR: forward multiplies by w, inverse by conj(w).
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> twmul(cx<T> v, cx<T> w) {
+  return DIR < 0 ? cmul(v, w) : cmulc(v, w);
+}
+
+// ---------------------------------------------------------------------------
+// Stockham engine
+// ---------------------------------------------------------------------------
+// Lds must provide put(pos, v), get(pos) for this thread's line and sync().
+template <typename T, int DIR, int N, int R, int Ns, int... Rs>
+struct Stages;
+
+template <typename T, int DIR, int N, int R, int Ns>
+struct Stages<T, DIR, N, R, Ns> {
+  template <class L>
+  __device__ __forceinline__ static void run(cx<T>*, int, L&, const cx<T>*) {
+    static_assert(Ns == N, "radices must multiply to N");
+  }
+};
+
+template <typename T, int DIR, int N, int R, int Ns, int r, int... Rs>
+struct Stages<T, DIR, N, R, Ns, r, Rs...> {
+  static constexpr int Tl = N / R;
+  static constexpr int nb = R / r;
+  static constexpr bool last = (Ns * r == N);
+  static_assert(R % r == 0, "each radix must divide the per-thread count");
+
+  template <class L>
+  __device__ __forceinline__ static void run(cx<T>* v, int j, L& lds, const cx<T>* tw) {
+    static_for<0, nb>([&](auto m) {
+      const int jj = j + m * Tl;
+      cx<T> b[r];
+      static_for<0, r>([&](auto q) { b[q] = v[m + q * nb]; });
+      if constexpr (Ns > 1) {
+        const int step = (jj % Ns) * (tw_size<N>() / (Ns * r));
+        static_for<1, r>([&](auto q) { b[q] = twmul<DIR>(b[q], tw[step * q]); });
+      }
+      Dft<r, DIR, T>::run(b);
+      if constexpr (!last) {
+        const int ob = (jj / Ns) * (Ns * r) + (jj % Ns);
+        static_for<0, r>([&](auto q) { lds.put(ob + q * Ns, b[q]); });
+      } else {
+        static_for<0, r>([&](auto q) { v[m + q * nb] = b[q]; });
+      }
+    });
+    if constexpr (!last) {
+      lds.sync();
+      static_for<0, R>([&](auto s) { v[s] = lds.get(j + s * Tl); });
+      lds.sync();
+      Stages<T, DIR, N, R, Ns * r, Rs...>::run(v, j, lds, tw);
+    }
+  }
+};
+
+// A line-length plan: N points, R per thread, radix sequence.
+template <int N_, int R_, int... Rs>
+struct LinePlan {
+  static constexpr int N = N_;
+  static constexpr int R = R_;
+  static constexpr int Tl = N_ / R_;
+  template <typename T, int DIR, class L>
+  __device__ __forceinline__ static void fft(cx<T>* v, int j, L& lds, const cx<T>* tw) {
+    Stages<T, DIR, N_, R_, 1, Rs...>::run(v, j, lds, tw);
+  }
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace hot

@@ -33,6 +33,7 @@ __all__ = [
     "taylor_green",
     "taylor_green_physical",
     "smooth_random",
+    "smooth_random_modes",
     "rough_random",
     "beltrami",
     "kinetic_energy",
@@ -146,23 +147,42 @@ def _retained(N, k, dealias):
     raise ValueError(dealias)
 
 
-def smooth_random(N: int, seed: int, dealias: str = "two_thirds", band: int = 16) -> np.ndarray:
-    """R1: random solenoidal field, spectrum |k|^4 exp(-2|k|^2/9), band-limited
-    to |k_i| <= band, E = 1/8.  The draws cover the whole band cube in a fixed
-    order, so the field does not depend on N (beyond truncation)."""
+def smooth_random_modes(N: int, seed: int, dealias: str = "two_thirds", band: int = 16):
+    """R1 in sparse form: FFT indices (ix, iy, iz) and values (3, n) of the
+    nonzero half-spectrum entries.  Spectrum |k|^4 exp(-2|k|^2/9), random
+    solenoidal directions, band-limited to |k_i| <= band, E = 1/8.  The draws
+    cover the whole band cube in a fixed order, so the field does not depend
+    on N (beyond truncation by the retained set)."""
     rng = np.random.default_rng(seed)
     k = _band_vectors(band)
-    a1 = rng.standard_normal(len(k)) + 1j * rng.standard_normal(len(k))
-    a2 = rng.standard_normal(len(k)) + 1j * rng.standard_normal(len(k))
+    n = len(k)
+    a1 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    a2 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     nz = np.any(k != 0, axis=-1)
     k2 = np.sum(k * k, axis=-1).astype(np.float64)
     shape = np.where(nz, k2 * np.exp(-k2 / 9.0), 0.0)
-    amp = np.zeros((len(k), 3), dtype=np.complex128)
+    amp = np.zeros((n, 3), dtype=np.complex128)
     e1, e2 = _plane_basis(k[nz])
     amp[nz] = (a1[nz, None] * e1 + a2[nz, None] * e2) * shape[nz, None]
-    uh = _place_band(N, k, amp, _retained(N, k, dealias) & nz)
-    E = kinetic_energy(uh)
-    return uh * np.sqrt(0.125 / E) if E > 0 else uh
+    # the cube is ordered lexicographically and symmetric, so -k sits at n-1-m;
+    # on kz = 0 take u(k) = (a(k) + conj a(-k))/2 so that u(-k) = conj u(k)
+    z0 = k[:, 2] == 0
+    amp[z0] = 0.5 * (amp[z0] + np.conj(amp[::-1][z0]))
+    keep = _retained(N, k, dealias) & nz & (k[:, 2] >= 0)
+    kk, vals = k[keep], amp[keep].T.copy()
+    w = np.where(kk[:, 2] == 0, 1.0, 2.0)
+    E = float(np.sum(w * np.sum(np.abs(vals) ** 2, axis=0)) / (2.0 * float(N) ** 6))
+    if E > 0:
+        vals *= np.sqrt(0.125 / E)
+    return kk[:, 0] % N, kk[:, 1] % N, kk[:, 2], vals
+
+
+def smooth_random(N: int, seed: int, dealias: str = "two_thirds", band: int = 16) -> np.ndarray:
+    """R1 as a dense half-spectrum (see smooth_random_modes)."""
+    ix, iy, iz, vals = smooth_random_modes(N, seed, dealias, band)
+    uh = np.zeros(_half_shape(N), dtype=np.complex128)
+    uh[:, ix, iy, iz] = vals
+    return uh
 
 
 def rough_random(N: int, seed: int, dealias: str = "two_thirds") -> np.ndarray:

@@ -1,0 +1,76 @@
+"""Test helpers: run one libhot operation on the GPU through the C ABI.
+
+Only marshalling lives here: numpy arrays go to device tensors, the C ABI is
+called, results come back to numpy.
+"""
+import numpy as np
+
+from paper_1607_00850_amd import binding
+
+CDT = {"f64": "complex128", "f32": "complex64"}
+RDT = {"f64": "float64", "f32": "float32"}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_dev(x, dtype):
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(x.astype(CDT[dtype] if np.iscomplexobj(x) else RDT[dtype])))
+    return t.to("cuda")
+
+
+def empty_spectral(N, dtype):
+    torch = _torch()
+    return torch.empty((3, N, N, N // 2 + 1), dtype=getattr(torch, CDT[dtype]), device="cuda")
+
+
+def empty_physical(N, dtype):
+    torch = _torch()
+    return torch.empty((3, N, N, N), dtype=getattr(torch, RDT[dtype]), device="cuda")
+
+
+def workspace(nbytes):
+    torch = _torch()
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def run(op, arrays, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0, nsteps=0, inplace=False):
+    """arrays: list of numpy inputs (one per instance).  Returns numpy outputs."""
+    torch = _torch()
+    ns = [a.shape[1] for a in arrays]
+    h, wsb = binding.hot_plan(ns, op, dtype, dealias, nu, dt)
+    try:
+        ins = [to_dev(a, dtype) for a in arrays]
+        if inplace:
+            outs = ins
+        elif op == "c2r":
+            outs = [empty_physical(N, dtype) for N in ns]
+        else:
+            outs = [empty_spectral(N, dtype) for N in ns]
+        ws = workspace(wsb)
+        binding.hot_run(h, ins, outs, ws, nsteps)
+        torch.cuda.synchronize()
+        return [o.cpu().numpy() for o in outs]
+    finally:
+        binding.hot_destroy(h)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) or np.iscomplexobj(b) else np.float64)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a))
+
+
+def fp32_tol(N, C=10.0):
+    """Tolerance for the FP32 path: C * eps32 * log2(N^3)."""
+    return C * float(np.finfo(np.float32).eps) * np.log2(float(N) ** 3)
+
+
+def round32(x):
+    """The FP32-rounded input, upcast back to FP64 (what the FP32 path sees)."""
+    return x.astype(np.complex64).astype(np.complex128) if np.iscomplexobj(x) else x.astype(np.float32).astype(np.float64)

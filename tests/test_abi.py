@@ -1,0 +1,137 @@
+"""The C-ABI library loads, exports every symbol include/hot.h declares, and
+validates its arguments on the host (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1607_00850_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "hot.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hot_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("hot_plan", "hot_run", "hot_destroy"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.library()
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+        assert ctypes.cast(getattr(lib, s), ctypes.c_void_p).value
+
+
+def test_header_compiles_as_c():
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "t.c")
+        open(src, "w").write('#include "hot.h"\nint main(void){hot_desc d; (void)d; return 0;}\n')
+        r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), "-c", src,
+                            "-o", os.path.join(d, "t.o")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def _expect(code, **kw):
+    args = dict(n=64, op="rk4", dtype="f64", dealias="two_thirds", nu=0.01, dt=0.001)
+    args.update(kw)
+    with pytest.raises(binding.HotError) as e:
+        binding.hot_plan(**args)
+    assert e.value.code == code
+
+
+def test_plan_rejects_bad_arguments():
+    _expect(binding.HOT_E_INVALID, n=63)         # odd
+    _expect(binding.HOT_E_INVALID, n=6)          # below 8
+    _expect(binding.HOT_E_INVALID, nu=-1.0)
+    _expect(binding.HOT_E_INVALID, nu=float("nan"))
+    _expect(binding.HOT_E_INVALID, dt=0.0)
+    _expect(binding.HOT_E_INVALID, dt=-1e-3)
+    _expect(binding.HOT_E_UNSUPPORTED, n=2048)   # even, but no kernels for it
+    _expect(binding.HOT_E_UNSUPPORTED, n=[64, 100])
+
+
+def test_plan_rejects_bad_descriptor_fields():
+    lib = binding.library()
+    n = (ctypes.c_int32 * 1)(64)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    good = dict(abi_version=1, batch=1, n=n, nu=0.0, dt=1e-3, dtype=0, dealias=0, op=3, flags=0)
+    for field, bad in [("abi_version", 2), ("batch", 0), ("dtype", 7), ("dealias", 5), ("op", 9), ("flags", 1)]:
+        kw = dict(good)
+        kw[field] = bad
+        d = binding.HotDesc(**kw)
+        assert lib.hot_plan(ctypes.byref(d), ctypes.byref(h), ctypes.byref(ws)) == binding.HOT_E_INVALID
+        assert not h.value
+    assert lib.hot_plan(None, ctypes.byref(h), ctypes.byref(ws)) == binding.HOT_E_INVALID
+
+
+def test_run_rejects_bad_pointers_without_touching_the_gpu():
+    h, wsb = binding.hot_plan(16, "rhs", "f64", nu=0.01)
+    lib = binding.library()
+    try:
+        arr = (ctypes.c_void_p * 1)(256 * 1000)
+        nul = (ctypes.c_void_p * 1)(None)
+        assert lib.hot_run(h, arr, arr, None, 0, None) == binding.HOT_E_WORKSPACE
+        assert lib.hot_run(h, arr, arr, ctypes.c_void_p(256 * 7 + 3), 0, None) == binding.HOT_E_WORKSPACE
+        assert lib.hot_run(h, nul, arr, ctypes.c_void_p(256 * 9), 0, None) == binding.HOT_E_INVALID
+        mis = (ctypes.c_void_p * 1)(256 * 1000 + 8)
+        assert lib.hot_run(h, mis, arr, ctypes.c_void_p(256 * 9), 0, None) == binding.HOT_E_INVALID
+        assert lib.hot_run(h, arr, arr, ctypes.c_void_p(256 * 9), -1, None) == binding.HOT_E_INVALID
+        assert lib.hot_run(None, arr, arr, ctypes.c_void_p(256 * 9), 0, None) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    assert lib.hot_destroy(None) == 0
+
+
+def _align(v):
+    return (v + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("dtype,elem", [("f64", 16), ("f32", 8)])
+@pytest.mark.parametrize("N", [8, 32, 64, 1024])
+def test_workspace_size_formula(N, dtype, elem):
+    if N not in (8, 16, 32, 64, 128, 256, 512, 1024):
+        pytest.skip("size not built")
+    K = (N - 1) // 3
+    M, Mz = 2 * K + 1, K + 1
+    C, D1, D2 = M * M * Mz, N * M * Mz, N * N * Mz
+    h, ws = binding.hot_plan(N, "rk4", dtype, nu=0.01, dt=1e-3)
+    binding.hot_destroy(h)
+    assert ws == 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem)
+    h, ws = binding.hot_plan(N, "r2c", dtype)
+    binding.hot_destroy(h)
+    assert ws == 2 * _align(3 * N * N * (N // 2 + 1) * elem)
+
+
+def test_pass_byte_model_rk4_1024_f32():
+    h, _ = binding.hot_plan(1024, "rk4", "f32", nu=1 / 1600, dt=1e-3)
+    try:
+        K = 341
+        M, Mz, N = 683, 342, 1024
+        C, D1, D2 = M * M * Mz, N * M * Mz, N * N * Mz
+        assert binding.hot_pass_bytes(h, 0, "y_inv") == 8.0 * (6 * D1 + 6 * D2)
+        assert binding.hot_pass_bytes(h, 0, "z_cross") == 8.0 * (9 * D2)
+        assert binding.hot_pass_bytes(h, 0, "x_inv_curl") == 8.0 * (3 * C + 6 * D1)
+        assert K == (N - 1) // 3
+    finally:
+        binding.hot_destroy(h)
+
+
+def test_error_strings():
+    lib = binding.library()
+    for code in (0, -1, -2, -3, -4, -99):
+        assert lib.hot_error_string(code)
