@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (a known-size kernel "
+                         "for scaling HBM byte counters)")
     a = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -119,6 +122,14 @@ def main():
     import torch
 
     from paper_1607_00850_amd import binding
+
+    if a.calibrate_copy > 0:
+        nbytes = a.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     N, dtype = a.n, a.dtype
     x = device_field(N, dtype)

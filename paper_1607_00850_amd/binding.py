@@ -2,7 +2,8 @@
 
 Every computation runs in the HIP kernels of libhot.so; this module converts
 Python values and torch tensors into the C ABI's plain pointers and sizes.
-Importing it fails loudly if the library has not been built.
+The first call fails loudly if the library has not been built.  The
+environment variable HOT_LIBRARY may name another build of the same library.
 """
 from __future__ import annotations
 
@@ -57,9 +58,10 @@ _LIB = None
 def _lib():
     global _LIB
     if _LIB is None:
-        if not os.path.exists(LIB):
-            raise ImportError(f"{LIB} is missing: build it with `python -m paper_1607_00850_amd.build`")
-        lib = ctypes.CDLL(LIB)
+        path = os.environ.get("HOT_LIBRARY", LIB)
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_1607_00850_amd.build`")
+        lib = ctypes.CDLL(path)
         vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
         lib.hot_plan.argtypes = [ctypes.POINTER(HotDesc), ctypes.POINTER(vp), ctypes.POINTER(sz)]
         lib.hot_plan.restype = ctypes.c_int

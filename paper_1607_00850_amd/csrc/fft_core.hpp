@@ -246,6 +246,18 @@ __device__ __forceinline__ cx<T> twmul(cx<T> v, cx<T> w) {
   return DIR < 0 ? cmul(v, w) : cmulc(v, w);
 }
 
+// Twiddle sources: operator()(e) returns w_N^e = exp(-2 pi i e / N), e in [0, N).
+template <typename T, int N>
+struct TwGlobal {  // the constant table of size tw_size<N>()
+  const cx<T>* tab;
+  __device__ __forceinline__ cx<T> operator()(int e) const { return tab[e * (tw_size<N>() / N)]; }
+};
+template <typename T>
+struct TwLds {  // a per-block copy of the N entries in LDS
+  const cx<T>* tab;
+  __device__ __forceinline__ cx<T> operator()(int e) const { return tab[e]; }
+};
+
 // ---------------------------------------------------------------------------
 // Stockham engine
 // ---------------------------------------------------------------------------
@@ -255,8 +267,8 @@ struct Stages;
 
 template <typename T, int DIR, int N, int R, int Ns>
 struct Stages<T, DIR, N, R, Ns> {
-  template <class L>
-  __device__ __forceinline__ static void run(cx<T>*, int, L&, const cx<T>*) {
+  template <class L, class TW>
+  __device__ __forceinline__ static void run(cx<T>*, int, L&, const TW&) {
     static_assert(Ns == N, "radices must multiply to N");
   }
 };
@@ -268,15 +280,15 @@ struct Stages<T, DIR, N, R, Ns, r, Rs...> {
   static constexpr bool last = (Ns * r == N);
   static_assert(R % r == 0, "each radix must divide the per-thread count");
 
-  template <class L>
-  __device__ __forceinline__ static void run(cx<T>* v, int j, L& lds, const cx<T>* tw) {
+  template <class L, class TW>
+  __device__ __forceinline__ static void run(cx<T>* v, int j, L& lds, const TW& tw) {
     static_for<0, nb>([&](auto m) {
       const int jj = j + m * Tl;
       cx<T> b[r];
       static_for<0, r>([&](auto q) { b[q] = v[m + q * nb]; });
       if constexpr (Ns > 1) {
-        const int step = (jj % Ns) * (tw_size<N>() / (Ns * r));
-        static_for<1, r>([&](auto q) { b[q] = twmul<DIR>(b[q], tw[step * q]); });
+        const int step = (jj % Ns) * (N / (Ns * r));
+        static_for<1, r>([&](auto q) { b[q] = twmul<DIR>(b[q], tw(step * q)); });
       }
       Dft<r, DIR, T>::run(b);
       if constexpr (!last) {
@@ -295,14 +307,31 @@ struct Stages<T, DIR, N, R, Ns, r, Rs...> {
   }
 };
 
+template <int V>
+constexpr int ilog2() {
+  int k = 0;
+  while ((1 << (k + 1)) <= V) ++k;
+  return k;
+}
+
+template <int First, int... Rest>
+struct FirstOf {
+  static constexpr int value = First;
+};
+
 // A line-length plan: N points, R per thread, radix sequence.
 template <int N_, int R_, int... Rs>
 struct LinePlan {
   static constexpr int N = N_;
   static constexpr int R = R_;
   static constexpr int Tl = N_ / R_;
-  template <typename T, int DIR, class L>
-  __device__ __forceinline__ static void fft(cx<T>* v, int j, L& lds, const cx<T>* tw) {
+  // First-stage writes go to positions r1 apart (r1 = first radix); padding
+  // one slot every 2^SH positions of a contiguous line spreads them over the
+  // LDS banks.
+  static constexpr int SH = ilog2<FirstOf<Rs...>::value>();
+  static constexpr int line_slots = N_ + (N_ >> SH) + 1;
+  template <typename T, int DIR, class L, class TW>
+  __device__ __forceinline__ static void fft(cx<T>* v, int j, L& lds, const TW& tw) {
     Stages<T, DIR, N_, R_, 1, Rs...>::run(v, j, lds, tw);
   }
 };

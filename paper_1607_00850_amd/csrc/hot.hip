@@ -32,14 +32,29 @@ template <> struct LP<256> { using P = LinePlan<256, 16, 16, 16>; };
 template <> struct LP<512> { using P = LinePlan<512, 16, 16, 16, 2>; };
 template <> struct LP<1024> { using P = LinePlan<1024, 16, 16, 16, 4>; };
 
-// Columns per block of a strided pass: keep the block's LDS tile at 64 KB
-// and its size at most 1024 threads.
+// line plans of the z passes (one line per Tl lanes; see ZShape)
+template <int N>
+struct LPz {
+  using P = typename LP<N>::P;
+};
+#ifndef HOT_Z1024_R
+#define HOT_Z1024_R 16
+#endif
+#if HOT_Z1024_R == 8
+template <> struct LPz<1024> { using P = LinePlan<1024, 8, 8, 8, 8, 2>; };
+#endif
+
+// Columns per block of a strided pass: at least one 128-byte segment per row
+// (16 FP32 / 8 FP64 complex values), more while the LDS tile stays within
+// 64 KB; never above 1024 threads or a 128 KB tile.
 template <typename T, int N>
 constexpr int cols_per_block() {
   constexpr int tl = LP<N>::P::Tl;
+  constexpr int seg = int(128 / sizeof(cx<T>));
   int w = int(65536 / (N * sizeof(cx<T>)));
   if (w > 64) w = 64;
-  while (w * tl > 1024) w /= 2;
+  if (w < seg) w = seg;
+  while (w > 1 && (w * tl > 1024 || (long)N * w * (long)sizeof(cx<T>) > 131072)) w /= 2;
   return w;
 }
 
@@ -77,7 +92,7 @@ static inline unsigned grid_1d(long work, int block) {
 // Kernel launchers for one (element type, N).  Every function enqueues one
 // kernel on the stream and returns hipGetLastError().
 struct Ops {
-  hipError_t (*strided)(hipStream_t, int dir, bool inc, bool outc, const void* in, void* out, int Q, long ncols,
+  hipError_t (*strided)(hipStream_t, int dir, bool inc, bool outc, const void* in, void* out, long ncols, long Qp,
                         long ld_in, long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, int ncomp,
                         const Geo&);
   hipError_t (*x_inv_curl)(hipStream_t, const void* U, long csU, void* A, long csA, const Geo&);
@@ -97,51 +112,54 @@ struct Impl {
   static constexpr int Tl = P::Tl;
 
   template <int DIR, bool IC, bool OC>
-  static void go(hipStream_t s, const void* in, void* out, int Q, long ncols, long ld_in, long ld_out, long bs_in,
+  static void go(hipStream_t s, const void* in, void* out, long ncols, long Qp, long ld_in, long ld_out, long bs_in,
                  long bs_out, long cs_in, long cs_out, int ncomp, const Geo& g) {
     dim3 grid((unsigned)((ncols + W - 1) / W), (unsigned)ncomp);
-    hipLaunchKernelGGL((k_strided<T, P, DIR, W, IC, OC>), grid, dim3(W * Tl), 0, s, (const cx<T>*)in, (cx<T>*)out, Q,
-                       ncols, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, g);
+    hipLaunchKernelGGL((k_strided<T, P, DIR, W, IC, OC>), grid, dim3(W * Tl), 0, s, (const cx<T>*)in, (cx<T>*)out,
+                       ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, g);
   }
-  static hipError_t strided(hipStream_t s, int dir, bool inc, bool outc, const void* in, void* out, int Q,
-                            long ncols, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in, long cs_out,
+  static hipError_t strided(hipStream_t s, int dir, bool inc, bool outc, const void* in, void* out, long ncols,
+                            long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in, long cs_out,
                             int ncomp, const Geo& g) {
+#define HOT_GO(D, I, O) go<D, I, O>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, g)
     if (dir > 0) {
-      if (inc && !outc) go<+1, true, false>(s, in, out, Q, ncols, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, g);
-      else if (!inc && !outc) go<+1, false, false>(s, in, out, Q, ncols, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, g);
+      if (inc && !outc) HOT_GO(+1, true, false);
+      else if (!inc && !outc) HOT_GO(+1, false, false);
       else return hipErrorInvalidValue;
     } else {
-      if (!inc && outc) go<-1, false, true>(s, in, out, Q, ncols, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, g);
-      else if (!inc && !outc) go<-1, false, false>(s, in, out, Q, ncols, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, g);
+      if (!inc && outc) HOT_GO(-1, false, true);
+      else if (!inc && !outc) HOT_GO(-1, false, false);
       else return hipErrorInvalidValue;
     }
+#undef HOT_GO
     return hipGetLastError();
   }
   static hipError_t x_inv_curl(hipStream_t s, const void* U, long csU, void* A, long csA, const Geo& g) {
-    const long Q = (long)g.M * g.Mz;
+    const long Q = (long)g.M * g.Mzp;
     const int ntiles = (int)((Q + W - 1) / W);
     const unsigned nblk = 8u * 6u * (unsigned)((ntiles + 7) / 8);
     hipLaunchKernelGGL((k_x_inv_curl<T, P, W>), dim3(nblk), dim3(W * Tl), 0, s, (const cx<T>*)U, csU, (cx<T>*)A, csA,
                        ntiles, g);
     return hipGetLastError();
   }
-  static constexpr int lines_per_block() { return 256 / Tl; }
+  using PZ = typename LPz<N>::P;
+  static constexpr int lines_per_block() { return ZShape<PZ>::LPB; }
   static hipError_t z_cross(hipStream_t s, void* A, long csA, long nlines, const Geo& g) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const double n3 = double(N) * N * N;
     const T scale = T(1.0 / (n3 * n3));
-    hipLaunchKernelGGL((k_z_cross<T, P>), dim3(nblk), dim3(256), 0, s, (cx<T>*)A, csA, nlines, g, scale);
+    hipLaunchKernelGGL((k_z_cross<T, PZ>), dim3(nblk), dim3(256), 0, s, (cx<T>*)A, csA, nlines, g, scale);
     return hipGetLastError();
   }
   static hipError_t z_c2r(hipStream_t s, const void* in, void* out, long nlines, const Geo& g) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const T scale = T(1.0 / (double(N) * N * N));
-    hipLaunchKernelGGL((k_z_c2r<T, P>), dim3(nblk), dim3(256), 0, s, (const cx<T>*)in, (T*)out, nlines, g, scale);
+    hipLaunchKernelGGL((k_z_c2r<T, PZ>), dim3(nblk), dim3(256), 0, s, (const cx<T>*)in, (T*)out, nlines, g, scale);
     return hipGetLastError();
   }
   static hipError_t z_r2c(hipStream_t s, const void* in, void* out, long nlines, const Geo& g) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
-    hipLaunchKernelGGL((k_z_r2c<T, P>), dim3(nblk), dim3(256), 0, s, (const T*)in, (cx<T>*)out, nlines, g);
+    hipLaunchKernelGGL((k_z_r2c<T, PZ>), dim3(nblk), dim3(256), 0, s, (const T*)in, (cx<T>*)out, nlines, g);
     return hipGetLastError();
   }
   static hipError_t rk_stage(hipStream_t s, const void* Nh, void* U0, void* U1, void* Acc, long C, const Geo& g,
@@ -186,13 +204,17 @@ static bool ops_for(int N, Ops* o) {
 struct Inst {
   Geo g;      // retained geometry for the op
   Ops ops;
-  long C;     // compact modes per component, M*M*Mz
-  long D1;    // per component: N*M*Mz  (after the x pass)
-  long D2;    // per component: N*N*Mz  (after the y pass)
+  long C;     // compact slots per component, M*M*Mzp
+  long D1;    // per component after the x pass: N*M*Mzp
+  long D2;    // per component after the y pass: N*N*Mzp
+  double lC, lD1, lD2;  // the same counts of live values (Mz instead of Mzp)
   size_t ws;  // workspace bytes
 };
 
-static Geo make_geo(int N, int mode) {
+// mode: 0 = 2/3 rule, 1 = all but Nyquist, 2 = every mode (plain transforms).
+// elem: bytes per complex value; the z pitch is padded to whole 128-byte rows
+// once rows are long enough for the padding to be cheap.
+static Geo make_geo(int N, int mode, int elem) {
   Geo g{};
   g.N = N;
   if (mode == 0) {  // 2/3 rule: |k| <= K = floor((N-1)/3)
@@ -210,6 +232,8 @@ static Geo make_geo(int N, int mode) {
     g.Mz = N / 2 + 1;
   }
   g.M = g.lo + g.hi;
+  const int seg = 128 / elem;
+  g.Mzp = (mode != 2 && g.Mz >= 4 * seg) ? (g.Mz + seg - 1) / seg * seg : g.Mz;
   return g;
 }
 
@@ -285,10 +309,13 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
       delete p;
       return HOT_E_UNSUPPORTED;
     }
-    I.g = make_geo(N, plain ? 2 : d->dealias);
-    I.C = (long)I.g.M * I.g.M * I.g.Mz;
-    I.D1 = (long)N * I.g.M * I.g.Mz;
-    I.D2 = (long)N * N * I.g.Mz;
+    I.g = make_geo(N, plain ? 2 : d->dealias, (int)p->elem);
+    I.C = (long)I.g.M * I.g.M * I.g.Mzp;
+    I.D1 = (long)N * I.g.M * I.g.Mzp;
+    I.D2 = (long)N * N * I.g.Mzp;
+    I.lC = (double)I.g.M * I.g.M * I.g.Mz;
+    I.lD1 = (double)N * I.g.M * I.g.Mz;
+    I.lD2 = (double)N * N * I.g.Mz;
     if (plain) {
       I.ws = 2 * align_up(3 * (size_t)I.D2 * p->elem);
     } else {
@@ -355,7 +382,7 @@ const char* hot_pass_name(int32_t pass) {
 int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) {
   if (!p || !bytes || instance < 0 || instance >= (int)p->inst.size()) return HOT_E_INVALID;
   const Inst& I = p->inst[instance];
-  const double e = (double)p->elem, C = (double)I.C, D1 = (double)I.D1, D2 = (double)I.D2;
+  const double e = (double)p->elem, C = I.lC, D1 = I.lD1, D2 = I.lD2;
   const double N = I.g.N, canon = 3.0 * N * N * (N / 2 + 1);
   double b = 0;
   const bool plain = p->op == HOT_OP_R2C || p->op == HOT_OP_C2R;
@@ -422,22 +449,22 @@ struct Runner {
 // One evaluation of the right-hand side from compact state `src` into Nh.
 void rhs_passes(Runner& r, const Inst& I, const char* src, char* A1, char* A2, char* Nh) {
   const Geo& g = I.g;
-  const long N = g.N, M = g.M, Mz = g.Mz;
+  const long N = g.N, M = g.M, P = g.Mzp;
   const Ops& o = I.ops;
   r.pass(PASS_X_INV_CURL, [&] { return o.x_inv_curl(r.s, src, I.C, A1, I.D1, g); });
   // y inverse: 6 components, batch over x, rows ky (compact) -> y (all N)
   r.pass(PASS_Y_INV, [&] {
-    return o.strided(r.s, +1, true, false, A1, A2, (int)Mz, N * Mz, Mz, Mz, M * Mz, N * Mz, I.D1, I.D2, 6, g);
+    return o.strided(r.s, +1, true, false, A1, A2, N * P, P, P, P, M * P, N * P, I.D1, I.D2, 6, g);
   });
   r.pass(PASS_Z_CROSS, [&] { return o.z_cross(r.s, A2, I.D2, N * N, g); });
   // y forward: 3 components, y (all N) -> ky (compact)
   r.pass(PASS_Y_FWD, [&] {
-    return o.strided(r.s, -1, false, true, A2, A1, (int)Mz, N * Mz, Mz, Mz, N * Mz, M * Mz, I.D2, I.D1, 3, g);
+    return o.strided(r.s, -1, false, true, A2, A1, N * P, P, P, P, N * P, M * P, I.D2, I.D1, 3, g);
   });
   // x forward: rows x (all N) -> kx (compact), columns (ky, kz)
   r.pass(PASS_X_FWD, [&] {
-    const long Q = M * Mz;
-    return o.strided(r.s, -1, false, true, A1, Nh, (int)Q, Q, Q, Q, 0, 0, I.D1, I.C, 3, g);
+    const long Q = M * P;
+    return o.strided(r.s, -1, false, true, A1, Nh, Q, Q, Q, Q, 0, 0, I.D1, I.C, 3, g);
   });
 }
 
@@ -466,19 +493,19 @@ extern "C" int hot_run(hot_plan_t p, void* const* in, void* const* out, void* wo
       if (p->op == HOT_OP_R2C) {
         r.pass(PASS_Z_R2C, [&] { return o.z_r2c(r.s, in[i], Z1, 3 * N * N, g); });
         r.pass(PASS_Y_FWD, [&] {
-          return o.strided(r.s, -1, false, false, Z1, Z2, (int)Nh, N * Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, g);
+          return o.strided(r.s, -1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, g);
         });
         r.pass(PASS_X_FWD, [&] {
           const long Q = N * Nh;
-          return o.strided(r.s, -1, false, false, Z2, out[i], (int)Q, Q, Q, Q, 0, 0, D2, D2, 3, g);
+          return o.strided(r.s, -1, false, false, Z2, out[i], Q, Q, Q, Q, 0, 0, D2, D2, 3, g);
         });
       } else {
         r.pass(PASS_X_INV, [&] {
           const long Q = N * Nh;
-          return o.strided(r.s, +1, false, false, in[i], Z1, (int)Q, Q, Q, Q, 0, 0, D2, D2, 3, g);
+          return o.strided(r.s, +1, false, false, in[i], Z1, Q, Q, Q, Q, 0, 0, D2, D2, 3, g);
         });
         r.pass(PASS_Y_INV, [&] {
-          return o.strided(r.s, +1, false, false, Z1, Z2, (int)Nh, N * Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, g);
+          return o.strided(r.s, +1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, g);
         });
         r.pass(PASS_Z_C2R, [&] { return o.z_c2r(r.s, Z2, out[i], 3 * N * N, g); });
       }

@@ -4,18 +4,19 @@
 // Spectral data inside the library is "compact": only the retained modes are
 // stored.  On the x and y axes the retained FFT positions are [0, lo) and
 // [N-hi, N) (M = lo + hi rows; row i holds position i for i < lo and
-// i + N - M above); on the half (z) axis they are kz in [0, Mz).  With the 2/3
-// rule lo = K+1, hi = K, Mz = K+1 where K = floor((N-1)/3); with every mode
-// kept (plain transforms) lo = N/2+1, hi = N/2-1, Mz = N/2+1, which is the
-// canonical half-spectrum layout itself.
+// i + N - M above); on the half (z) axis they are kz in [0, Mz), stored with a
+// row pitch Mzp >= Mz that keeps rows 128-byte aligned (the padding slots are
+// never read or written).  With the 2/3 rule lo = K+1, hi = K, Mz = K+1 where
+// K = floor((N-1)/3); with every mode kept (plain transforms) lo = N/2+1,
+// hi = N/2-1, Mz = Mzp = N/2+1: the canonical half-spectrum layout itself.
 //
 // Per right-hand side (Eq. ffteq order: inverse x, y, z; forward z, y, x):
-//   P1  x inverse, curl fused on load        U[3][M][M*Mz]  -> A1[6][N][M*Mz]
-//   P2  y inverse                            A1[6][N][M][Mz] -> A2[6][N][N][Mz]
-//   P3  z C2R, u x omega, z R2C              A2[6][N*N][Mz] -> A2[0..3) (in place)
-//   P4  y forward                            A2[3][N][N][Mz] -> A1[3][N][M][Mz]
-//   P5  x forward                            A1[3][N][M*Mz] -> Nh[3][M][M*Mz]
-//   E   mask/projection/viscous/RK4 stage    Nh, U0, U1, Acc (compact, elementwise)
+//   P1  x inverse, curl fused on load        U[3][M][M*Mzp]  -> A1[6][N][M*Mzp]
+//   P2  y inverse                            A1[6][N][M][Mzp] -> A2[6][N][N][Mzp]
+//   P3  z C2R, u x omega, z R2C              A2[6][N*N][Mzp] -> A2[0..3) (in place)
+//   P4  y forward                            A2[3][N][N][Mzp] -> A1[3][N][M][Mzp]
+//   P5  x forward                            A1[3][N][M*Mzp] -> Nh[3][M][M*Mzp]
+//   E   projection/viscous/RK4 stage         Nh, U0, U1, Acc (compact, elementwise)
 #pragma once
 
 #include "fft_core.hpp"
@@ -25,7 +26,8 @@ namespace hot {
 struct Geo {
   int N;
   int lo, hi, M;  // x and y axes
-  int Mz;         // z (half) axis
+  int Mz;         // retained z (half-axis) modes
+  int Mzp;        // z pitch of compact arrays (>= Mz)
 };
 
 __device__ __forceinline__ bool kept(int p, const Geo& g) { return p < g.lo || p >= g.N - g.hi; }
@@ -42,7 +44,7 @@ extern __device__ const TwTable<float, 1728> g_tw1728_f;
 extern __device__ const TwTable<double, 1728> g_tw1728_d;
 
 template <typename T, int N>
-__device__ __forceinline__ const cx<T>* twiddles() {
+__device__ __forceinline__ const cx<T>* twiddle_table() {
   if constexpr (std::is_same<T, float>::value) {
     if constexpr (tw_size<N>() == 1024) return g_tw1024_f.w;
     else return g_tw1728_f.w;
@@ -52,63 +54,84 @@ __device__ __forceinline__ const cx<T>* twiddles() {
   }
 }
 
-// LDS view for a tile of W interleaved columns (strided passes).
-template <typename T, int W>
+// LDS view for a tile of W interleaved columns (strided passes).  Positions
+// are XOR-swizzled in their low two bits by bits 4-5 so that the first-stage
+// writes of neighbouring lanes (r positions apart) fall in different banks.
+template <typename T, int N, int W>
 struct LdsCols {
   cx<T>* base;
   int c;
-  __device__ __forceinline__ void put(int pos, cx<T> v) { base[pos * W + c] = v; }
-  __device__ __forceinline__ cx<T> get(int pos) const { return base[pos * W + c]; }
+  static constexpr bool kSwz = (N % 64 == 0);
+  __device__ __forceinline__ static int sw(int p) { return kSwz ? (p ^ ((p >> 4) & 3)) : p; }
+  __device__ __forceinline__ void put(int pos, cx<T> v) { base[sw(pos) * W + c] = v; }
+  __device__ __forceinline__ cx<T> get(int pos) const { return base[sw(pos) * W + c]; }
   __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
-// LDS view for one contiguous line owned by part of one wave.
-template <typename T>
+// LDS view for one contiguous line owned by a lane group (inside one wave,
+// or whole waves of the block when BLOCK); one padding slot every 2^SH
+// positions.
+template <typename T, int SH, bool BLOCK>
 struct LdsLine {
   cx<T>* base;
-  __device__ __forceinline__ void put(int pos, cx<T> v) { base[pos] = v; }
-  __device__ __forceinline__ cx<T> get(int pos) const { return base[pos]; }
-  __device__ __forceinline__ void sync() { wave_sync(); }
+  __device__ __forceinline__ static int sw(int p) { return p + (p >> SH); }
+  __device__ __forceinline__ void put(int pos, cx<T> v) { base[sw(pos)] = v; }
+  __device__ __forceinline__ cx<T> get(int pos) const { return base[sw(pos)]; }
+  __device__ __forceinline__ void sync() {
+    if constexpr (BLOCK) __syncthreads();
+    else wave_sync();
+  }
+};
+
+// z kernels run 256-thread blocks; a line is held by Tl lanes that either sit
+// inside one wave (Tl divides 64) or span whole waves (block barriers).
+template <class Plan>
+struct ZShape {
+  static constexpr int Tl = Plan::Tl;
+  static_assert((Tl <= 64 && 64 % Tl == 0) || (Tl % 64 == 0 && 256 % Tl == 0), "unsupported z line shape");
+  static constexpr bool kBlock = Tl > 64;
+  static constexpr int LPB = 256 / Tl;  // lines per block
 };
 
 // ---------------------------------------------------------------------------
 // Strided axis pass: columns are contiguous, lines run along rows.
-// The array is a batch of [rows][Q] blocks; global column g = b*Q + q.
+// The array is a batch of [rows][Qp] blocks (global column gc = b*Qp + q);
+// a column is live iff (q mod Mzp) < Mz (the rest is row padding).
 // IN_C / OUT_C: rows are compact (retained positions only) or all N.
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int DIR, int W, bool IN_C, bool OUT_C>
-__global__ __launch_bounds__(W* Plan::Tl) void k_strided(
-    const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int Q, long ncols, long ld_in, long ld_out,
-    long bs_in, long bs_out, long cs_in, long cs_out, Geo g) {
+__global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                         long ncols, long Qp, long ld_in, long ld_out, long bs_in,
+                                                         long bs_out, long cs_in, long cs_out, Geo g) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   __shared__ cx<T> sm[N * W];
   const int tid = threadIdx.x;
   const int c = tid % W, j = tid / W;
   const long gc = (long)blockIdx.x * W + c;
-  const bool valid = gc < ncols;
-  const long b = valid ? gc / Q : 0;
-  const long q = valid ? gc - b * Q : 0;
-  const cx<T>* src = in + blockIdx.y * cs_in + b * bs_in + q;
-  cx<T>* dst = out + blockIdx.y * cs_out + b * bs_out + q;
+  const long b = gc / Qp;
+  const long q = gc - b * Qp;
+  const bool valid = gc < ncols && (int)(q % g.Mzp) < g.Mz;
+  const long ib = valid ? blockIdx.y * cs_in + b * bs_in + q : 0;
+  const long ob = valid ? blockIdx.y * cs_out + b * bs_out + q : 0;
   cx<T> v[R];
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
     cx<T> x = {T(0), T(0)};
     if (IN_C) {
-      if (valid && kept(p, g)) x = src[(long)crow(p, g) * ld_in];
+      if (valid && kept(p, g)) x = in[ib + (long)crow(p, g) * ld_in];
     } else {
-      if (valid) x = src[(long)p * ld_in];
+      if (valid) x = in[ib + (long)p * ld_in];
     }
     v[s] = x;
   });
-  LdsCols<T, W> lds{sm, c};
-  Plan::template fft<T, DIR>(v, j, lds, twiddles<T, N>());
+  LdsCols<T, N, W> lds{sm, c};
+  Plan::template fft<T, DIR>(v, j, lds, TwGlobal<T, N>{twiddle_table<T, N>()});
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
     if (OUT_C) {
-      if (valid && kept(p, g)) dst[(long)crow(p, g) * ld_out] = v[s];
+      if (valid && kept(p, g)) out[ob + (long)crow(p, g) * ld_out] = v[s];
     } else {
-      if (valid) dst[(long)p * ld_out] = v[s];
+      if (valid) out[ob + (long)p * ld_out] = v[s];
     }
   });
 }
@@ -116,9 +139,9 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(
 // ---------------------------------------------------------------------------
 // P1: inverse transform along x of the velocity and of the vorticity
 // omega_hat = i k x u_hat (curl fused into the load).  Input compact state
-// U[3][M rows (kx)][Q = M*Mz cols (ky,kz)], output A[6][N rows (x)][Q].
+// U[3][M rows (kx)][Q = M*Mzp cols (ky,kz)], output A[6][N rows (x)][Q].
 // Block b: the 6 output components of one tile go to blocks with equal
-// b mod 8 so that their shared input rows meet in the same L2.
+// b mod 8 (one XCD) so that their shared input rows meet in one L2.
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int W>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restrict__ U, long csU,
@@ -133,16 +156,17 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
   if (tile >= ntiles) return;  // whole block leaves together
   const int tid = threadIdx.x;
   const int c = tid % W, j = tid / W;
-  const long Q = (long)g.M * g.Mz;
+  const long Q = (long)g.M * g.Mzp;
   const long q = (long)tile * W + c;
-  const bool valid = q < Q;
-  const int iy = valid ? (int)(q / g.Mz) : 0;
-  const int kz = valid ? (int)(q - (long)iy * g.Mz) : 0;
-  const T ky = T(kwave(cpos(iy, g), N));
+  const int iy = (int)(q / g.Mzp);
+  const int kz = (int)(q - (long)iy * g.Mzp);
+  const bool valid = q < Q && kz < g.Mz;
+  const T ky = T(kwave(cpos(valid ? iy : 0, g), N));
   const T kzf = T(kz);
-  const cx<T>* u0 = U + q;
-  const cx<T>* u1 = U + csU + q;
-  const cx<T>* u2 = U + 2 * csU + q;
+  const long qq = valid ? q : 0;
+  const cx<T>* u0 = U + qq;
+  const cx<T>* u1 = U + csU + qq;
+  const cx<T>* u2 = U + 2 * csU + qq;
   cx<T> v[R];
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
@@ -161,8 +185,8 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
     }
     v[s] = x;
   });
-  LdsCols<T, W> lds{sm, c};
-  Plan::template fft<T, +1>(v, j, lds, twiddles<T, N>());
+  LdsCols<T, N, W> lds{sm, c};
+  Plan::template fft<T, +1>(v, j, lds, TwGlobal<T, N>{twiddle_table<T, N>()});
   if (valid) {
     cx<T>* dst = A + o * csA + q;
     static_for<0, R>([&](auto s) { dst[(long)(j + s * Tl) * Q] = v[s]; });
@@ -170,76 +194,105 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
 }
 
 // ---------------------------------------------------------------------------
-// z-axis line helpers.  A thread group of Tl = N/R lanes (inside one wave)
-// owns one line; the line's LDS region holds N complex values.
+// z-axis lines.  A group of Tl = N/R lanes owns one line (see ZShape).
 // ---------------------------------------------------------------------------
 
-// Hermitian completion of a half-spectrum line pair (a, b) into
-// Z_p = a_p + i b_p on the full circle, as the complex input of one inverse
-// FFT that returns a in its real part and b in its imaginary part.  As in a
-// real inverse transform, the imaginary parts of the kz = 0 and kz = N/2
-// coefficients are dropped.
-template <typename T, int N>
-__device__ __forceinline__ cx<T> completed_pair(const cx<T>* a, const cx<T>* b, int p, int Mz) {
-  if (p < Mz && 2 * p <= N) {
-    cx<T> x = a[p], y = b[p];
-    if (p == 0 || 2 * p == N) {
-      x.y = T(0);
-      y.y = T(0);
-    }
-    return {x.x - y.y, x.y + y.x};
-  }
-  const int m = N - p;
-  if (2 * p > N && m < Mz) {
-    const cx<T> x = a[m], y = b[m];
-    return {x.x + y.y, y.x - x.y};  // conj(x) + i conj(y)
-  }
-  return {T(0), T(0)};
+// Number of compact z coefficients a lane loads (upper bound over modes).
+template <class Plan>
+constexpr int z_loads() {
+  return (Plan::N / 2 + 1 + Plan::Tl - 1) / Plan::Tl;
 }
 
+// Lay out Z_p = a_p + i b_p on the full circle in the line's LDS region from
+// the half-spectrum pair (a, b) held as lane j's coefficients k = j + t*Tl:
+// Z_k = a_k + i b_k and Z_{N-k} = conj(a_k) + i conj(b_k).  As in a real
+// inverse transform, the imaginary parts of the kz = 0 and kz = N/2
+// coefficients are dropped.  Positions no coefficient reaches read as zero in
+// read_completed().
+template <typename T, class Plan, class L>
+__device__ __forceinline__ void put_completed(L& lds, const cx<T> (&la)[z_loads<Plan>()],
+                                              const cx<T> (&lb)[z_loads<Plan>()], int j, int Mz) {
+  constexpr int N = Plan::N, Tl = Plan::Tl;
+  static_for<0, z_loads<Plan>()>([&](auto t) {
+    const int k = j + t * Tl;
+    if (k < Mz) {
+      cx<T> x = la[t], y = lb[t];
+      if (k == 0 || 2 * k == N) {
+        x.y = T(0);
+        y.y = T(0);
+      }
+      lds.put(k, cx<T>{x.x - y.y, x.y + y.x});
+      if (k > 0 && 2 * k < N) lds.put(N - k, cx<T>{x.x + y.y, y.x - x.y});
+    }
+  });
+}
+
+template <typename T, class Plan, class L>
+__device__ __forceinline__ void read_completed(const L& lds, cx<T>* v, int j, int Mz) {
+  constexpr int N = Plan::N, Tl = Plan::Tl;
+  static_for<0, Plan::R>([&](auto s) {
+    const int p = j + s * Tl;
+    const bool live = (p < Mz) || (N - p < Mz);
+    v[s] = live ? lds.get(p) : cx<T>{T(0), T(0)};
+  });
+}
+
+// Coalesced load of a compact z line: lane j takes k = j + t*Tl (k < Mz).
+template <typename T, class Plan>
+__device__ __forceinline__ void load_line(cx<T> (&la)[z_loads<Plan>()], const cx<T>* __restrict__ a, int j, int Mz,
+                                          bool valid) {
+  static_for<0, z_loads<Plan>()>([&](auto t) {
+    const int k = j + t * Plan::Tl;
+    la[t] = (valid && k < Mz) ? a[k] : cx<T>{T(0), T(0)};
+  });
+}
+
+// Copy the N twiddles w_N^e of this line length into LDS (once per block).
 template <typename T, int N>
-__device__ __forceinline__ cx<T> completed_one(const cx<T>* a, int p, int Mz) {
-  if (p < Mz && 2 * p <= N) {
-    cx<T> x = a[p];
-    if (p == 0 || 2 * p == N) x.y = T(0);
-    return x;
-  }
-  const int m = N - p;
-  if (2 * p > N && m < Mz) return conj(a[m]);
-  return {T(0), T(0)};
+__device__ __forceinline__ void stage_twiddles(cx<T>* tws) {
+  const cx<T>* tab = twiddle_table<T, N>();
+  for (int e = threadIdx.x; e < N; e += blockDim.x) tws[e] = tab[e * (tw_size<N>() / N)];
 }
 
 // ---------------------------------------------------------------------------
 // P3: per z-line, inverse real transforms of u and omega (three complex FFTs,
-// two real lines each), the cross product c = u x omega (component formula
-// of Sec. 3.4) scaled by 1/N^6 (the 1/N^3 of Eq. ffteq for each factor), and
-// the forward real transform of c (c0 + i c1 in one FFT, c2 in another).
-// In place: reads components 0..5 of the line, writes 0..2.
+// two real lines each), the cross product c = u x omega (component formula of
+// Sec. 3.4) scaled by 1/N^6 (the 1/N^3 of Eq. ffteq for each factor), and the
+// forward real transform of c (c0 + i c1 in one FFT, c2 in another).
+// In place: reads components 0..5 of the line, writes 0..2.  The loads of the
+// next component pair are issued before the current pair's FFT.
 // ---------------------------------------------------------------------------
 template <typename T, class Plan>
-__global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA, long nlines, Geo g,
-                                                 T scale) {
-  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
-  static_assert(64 % Tl == 0, "a z line must sit inside one wave");
-  constexpr int LPB = 256 / Tl;  // lines per block
-  __shared__ cx<T> sm[LPB * N];
+__global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA, long nlines, Geo g, T scale) {
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, KL = z_loads<Plan>();
+  constexpr int LPB = ZShape<Plan>::LPB;
+  constexpr int LS = Plan::line_slots;
+  __shared__ cx<T> sm[LPB * LS];
+  __shared__ cx<T> tws[N];
+  stage_twiddles<T, N>(tws);
+  __syncthreads();
   const int tid = threadIdx.x;
   const int li = tid / Tl, j = tid % Tl;
   const long line = (long)blockIdx.x * LPB + li;
   const bool valid = line < nlines;
   const int Mz = g.Mz;
-  LdsLine<T> lds{sm + li * N};
-  const cx<T>* tw = twiddles<T, N>();
-  const long base = valid ? line * Mz : 0;
+  LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
+  const TwLds<T> tw{tws};
+  const long base = valid ? line * g.Mzp : 0;
 
+  cx<T> la[KL], lb[KL];
+  load_line<T, Plan>(la, A + base, j, Mz, valid);
+  load_line<T, Plan>(lb, A + csA + base, j, Mz, valid);
   cx<T> ph[3][R];
   static_for<0, 3>([&](auto pr) {
-    const cx<T>* a = A + (2 * pr) * csA + base;
-    const cx<T>* b = A + (2 * pr + 1) * csA + base;
-    static_for<0, R>([&](auto s) {
-      const int p = j + s * Tl;
-      ph[pr][s] = valid ? completed_pair<T, N>(a, b, p, Mz) : cx<T>{T(0), T(0)};
-    });
+    put_completed<T, Plan>(lds, la, lb, j, Mz);
+    lds.sync();
+    read_completed<T, Plan>(lds, ph[pr], j, Mz);
+    lds.sync();
+    if constexpr (pr < 2) {
+      load_line<T, Plan>(la, A + (2 * pr + 2) * csA + base, j, Mz, valid);
+      load_line<T, Plan>(lb, A + (2 * pr + 3) * csA + base, j, Mz, valid);
+    }
     Plan::template fft<T, +1>(ph[pr], j, lds, tw);
   });
   // u = (ph0.x, ph0.y, ph1.x), omega = (ph1.y, ph2.x, ph2.y)
@@ -278,23 +331,29 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
 // 1/N^3 of the inverse transform of Eq. ffteq (scale).
 // ---------------------------------------------------------------------------
 template <typename T, class Plan>
-__global__ __launch_bounds__(256) void k_z_c2r(const cx<T>* __restrict__ in, T* __restrict__ out,
-                                               long nlines, Geo g, T scale) {
-  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
-  static_assert(64 % Tl == 0, "a z line must sit inside one wave");
-  constexpr int LPB = 256 / Tl;
-  __shared__ cx<T> sm[LPB * N];
+__global__ __launch_bounds__(256) void k_z_c2r(const cx<T>* __restrict__ in, T* __restrict__ out, long nlines,
+                                               Geo g, T scale) {
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, KL = z_loads<Plan>();
+  constexpr int LPB = ZShape<Plan>::LPB;
+  constexpr int LS = Plan::line_slots;
+  __shared__ cx<T> sm[LPB * LS];
+  __shared__ cx<T> tws[N];
+  stage_twiddles<T, N>(tws);
+  __syncthreads();
   const int tid = threadIdx.x;
   const int li = tid / Tl, j = tid % Tl;
   const long line = (long)blockIdx.x * LPB + li;
   const bool valid = line < nlines;
-  LdsLine<T> lds{sm + li * N};
-  const cx<T>* a = in + (valid ? line * g.Mz : 0);
+  LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
+  cx<T> la[KL], lb[KL];
+  load_line<T, Plan>(la, in + (valid ? line * g.Mzp : 0), j, g.Mz, valid);
+  static_for<0, KL>([&](auto t) { lb[t] = {T(0), T(0)}; });
   cx<T> v[R];
-  static_for<0, R>([&](auto s) {
-    v[s] = valid ? completed_one<T, N>(a, j + s * Tl, g.Mz) : cx<T>{T(0), T(0)};
-  });
-  Plan::template fft<T, +1>(v, j, lds, twiddles<T, N>());
+  put_completed<T, Plan>(lds, la, lb, j, g.Mz);
+  lds.sync();
+  read_completed<T, Plan>(lds, v, j, g.Mz);
+  lds.sync();
+  Plan::template fft<T, +1>(v, j, lds, TwLds<T>{tws});
   if (valid) {
     T* o = out + line * N;
     static_for<0, R>([&](auto s) { o[j + s * Tl] = v[s].x * scale; });
@@ -305,20 +364,23 @@ template <typename T, class Plan>
 __global__ __launch_bounds__(256) void k_z_r2c(const T* __restrict__ in, cx<T>* __restrict__ out, long nlines,
                                                Geo g) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
-  static_assert(64 % Tl == 0, "a z line must sit inside one wave");
-  constexpr int LPB = 256 / Tl;
-  __shared__ cx<T> sm[LPB * N];
+  constexpr int LPB = ZShape<Plan>::LPB;
+  constexpr int LS = Plan::line_slots;
+  __shared__ cx<T> sm[LPB * LS];
+  __shared__ cx<T> tws[N];
+  stage_twiddles<T, N>(tws);
+  __syncthreads();
   const int tid = threadIdx.x;
   const int li = tid / Tl, j = tid % Tl;
   const long line = (long)blockIdx.x * LPB + li;
   const bool valid = line < nlines;
-  LdsLine<T> lds{sm + li * N};
+  LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
   const T* a = in + (valid ? line * N : 0);
   cx<T> v[R];
   static_for<0, R>([&](auto s) { v[s] = {valid ? a[j + s * Tl] : T(0), T(0)}; });
-  Plan::template fft<T, -1>(v, j, lds, twiddles<T, N>());
+  Plan::template fft<T, -1>(v, j, lds, TwLds<T>{tws});
   if (valid) {
-    cx<T>* o = out + line * g.Mz;
+    cx<T>* o = out + line * g.Mzp;
     static_for<0, R>([&](auto s) {
       const int k = j + s * Tl;
       if (k < g.Mz) o[k] = v[s];
@@ -342,12 +404,13 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
                                                   cx<T>* __restrict__ U1, cx<T>* __restrict__ Acc, long C,
                                                   Geo g, int mode, T nu, T dt) {
   const long stride = (long)gridDim.x * blockDim.x;
-  const long MMz = (long)g.M * g.Mz;
+  const long MMz = (long)g.M * g.Mzp;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < C; e += stride) {
     const int ix = (int)(e / MMz);
     const long r = e - ix * MMz;
-    const int iy = (int)(r / g.Mz);
-    const int kz = (int)(r - (long)iy * g.Mz);
+    const int iy = (int)(r / g.Mzp);
+    const int kz = (int)(r - (long)iy * g.Mzp);
+    if (kz >= g.Mz) continue;  // row padding
     const int kxi = kwave(cpos(ix, g), g.N), kyi = kwave(cpos(iy, g), g.N);
     const int k2i = kxi * kxi + kyi * kyi + kz * kz;
     const T kx = T(kxi), ky = T(kyi), kzf = T(kz), k2 = T(k2i);
@@ -395,23 +458,24 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
 }
 
 // ---------------------------------------------------------------------------
-// Canonical <-> compact.  Canonical: [3][N][N][N/2+1].  Compact: [3][M][M][Mz].
-// Gather drops the modes outside the retained set (projection onto the
-// Galerkin space); scatter writes zeros there.
+// Canonical <-> compact.  Canonical: [3][N][N][N/2+1].  Compact:
+// [3][M][M][Mzp].  Gather drops the modes outside the retained set
+// (projection onto the Galerkin space); scatter writes zeros there.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long C,
                                                 Geo g) {
   const long stride = (long)gridDim.x * blockDim.x;
   const long Nh = g.N / 2 + 1;
-  const long MMz = (long)g.M * g.Mz;
+  const long MMz = (long)g.M * g.Mzp;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < 3 * C; e += stride) {
     const int c = (int)(e / C);
     const long r0 = e - c * C;
     const int ix = (int)(r0 / MMz);
     const long r = r0 - ix * MMz;
-    const int iy = (int)(r / g.Mz);
-    const int kz = (int)(r - (long)iy * g.Mz);
+    const int iy = (int)(r / g.Mzp);
+    const int kz = (int)(r - (long)iy * g.Mzp);
+    if (kz >= g.Mz) continue;
     const long src = (((long)c * g.N + cpos(ix, g)) * g.N + cpos(iy, g)) * Nh + kz;
     out[e] = in[src];
   }
@@ -433,7 +497,7 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, c
     const int kz = (int)(r - (long)py * Nh);
     cx<T> v = {T(0), T(0)};
     if (kz < g.Mz && kept(px, g) && kept(py, g))
-      v = in[(long)c * C + ((long)crow(px, g) * g.M + crow(py, g)) * g.Mz + kz];
+      v = in[(long)c * C + ((long)crow(px, g) * g.M + crow(py, g)) * g.Mzp + kz];
     out[e] = v;
   }
 }

@@ -108,7 +108,9 @@ def test_workspace_size_formula(N, dtype, elem):
         pytest.skip("size not built")
     K = (N - 1) // 3
     M, Mz = 2 * K + 1, K + 1
-    C, D1, D2 = M * M * Mz, N * M * Mz, N * N * Mz
+    seg = 128 // elem  # rows padded to whole 128-byte segments once Mz >= 4 segments
+    P = -(-Mz // seg) * seg if Mz >= 4 * seg else Mz
+    C, D1, D2 = M * M * P, N * M * P, N * N * P
     h, ws = binding.hot_plan(N, "rk4", dtype, nu=0.01, dt=1e-3)
     binding.hot_destroy(h)
     assert ws == 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem)

@@ -153,3 +153,22 @@ def test_runs_are_bitwise_deterministic():
     a = run("rk4", [uh], "f32", nu=NU, dt=DT, nsteps=2)[0]
     b = run("rk4", [uh], "f32", nu=NU, dt=DT, nsteps=2)[0]
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("dtype,N", [("f64", 128), ("f32", 256)])
+def test_rhs_with_padded_rows_matches_oracle(dtype, N):
+    # sizes whose compact z rows are padded to whole 128-byte segments
+    print(f"rhs padded N={N} {dtype}", flush=True)
+    uh = inputs.smooth_random(N, 3)
+    (got,) = run("rhs", [uh], dtype, nu=NU)
+    ref = oracle.rhs(ref_input(uh, dtype), NU)
+    assert rel_l2(got, ref) < tol(dtype, N)
+
+
+def test_rk4_beltrami_exact_decay_padded_fp32():
+    N, K2, nu, dt, n = 256, 50, 0.02, 0.01, 3
+    u0 = inputs.beltrami(N, K2, seed=2)
+    (got,) = run("rk4", [u0], "f32", nu=nu, dt=dt, nsteps=n)
+    z = -nu * K2 * dt
+    R = 1 + z + z**2 / 2 + z**3 / 6 + z**4 / 24
+    assert rel_l2(got, R**n * round32(u0)) < fp32_tol(N)
