@@ -212,72 +212,71 @@ struct Dft {
   }
 };
 
-// ---------------------------------------------------------------------------
-// twiddle tables: w[m] = exp(-2 pi i m / NT), FP64 values rounded once
-// ---------------------------------------------------------------------------
-template <typename T, int NT>
-struct TwTable {
-  cx<T> w[NT];
-};
-
-template <typename T, int NT>
-constexpr TwTable<T, NT> make_twiddles() {
-  TwTable<T, NT> t{};
-  for (int m = 0; m < NT; ++m) {
-    const cs_pair p = unit_root(m, NT);
-    t.w[m].x = T(p.c);
-    t.w[m].y = T(-p.s);
-  }
-  return t;
-}
-
-// Table size for a line length N: 1024 serves every power of two up to 1024,
-// 1728 = 2^6 3^3 every 2^a 3^b (a <= 6, b <= 3).  A length-N twiddle
-// w_N^e is entry e * (tw_size(N) / N).
-template <int N>
-constexpr int tw_size() {
-  static_assert(1024 % N == 0 || 1728 % N == 0, "no twiddle table for this length");
-  return (1024 % N == 0) ? 1024 : 1728;
-}
-
 // Stage twiddle for DIR: forward multiplies by w, inverse by conj(w).
 template <int DIR, typename T>
 __device__ __forceinline__ cx<T> twmul(cx<T> v, cx<T> w) {
   return DIR < 0 ? cmul(v, w) : cmulc(v, w);
 }
 
-// Twiddle sources: operator()(e) returns w_N^e = exp(-2 pi i e / N), e in [0, N).
+// Stage twiddles in stage-major order.  For stage k >= 1 (0-based) with span
+// Ns and radix r, entry off_k + (q-1)*Ns + b holds exp(-2 pi i b q / (Ns r))
+// for q in [1, r) and butterfly residue b in [0, Ns); off_k = sum over the
+// earlier stages k' >= 1 of (r_k' - 1) Ns_k'.  Neighbouring butterflies read
+// neighbouring entries, so the loads coalesce and LDS reads do not conflict.
+// The table has N - r_0 entries (padded to N).
 template <typename T, int N>
-struct TwGlobal {  // the constant table of size tw_size<N>()
-  const cx<T>* tab;
-  __device__ __forceinline__ cx<T> operator()(int e) const { return tab[e * (tw_size<N>() / N)]; }
+struct StageTw {
+  cx<T> w[N];
 };
+
+template <typename T, int N, int... Rs>
+constexpr StageTw<T, N> make_stage_tw() {
+  StageTw<T, N> t{};
+  constexpr int rr[] = {Rs...};
+  long Ns = rr[0];
+  int off = 0;
+  for (int k = 1; k < (int)sizeof...(Rs); ++k) {
+    const int r = rr[k];
+    for (int q = 1; q < r; ++q)
+      for (long b = 0; b < Ns; ++b) {
+        const cs_pair p = unit_root(b * q, Ns * r);
+        t.w[off + (q - 1) * Ns + b].x = T(p.c);
+        t.w[off + (q - 1) * Ns + b].y = T(-p.s);
+      }
+    off += (r - 1) * (int)Ns;
+    Ns *= r;
+  }
+  return t;
+}
+
+// Twiddle source: operator()(i) returns entry i of the stage-major table.
 template <typename T>
-struct TwLds {  // a per-block copy of the N entries in LDS
+struct TwTab {
   const cx<T>* tab;
-  __device__ __forceinline__ cx<T> operator()(int e) const { return tab[e]; }
+  __device__ __forceinline__ cx<T> operator()(int i) const { return tab[i]; }
 };
 
 // ---------------------------------------------------------------------------
 // Stockham engine
 // ---------------------------------------------------------------------------
 // Lds must provide put(pos, v), get(pos) for this thread's line and sync().
-template <typename T, int DIR, int N, int R, int Ns, int... Rs>
+template <typename T, int DIR, int N, int R, int Ns, int OFF, int... Rs>
 struct Stages;
 
-template <typename T, int DIR, int N, int R, int Ns>
-struct Stages<T, DIR, N, R, Ns> {
+template <typename T, int DIR, int N, int R, int Ns, int OFF>
+struct Stages<T, DIR, N, R, Ns, OFF> {
   template <class L, class TW>
   __device__ __forceinline__ static void run(cx<T>*, int, L&, const TW&) {
     static_assert(Ns == N, "radices must multiply to N");
   }
 };
 
-template <typename T, int DIR, int N, int R, int Ns, int r, int... Rs>
-struct Stages<T, DIR, N, R, Ns, r, Rs...> {
+template <typename T, int DIR, int N, int R, int Ns, int OFF, int r, int... Rs>
+struct Stages<T, DIR, N, R, Ns, OFF, r, Rs...> {
   static constexpr int Tl = N / R;
   static constexpr int nb = R / r;
   static constexpr bool last = (Ns * r == N);
+  static constexpr int NEXT_OFF = Ns > 1 ? OFF + (r - 1) * Ns : OFF;
   static_assert(R % r == 0, "each radix must divide the per-thread count");
 
   template <class L, class TW>
@@ -287,8 +286,8 @@ struct Stages<T, DIR, N, R, Ns, r, Rs...> {
       cx<T> b[r];
       static_for<0, r>([&](auto q) { b[q] = v[m + q * nb]; });
       if constexpr (Ns > 1) {
-        const int step = (jj % Ns) * (N / (Ns * r));
-        static_for<1, r>([&](auto q) { b[q] = twmul<DIR>(b[q], tw(step * q)); });
+        const int res = jj % Ns;
+        static_for<1, r>([&](auto q) { b[q] = twmul<DIR>(b[q], tw(OFF + (q - 1) * Ns + res)); });
       }
       Dft<r, DIR, T>::run(b);
       if constexpr (!last) {
@@ -302,7 +301,7 @@ struct Stages<T, DIR, N, R, Ns, r, Rs...> {
       lds.sync();
       static_for<0, R>([&](auto s) { v[s] = lds.get(j + s * Tl); });
       lds.sync();
-      Stages<T, DIR, N, R, Ns * r, Rs...>::run(v, j, lds, tw);
+      Stages<T, DIR, N, R, Ns * r, NEXT_OFF, Rs...>::run(v, j, lds, tw);
     }
   }
 };
@@ -330,11 +329,19 @@ struct LinePlan {
   // LDS banks.
   static constexpr int SH = ilog2<FirstOf<Rs...>::value>();
   static constexpr int line_slots = N_ + (N_ >> SH) + 1;
+  template <typename T>
+  static constexpr StageTw<T, N_> twiddles() {
+    return make_stage_tw<T, N_, Rs...>();
+  }
   template <typename T, int DIR, class L, class TW>
   __device__ __forceinline__ static void fft(cx<T>* v, int j, L& lds, const TW& tw) {
-    Stages<T, DIR, N_, R_, 1, Rs...>::run(v, j, lds, tw);
+    Stages<T, DIR, N_, R_, 1, 0, Rs...>::run(v, j, lds, tw);
   }
 };
+
+// Stage-major twiddles of a plan, in device memory.
+template <typename T, class Plan>
+__device__ const StageTw<T, Plan::N> g_stage_tw = Plan::template twiddles<T>();
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -13,11 +13,6 @@
 
 namespace hot {
 
-__device__ const TwTable<float, 1024> g_tw1024_f = make_twiddles<float, 1024>();
-__device__ const TwTable<double, 1024> g_tw1024_d = make_twiddles<double, 1024>();
-__device__ const TwTable<float, 1728> g_tw1728_f = make_twiddles<float, 1728>();
-__device__ const TwTable<double, 1728> g_tw1728_d = make_twiddles<double, 1728>();
-
 // ---------------------------------------------------------------------------
 // line plans per length (per-thread count R and radix sequence)
 // ---------------------------------------------------------------------------
@@ -47,10 +42,13 @@ template <> struct LPz<1024> { using P = LinePlan<1024, 8, 8, 8, 8, 2>; };
 // Columns per block of a strided pass: at least one 128-byte segment per row
 // (16 FP32 / 8 FP64 complex values), more while the LDS tile stays within
 // 64 KB; never above 1024 threads or a 128 KB tile.
+#ifndef HOT_SEG_BYTES
+#define HOT_SEG_BYTES 128
+#endif
 template <typename T, int N>
 constexpr int cols_per_block() {
   constexpr int tl = LP<N>::P::Tl;
-  constexpr int seg = int(128 / sizeof(cx<T>));
+  constexpr int seg = int(HOT_SEG_BYTES / sizeof(cx<T>));
   int w = int(65536 / (N * sizeof(cx<T>)));
   if (w > 64) w = 64;
   if (w < seg) w = seg;
@@ -114,7 +112,10 @@ struct Impl {
   template <int DIR, bool IC, bool OC>
   static void go(hipStream_t s, const void* in, void* out, long ncols, long Qp, long ld_in, long ld_out, long bs_in,
                  long bs_out, long cs_in, long cs_out, int ncomp, const Geo& g) {
-    dim3 grid((unsigned)((ncols + W - 1) / W), (unsigned)ncomp);
+    constexpr int pair = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+    const long ntiles = (ncols + W - 1) / W;
+    const long group = 8L * pair;
+    dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)ncomp);
     hipLaunchKernelGGL((k_strided<T, P, DIR, W, IC, OC>), grid, dim3(W * Tl), 0, s, (const cx<T>*)in, (cx<T>*)out,
                        ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, g);
   }
@@ -137,9 +138,10 @@ struct Impl {
   static hipError_t x_inv_curl(hipStream_t s, const void* U, long csU, void* A, long csA, const Geo& g) {
     const long Q = (long)g.M * g.Mzp;
     const int ntiles = (int)((Q + W - 1) / W);
-    const unsigned nblk = 8u * 6u * (unsigned)((ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_x_inv_curl<T, P, W>), dim3(nblk), dim3(W * Tl), 0, s, (const cx<T>*)U, csU, (cx<T>*)A, csA,
-                       ntiles, g);
+    constexpr int pair = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+    const unsigned nblk = 8u * 6u * (unsigned)((ntiles + 8 * pair - 1) / (8 * pair) * pair);
+    hipLaunchKernelGGL((k_x_inv_curl<T, P, W>), dim3(nblk), dim3(W * Tl), 0, s, (const cx<T>*)U, csU, (cx<T>*)A,
+                       csA, ntiles, g);
     return hipGetLastError();
   }
   using PZ = typename LPz<N>::P;

@@ -38,20 +38,28 @@ __device__ __forceinline__ int cpos(int i, const Geo& g) { return i < g.lo ? i :
 // signed wavenumber (Eq. wavemesh) of FFT position p
 __device__ __forceinline__ int kwave(int p, int N) { return 2 * p <= N ? p : p - N; }
 
-extern __device__ const TwTable<float, 1024> g_tw1024_f;
-extern __device__ const TwTable<double, 1024> g_tw1024_d;
-extern __device__ const TwTable<float, 1728> g_tw1728_f;
-extern __device__ const TwTable<double, 1728> g_tw1728_d;
+// Stores of pass outputs: streamed (non-temporal), since no kernel re-reads
+// them while they could still sit in a cache.  (Measured on MI355X: faster
+// for the passes that write every row; the compacting forward passes are
+// faster with plain stores, see store_out.)
+template <typename T>
+__device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
 
-template <typename T, int N>
-__device__ __forceinline__ const cx<T>* twiddle_table() {
-  if constexpr (std::is_same<T, float>::value) {
-    if constexpr (tw_size<N>() == 1024) return g_tw1024_f.w;
-    else return g_tw1728_f.w;
-  } else {
-    if constexpr (tw_size<N>() == 1024) return g_tw1024_d.w;
-    else return g_tw1728_d.w;
-  }
+template <bool NT, typename T>
+__device__ __forceinline__ void store_out(cx<T>* p, cx<T> v) {
+  if constexpr (NT) store_stream(p, v);
+  else *p = v;
+}
+
+// Block barrier that orders LDS accesses only (global loads in flight stay in
+// flight across it).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // LDS view for a tile of W interleaved columns (strided passes).  Positions
@@ -65,7 +73,7 @@ struct LdsCols {
   __device__ __forceinline__ static int sw(int p) { return kSwz ? (p ^ ((p >> 4) & 3)) : p; }
   __device__ __forceinline__ void put(int pos, cx<T> v) { base[sw(pos) * W + c] = v; }
   __device__ __forceinline__ cx<T> get(int pos) const { return base[sw(pos) * W + c]; }
-  __device__ __forceinline__ void sync() { __syncthreads(); }
+  __device__ __forceinline__ void sync() { lds_barrier(); }
 };
 
 // LDS view for one contiguous line owned by a lane group (inside one wave,
@@ -78,7 +86,7 @@ struct LdsLine {
   __device__ __forceinline__ void put(int pos, cx<T> v) { base[sw(pos)] = v; }
   __device__ __forceinline__ cx<T> get(int pos) const { return base[sw(pos)]; }
   __device__ __forceinline__ void sync() {
-    if constexpr (BLOCK) __syncthreads();
+    if constexpr (BLOCK) lds_barrier();
     else wave_sync();
   }
 };
@@ -93,6 +101,19 @@ struct ZShape {
   static constexpr int LPB = 256 / Tl;  // lines per block
 };
 
+// Tile of block b when PAIR consecutive tiles share one 128-byte row segment:
+// the tiles of a segment go to blocks with equal b mod 8 (one XCD, one L2),
+// back to back, so the L2 merges their half-line reads and writes.
+template <int PAIR>
+__device__ __forceinline__ long tile_of_block(long b) {
+  if constexpr (PAIR == 1) {
+    return b;
+  } else {
+    const long xcd = b & 7, slot = b >> 3;
+    return ((slot / PAIR) * 8 + xcd) * PAIR + (slot % PAIR);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Strided axis pass: columns are contiguous, lines run along rows.
 // The array is a batch of [rows][Qp] blocks (global column gc = b*Qp + q);
@@ -104,10 +125,13 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
                                                          long ncols, long Qp, long ld_in, long ld_out, long bs_in,
                                                          long bs_out, long cs_in, long cs_out, Geo g) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
+  const long tile = tile_of_block<PAIR>(blockIdx.x);
+  if (tile * W >= ncols) return;  // whole block leaves together
   const int tid = threadIdx.x;
   const int c = tid % W, j = tid / W;
-  const long gc = (long)blockIdx.x * W + c;
+  const long gc = tile * W + c;
   const long b = gc / Qp;
   const long q = gc - b * Qp;
   const bool valid = gc < ncols && (int)(q % g.Mzp) < g.Mz;
@@ -125,13 +149,13 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
     v[s] = x;
   });
   LdsCols<T, N, W> lds{sm, c};
-  Plan::template fft<T, DIR>(v, j, lds, TwGlobal<T, N>{twiddle_table<T, N>()});
+  Plan::template fft<T, DIR>(v, j, lds, TwTab<T>{g_stage_tw<T, Plan>.w});
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
     if (OUT_C) {
-      if (valid && kept(p, g)) out[ob + (long)crow(p, g) * ld_out] = v[s];
+      if (valid && kept(p, g)) store_out<false>(out + ob + (long)crow(p, g) * ld_out, v[s]);
     } else {
-      if (valid) out[ob + (long)p * ld_out] = v[s];
+      if (valid) store_out<true>(out + ob + (long)p * ld_out, v[s]);
     }
   });
 }
@@ -139,20 +163,24 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
 // ---------------------------------------------------------------------------
 // P1: inverse transform along x of the velocity and of the vorticity
 // omega_hat = i k x u_hat (curl fused into the load).  Input compact state
-// U[3][M rows (kx)][Q = M*Mzp cols (ky,kz)], output A[6][N rows (x)][Q].
-// Block b: the 6 output components of one tile go to blocks with equal
-// b mod 8 (one XCD) so that their shared input rows meet in one L2.
+// U[3][M rows (kx)][Q = M*Mzp cols (ky,kz)], output A[6][N rows (x)][Q] with
+// components (u_x, u_y, u_z, w_x, w_y, w_z).  One block per (tile, output
+// component); the 6 components of a tile go to blocks with equal b mod 8
+// (one XCD) so that their shared input rows are read from HBM once and then
+// served by that XCD's L2.
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int W>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restrict__ U, long csU,
                                                             cx<T>* __restrict__ A, long csA, int ntiles,
                                                             Geo g) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
   const int blk = blockIdx.x;
   const int xcd = blk & 7, slot = blk >> 3;
   const int o = slot % 6;
-  const int tile = (slot / 6) * 8 + xcd;
+  const int rest = slot / 6;
+  const int tile = ((rest / PAIR) * 8 + xcd) * PAIR + rest % PAIR;
   if (tile >= ntiles) return;  // whole block leaves together
   const int tid = threadIdx.x;
   const int c = tid % W, j = tid / W;
@@ -186,10 +214,10 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
     v[s] = x;
   });
   LdsCols<T, N, W> lds{sm, c};
-  Plan::template fft<T, +1>(v, j, lds, TwGlobal<T, N>{twiddle_table<T, N>()});
+  Plan::template fft<T, +1>(v, j, lds, TwTab<T>{g_stage_tw<T, Plan>.w});
   if (valid) {
     cx<T>* dst = A + o * csA + q;
-    static_for<0, R>([&](auto s) { dst[(long)(j + s * Tl) * Q] = v[s]; });
+    static_for<0, R>([&](auto s) { store_stream(dst + (long)(j + s * Tl) * Q, v[s]); });
   }
 }
 
@@ -247,11 +275,11 @@ __device__ __forceinline__ void load_line(cx<T> (&la)[z_loads<Plan>()], const cx
   });
 }
 
-// Copy the N twiddles w_N^e of this line length into LDS (once per block).
-template <typename T, int N>
+// Copy the plan's stage-major twiddles into LDS (once per block).
+template <typename T, class Plan>
 __device__ __forceinline__ void stage_twiddles(cx<T>* tws) {
-  const cx<T>* tab = twiddle_table<T, N>();
-  for (int e = threadIdx.x; e < N; e += blockDim.x) tws[e] = tab[e * (tw_size<N>() / N)];
+  const cx<T>* tab = g_stage_tw<T, Plan>.w;
+  for (int e = threadIdx.x; e < Plan::N; e += blockDim.x) tws[e] = tab[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -269,7 +297,7 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   constexpr int LS = Plan::line_slots;
   __shared__ cx<T> sm[LPB * LS];
   __shared__ cx<T> tws[N];
-  stage_twiddles<T, N>(tws);
+  stage_twiddles<T, Plan>(tws);
   __syncthreads();
   const int tid = threadIdx.x;
   const int li = tid / Tl, j = tid % Tl;
@@ -277,7 +305,7 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   const bool valid = line < nlines;
   const int Mz = g.Mz;
   LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
-  const TwLds<T> tw{tws};
+  const TwTab<T> tw{tws};
   const long base = valid ? line * g.Mzp : 0;
 
   cx<T> la[KL], lb[KL];
@@ -318,9 +346,9 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
       if (k < Mz) {
         const cx<T> zk = lds.get(k);
         const cx<T> zm = lds.get((N - k) % N);
-        o0[k] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-        o1[k] = {T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
-        o2[k] = z2[s];
+        store_stream(o0 + k, cx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)});
+        store_stream(o1 + k, cx<T>{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)});
+        store_stream(o2 + k, z2[s]);
       }
     });
   }
@@ -338,7 +366,7 @@ __global__ __launch_bounds__(256) void k_z_c2r(const cx<T>* __restrict__ in, T* 
   constexpr int LS = Plan::line_slots;
   __shared__ cx<T> sm[LPB * LS];
   __shared__ cx<T> tws[N];
-  stage_twiddles<T, N>(tws);
+  stage_twiddles<T, Plan>(tws);
   __syncthreads();
   const int tid = threadIdx.x;
   const int li = tid / Tl, j = tid % Tl;
@@ -353,7 +381,7 @@ __global__ __launch_bounds__(256) void k_z_c2r(const cx<T>* __restrict__ in, T* 
   lds.sync();
   read_completed<T, Plan>(lds, v, j, g.Mz);
   lds.sync();
-  Plan::template fft<T, +1>(v, j, lds, TwLds<T>{tws});
+  Plan::template fft<T, +1>(v, j, lds, TwTab<T>{tws});
   if (valid) {
     T* o = out + line * N;
     static_for<0, R>([&](auto s) { o[j + s * Tl] = v[s].x * scale; });
@@ -368,7 +396,7 @@ __global__ __launch_bounds__(256) void k_z_r2c(const T* __restrict__ in, cx<T>* 
   constexpr int LS = Plan::line_slots;
   __shared__ cx<T> sm[LPB * LS];
   __shared__ cx<T> tws[N];
-  stage_twiddles<T, N>(tws);
+  stage_twiddles<T, Plan>(tws);
   __syncthreads();
   const int tid = threadIdx.x;
   const int li = tid / Tl, j = tid % Tl;
@@ -378,7 +406,7 @@ __global__ __launch_bounds__(256) void k_z_r2c(const T* __restrict__ in, cx<T>* 
   const T* a = in + (valid ? line * N : 0);
   cx<T> v[R];
   static_for<0, R>([&](auto s) { v[s] = {valid ? a[j + s * Tl] : T(0), T(0)}; });
-  Plan::template fft<T, -1>(v, j, lds, TwLds<T>{tws});
+  Plan::template fft<T, -1>(v, j, lds, TwTab<T>{tws});
   if (valid) {
     cx<T>* o = out + line * g.Mzp;
     static_for<0, R>([&](auto s) {
@@ -427,33 +455,33 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
     const cx<T> d1 = n1 - kn * ky - s1 * vk;
     const cx<T> d2 = n2 - kn * kzf - s2 * vk;
     if (mode == 4) {
-      Acc[e] = d0;
-      Acc[C + e] = d1;
-      Acc[2 * C + e] = d2;
+      store_stream(Acc + e, d0);
+      store_stream(Acc + C + e, d1);
+      store_stream(Acc + 2 * C + e, d2);
       continue;
     }
     if (mode == 3) {
       const T h = dt / T(6);
-      U0[e] = Acc[e] + d0 * h;
-      U0[C + e] = Acc[C + e] + d1 * h;
-      U0[2 * C + e] = Acc[2 * C + e] + d2 * h;
+      store_stream(U0 + e, Acc[e] + d0 * h);
+      store_stream(U0 + C + e, Acc[C + e] + d1 * h);
+      store_stream(U0 + 2 * C + e, Acc[2 * C + e] + d2 * h);
       continue;
     }
     const cx<T> a0 = U0[e], a1 = U0[C + e], a2 = U0[2 * C + e];
     const T ha = (mode == 0) ? dt / T(6) : dt / T(3);
     const T hu = (mode == 2) ? dt : dt / T(2);
     if (mode == 0) {
-      Acc[e] = a0 + d0 * ha;
-      Acc[C + e] = a1 + d1 * ha;
-      Acc[2 * C + e] = a2 + d2 * ha;
+      store_stream(Acc + e, a0 + d0 * ha);
+      store_stream(Acc + C + e, a1 + d1 * ha);
+      store_stream(Acc + 2 * C + e, a2 + d2 * ha);
     } else {
-      Acc[e] = Acc[e] + d0 * ha;
-      Acc[C + e] = Acc[C + e] + d1 * ha;
-      Acc[2 * C + e] = Acc[2 * C + e] + d2 * ha;
+      store_stream(Acc + e, Acc[e] + d0 * ha);
+      store_stream(Acc + C + e, Acc[C + e] + d1 * ha);
+      store_stream(Acc + 2 * C + e, Acc[2 * C + e] + d2 * ha);
     }
-    U1[e] = a0 + d0 * hu;
-    U1[C + e] = a1 + d1 * hu;
-    U1[2 * C + e] = a2 + d2 * hu;
+    store_stream(U1 + e, a0 + d0 * hu);
+    store_stream(U1 + C + e, a1 + d1 * hu);
+    store_stream(U1 + 2 * C + e, a2 + d2 * hu);
   }
 }
 
@@ -477,7 +505,7 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in, cx
     const int kz = (int)(r - (long)iy * g.Mzp);
     if (kz >= g.Mz) continue;
     const long src = (((long)c * g.N + cpos(ix, g)) * g.N + cpos(iy, g)) * Nh + kz;
-    out[e] = in[src];
+    store_stream(out + e, in[src]);
   }
 }
 
@@ -498,7 +526,7 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, c
     cx<T> v = {T(0), T(0)};
     if (kz < g.Mz && kept(px, g) && kept(py, g))
       v = in[(long)c * C + ((long)crow(px, g) * g.M + crow(py, g)) * g.Mzp + kz];
-    out[e] = v;
+    store_stream(out + e, v);
   }
 }
 

@@ -36,6 +36,7 @@ __all__ = [
     "smooth_random_modes",
     "rough_random",
     "beltrami",
+    "beltrami_modes",
     "kinetic_energy",
 ]
 
@@ -209,11 +210,13 @@ def rough_random(N: int, seed: int, dealias: str = "two_thirds") -> np.ndarray:
     return uh * np.sqrt(0.125 / E)
 
 
-def beltrami(N: int, K2: int, seed: int, sign: int = 1) -> np.ndarray:
-    """Random field on the shell |k|^2 = K2 built from helical vectors
-    h = (e1 + i*sign*e2)/sqrt(2), for which i k x h = sign*|k| h, so the
-    vorticity is sign*sqrt(K2) times the velocity and u x omega = 0.
-    Scaled to E = 1/8.  Requires the shell to survive the 2/3 rule."""
+def beltrami_modes(N: int, K2: int, seed: int, sign: int = 1):
+    """Random field on the shell |k|^2 = K2 in sparse form: FFT indices
+    (ix, iy, iz) and values (3, n) of the nonzero half-spectrum entries.
+    Built from helical vectors h = (e1 + i*sign*e2)/sqrt(2), for which
+    i k x h = sign*|k| h, so the vorticity is sign*sqrt(K2) times the velocity
+    and u x omega = 0.  Scaled to E = 1/8 on the N grid.  Requires the shell
+    to survive the 2/3 rule."""
     kmax = int(np.floor(np.sqrt(K2)))
     k = _band_vectors(kmax)
     on = np.sum(k * k, axis=-1) == K2
@@ -228,13 +231,20 @@ def beltrami(N: int, K2: int, seed: int, sign: int = 1) -> np.ndarray:
     # right-handed pair: e1 x e2 = k/|k|  (true by construction of _plane_basis)
     h = (e1 + 1j * sign * e2) / np.sqrt(2.0)
     amp = a[:, None] * h
-    # Hermitian pairing u(-k) = conj(u(k)) keeps the helicity sign; enforce it
-    # on the whole shell before placing so the kz=0 averaging is exact.
-    idx = {tuple(v): m for m, v in enumerate(k)}
-    paired = amp.copy()
-    for m, v in enumerate(k):
-        mm = idx[tuple(-v)]
-        paired[m] = 0.5 * (amp[m] + np.conj(amp[mm]))
-    uh = _place_band(N, k, paired, np.ones(len(k), bool))
-    E = kinetic_energy(uh)
-    return uh * np.sqrt(0.125 / E)
+    # Hermitian pairing u(-k) = conj(u(k)) keeps the helicity sign; the shell
+    # is symmetric and lexicographically ordered, so -k sits at n-1-m
+    amp = 0.5 * (amp + np.conj(amp[::-1]))
+    up = k[:, 2] >= 0
+    kk, vals = k[up], amp[up].T.copy()
+    w = np.where(kk[:, 2] == 0, 1.0, 2.0)
+    E = float(np.sum(w * np.sum(np.abs(vals) ** 2, axis=0)) / (2.0 * float(N) ** 6))
+    vals *= np.sqrt(0.125 / E)
+    return kk[:, 0] % N, kk[:, 1] % N, kk[:, 2], vals
+
+
+def beltrami(N: int, K2: int, seed: int, sign: int = 1) -> np.ndarray:
+    """Dense half-spectrum of beltrami_modes(N, K2, seed, sign)."""
+    ix, iy, iz, vals = beltrami_modes(N, K2, seed, sign)
+    uh = np.zeros(_half_shape(N), dtype=np.complex128)
+    uh[:, ix, iy, iz] = vals
+    return uh
