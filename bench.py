@@ -52,6 +52,54 @@ def load_counters(kernel, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def ingest_counters(fetch_csv, write_csv, calib_mib, workload, command):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch) of `bench.py --steps 1 --warmup 0 --calibrate-copy MIB` into
+    profiles/counters.json: mean HBM bytes per launch for each libhot kernel,
+    each counter scaled by what it reads for the plain copy kernel of known
+    size (MIB MiB read and MIB MiB written)."""
+    import csv
+    import re
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            m = re.search(r"hot::(k_\w+)", r["Kernel_Name"])
+            name = m.group(1) if m else r["Kernel_Name"]
+            if name.startswith("k_strided"):
+                m2 = re.search(r"LinePlan<[^>]*>, (-?1), \d+, (true|false), (true|false)", r["Kernel_Name"])
+                name = {("1", "true", "false"): "y_inv", ("-1", "false", "true"): "y_or_x_fwd"}.get(
+                    m2.groups() if m2 else None, "k_strided")
+            vals[name].append(float(r["Counter_Value"]))
+        return vals
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    true_bytes = float(calib_mib) * 2**20
+    fs = true_bytes / (fetch[COPY_KERNEL][0] * 1024.0)
+    ws = true_bytes / (write[COPY_KERNEL][0] * 1024.0)
+    names = {"k_z_cross": "z_cross", "k_x_inv_curl": "x_inv_curl", "k_rk_stage": "rk_stage",
+             "k_gather": "gather", "k_scatter": "scatter", "y_inv": "y_inv"}
+    out = {"fetch_scale": fs, "write_scale": ws, "command": command}
+    for k, pname in names.items():
+        if k in fetch and k in write:
+            f = sum(fetch[k]) / len(fetch[k]) * 1024.0 * fs
+            w = sum(write[k]) / len(write[k]) * 1024.0 * ws
+            out[pname] = {"fetch_bytes": f, "write_bytes": w, "hbm_bytes_per_launch": f + w,
+                          "dispatches": len(fetch[k]), "source_hash": source_hash()}
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    d = json.load(open(path)) if os.path.exists(path) else {}
+    d[workload] = out
+    json.dump(d, open(path, "w"), indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1))
+
+
 def device_field(N, dtype, seed=0):
     """R1 (smooth random solenoidal field, E = 1/8) scattered on the GPU."""
     import torch
@@ -111,7 +159,16 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (a known-size kernel "
                          "for scaling HBM byte counters)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/counters.json from two rocprofv3 --pmc counter_collection.csv files "
+                         "(no GPU needed); use with --calibrate-copy MIB and --pmc-command")
+    ap.add_argument("--pmc-command", default="", help="the profiled command, recorded with the counters")
     a = ap.parse_args()
+
+    if a.ingest_counters:
+        ingest_counters(a.ingest_counters[0], a.ingest_counters[1], a.calibrate_copy,
+                        f"rk4_step_{a.n}^3_{a.dtype}", a.pmc_command)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:

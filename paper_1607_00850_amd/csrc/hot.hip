@@ -150,7 +150,14 @@ struct Impl {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const double n3 = double(N) * N * N;
     const T scale = T(1.0 / (n3 * n3));
-    hipLaunchKernelGGL((k_z_cross<T, PZ>), dim3(nblk), dim3(256), 0, s, (cx<T>*)A, csA, nlines, g, scale);
+    // coefficients per lane: the 2/3-rule count, or the all-but-Nyquist one
+    constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
+    if (g.Mz <= KL23 * PZ::Tl)
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23>), dim3(nblk), dim3(256), 0, s, (cx<T>*)A, csA, nlines, g, scale);
+    else if (g.Mz <= KLall * PZ::Tl)
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall>), dim3(nblk), dim3(256), 0, s, (cx<T>*)A, csA, nlines, g, scale);
+    else
+      return hipErrorInvalidValue;
     return hipGetLastError();
   }
   static hipError_t z_c2r(hipStream_t s, const void* in, void* out, long nlines, const Geo& g) {

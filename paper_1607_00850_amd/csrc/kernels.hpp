@@ -225,10 +225,10 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
 // z-axis lines.  A group of Tl = N/R lanes owns one line (see ZShape).
 // ---------------------------------------------------------------------------
 
-// Number of compact z coefficients a lane loads (upper bound over modes).
+// Number of compact z coefficients a lane loads when Mz coefficients are kept.
 template <class Plan>
-constexpr int z_loads() {
-  return (Plan::N / 2 + 1 + Plan::Tl - 1) / Plan::Tl;
+constexpr int z_loads(int Mz = Plan::N / 2 + 1) {
+  return (Mz + Plan::Tl - 1) / Plan::Tl;
 }
 
 // Lay out Z_p = a_p + i b_p on the full circle in the line's LDS region from
@@ -237,11 +237,10 @@ constexpr int z_loads() {
 // inverse transform, the imaginary parts of the kz = 0 and kz = N/2
 // coefficients are dropped.  Positions no coefficient reaches read as zero in
 // read_completed().
-template <typename T, class Plan, class L>
-__device__ __forceinline__ void put_completed(L& lds, const cx<T> (&la)[z_loads<Plan>()],
-                                              const cx<T> (&lb)[z_loads<Plan>()], int j, int Mz) {
+template <typename T, class Plan, int KL, class L>
+__device__ __forceinline__ void put_completed(L& lds, const cx<T> (&la)[KL], const cx<T> (&lb)[KL], int j, int Mz) {
   constexpr int N = Plan::N, Tl = Plan::Tl;
-  static_for<0, z_loads<Plan>()>([&](auto t) {
+  static_for<0, KL>([&](auto t) {
     const int k = j + t * Tl;
     if (k < Mz) {
       cx<T> x = la[t], y = lb[t];
@@ -266,10 +265,9 @@ __device__ __forceinline__ void read_completed(const L& lds, cx<T>* v, int j, in
 }
 
 // Coalesced load of a compact z line: lane j takes k = j + t*Tl (k < Mz).
-template <typename T, class Plan>
-__device__ __forceinline__ void load_line(cx<T> (&la)[z_loads<Plan>()], const cx<T>* __restrict__ a, int j, int Mz,
-                                          bool valid) {
-  static_for<0, z_loads<Plan>()>([&](auto t) {
+template <typename T, class Plan, int KL>
+__device__ __forceinline__ void load_line(cx<T> (&la)[KL], const cx<T>* __restrict__ a, int j, int Mz, bool valid) {
+  static_for<0, KL>([&](auto t) {
     const int k = j + t * Plan::Tl;
     la[t] = (valid && k < Mz) ? a[k] : cx<T>{T(0), T(0)};
   });
@@ -290,9 +288,9 @@ __device__ __forceinline__ void stage_twiddles(cx<T>* tws) {
 // In place: reads components 0..5 of the line, writes 0..2.  The loads of the
 // next component pair are issued before the current pair's FFT.
 // ---------------------------------------------------------------------------
-template <typename T, class Plan>
+template <typename T, class Plan, int KL>
 __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA, long nlines, Geo g, T scale) {
-  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, KL = z_loads<Plan>();
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
   constexpr int LS = Plan::line_slots;
   __shared__ cx<T> sm[LPB * LS];
@@ -303,23 +301,23 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   const int li = tid / Tl, j = tid % Tl;
   const long line = (long)blockIdx.x * LPB + li;
   const bool valid = line < nlines;
-  const int Mz = g.Mz;
+  const int Mz = g.Mz;  // the launcher guarantees Mz <= KL * Tl
   LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
   const TwTab<T> tw{tws};
   const long base = valid ? line * g.Mzp : 0;
 
   cx<T> la[KL], lb[KL];
-  load_line<T, Plan>(la, A + base, j, Mz, valid);
-  load_line<T, Plan>(lb, A + csA + base, j, Mz, valid);
+  load_line<T, Plan, KL>(la, A + base, j, Mz, valid);
+  load_line<T, Plan, KL>(lb, A + csA + base, j, Mz, valid);
   cx<T> ph[3][R];
   static_for<0, 3>([&](auto pr) {
-    put_completed<T, Plan>(lds, la, lb, j, Mz);
+    put_completed<T, Plan, KL>(lds, la, lb, j, Mz);
     lds.sync();
     read_completed<T, Plan>(lds, ph[pr], j, Mz);
     lds.sync();
     if constexpr (pr < 2) {
-      load_line<T, Plan>(la, A + (2 * pr + 2) * csA + base, j, Mz, valid);
-      load_line<T, Plan>(lb, A + (2 * pr + 3) * csA + base, j, Mz, valid);
+      load_line<T, Plan, KL>(la, A + (2 * pr + 2) * csA + base, j, Mz, valid);
+      load_line<T, Plan, KL>(lb, A + (2 * pr + 3) * csA + base, j, Mz, valid);
     }
     Plan::template fft<T, +1>(ph[pr], j, lds, tw);
   });
@@ -374,10 +372,10 @@ __global__ __launch_bounds__(256) void k_z_c2r(const cx<T>* __restrict__ in, T* 
   const bool valid = line < nlines;
   LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
   cx<T> la[KL], lb[KL];
-  load_line<T, Plan>(la, in + (valid ? line * g.Mzp : 0), j, g.Mz, valid);
+  load_line<T, Plan, KL>(la, in + (valid ? line * g.Mzp : 0), j, g.Mz, valid);
   static_for<0, KL>([&](auto t) { lb[t] = {T(0), T(0)}; });
   cx<T> v[R];
-  put_completed<T, Plan>(lds, la, lb, j, g.Mz);
+  put_completed<T, Plan, KL>(lds, la, lb, j, g.Mz);
   lds.sync();
   read_completed<T, Plan>(lds, v, j, g.Mz);
   lds.sync();
