@@ -85,7 +85,7 @@ typedef struct hot_desc {
 
 typedef struct hot_plan_s* hot_plan_t;
 
-/* Supported sizes: N in {8, 16, 32, 64, 128, 256, 512, 1024}. */
+/* Supported sizes: N in {8, 16, 18, 24, 32, 36, 48, 54, 64, 128, 256, 512, 1024}. */
 
 /* Validate d, build a plan and report the workspace size in bytes.
  * The plan copies d->n.  On error *out is set to NULL.

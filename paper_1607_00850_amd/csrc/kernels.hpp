@@ -92,13 +92,30 @@ struct LdsLine {
 };
 
 // z kernels run 256-thread blocks; a line is held by Tl lanes that either sit
-// inside one wave (Tl divides 64) or span whole waves (block barriers).
+// inside one wave (floor(64/Tl) lines per wave; leftover lanes idle) or span
+// whole waves (block barriers).  Idle lanes work on a private dummy line.
 template <class Plan>
 struct ZShape {
   static constexpr int Tl = Plan::Tl;
-  static_assert((Tl <= 64 && 64 % Tl == 0) || (Tl % 64 == 0 && 256 % Tl == 0), "unsupported z line shape");
+  static_assert(Tl <= 64 || (Tl % 64 == 0 && 256 % Tl == 0), "unsupported z line shape");
   static constexpr bool kBlock = Tl > 64;
-  static constexpr int LPB = 256 / Tl;  // lines per block
+  static constexpr int LPW = kBlock ? 1 : 64 / Tl;        // lines per wave
+  static constexpr int LPB = kBlock ? 256 / Tl : 4 * LPW;  // lines per block
+  static constexpr int SLOTS = LPB + (kBlock ? 0 : 4);     // + one dummy line per wave
+  // line slot and lane index of thread tid; live == false for idle lanes
+  __device__ __forceinline__ static void place(int tid, int& li, int& j, bool& live) {
+    if constexpr (kBlock) {
+      li = tid / Tl;
+      j = tid % Tl;
+      live = true;
+    } else {
+      const int w = tid >> 6, lane = tid & 63;
+      const int l = lane / Tl;
+      live = l < LPW;
+      li = live ? w * LPW + l : LPB + w;
+      j = lane % Tl;
+    }
+  }
 };
 
 // Tile of block b when PAIR consecutive tiles share one 128-byte row segment:
@@ -293,14 +310,15 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
   constexpr int LS = Plan::line_slots;
-  __shared__ cx<T> sm[LPB * LS];
+  __shared__ cx<T> sm[ZShape<Plan>::SLOTS * LS];
   __shared__ cx<T> tws[N];
   stage_twiddles<T, Plan>(tws);
   __syncthreads();
-  const int tid = threadIdx.x;
-  const int li = tid / Tl, j = tid % Tl;
+  int li, j;
+  bool live;
+  ZShape<Plan>::place(threadIdx.x, li, j, live);
   const long line = (long)blockIdx.x * LPB + li;
-  const bool valid = line < nlines;
+  const bool valid = live && line < nlines;
   const int Mz = g.Mz;  // the launcher guarantees Mz <= KL * Tl
   LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
   const TwTab<T> tw{tws};
@@ -362,14 +380,15 @@ __global__ __launch_bounds__(256) void k_z_c2r(const cx<T>* __restrict__ in, T* 
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, KL = z_loads<Plan>();
   constexpr int LPB = ZShape<Plan>::LPB;
   constexpr int LS = Plan::line_slots;
-  __shared__ cx<T> sm[LPB * LS];
+  __shared__ cx<T> sm[ZShape<Plan>::SLOTS * LS];
   __shared__ cx<T> tws[N];
   stage_twiddles<T, Plan>(tws);
   __syncthreads();
-  const int tid = threadIdx.x;
-  const int li = tid / Tl, j = tid % Tl;
+  int li, j;
+  bool live;
+  ZShape<Plan>::place(threadIdx.x, li, j, live);
   const long line = (long)blockIdx.x * LPB + li;
-  const bool valid = line < nlines;
+  const bool valid = live && line < nlines;
   LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
   cx<T> la[KL], lb[KL];
   load_line<T, Plan, KL>(la, in + (valid ? line * g.Mzp : 0), j, g.Mz, valid);
@@ -392,14 +411,15 @@ __global__ __launch_bounds__(256) void k_z_r2c(const T* __restrict__ in, cx<T>* 
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
   constexpr int LS = Plan::line_slots;
-  __shared__ cx<T> sm[LPB * LS];
+  __shared__ cx<T> sm[ZShape<Plan>::SLOTS * LS];
   __shared__ cx<T> tws[N];
   stage_twiddles<T, Plan>(tws);
   __syncthreads();
-  const int tid = threadIdx.x;
-  const int li = tid / Tl, j = tid % Tl;
+  int li, j;
+  bool live;
+  ZShape<Plan>::place(threadIdx.x, li, j, live);
   const long line = (long)blockIdx.x * LPB + li;
-  const bool valid = line < nlines;
+  const bool valid = live && line < nlines;
   LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
   const T* a = in + (valid ? line * N : 0);
   cx<T> v[R];

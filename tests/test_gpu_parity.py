@@ -175,3 +175,23 @@ def test_rk4_beltrami_exact_decay_padded_fp32():
     z = -nu * K2 * dt
     R = 1 + z + z**2 / 2 + z**3 / 6 + z**4 / 24
     assert rel_l2(got, R**n * round32(u0)) < fp32_tol(N)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N", [18, 24, 36, 48, 54])
+def test_radix3_sizes_match_oracle(N, dtype):
+    # 2^a 3^b lengths (radix-3 and radix-6 stages); for N = 18, 36, 54 the 2/3
+    # rule's strict inequality decides the edge mode (3K < N)
+    print(f"radix3 N={N} {dtype}", flush=True)
+    rng = np.random.default_rng(N)
+    u = rng.standard_normal((3, N, N, N))
+    (got,) = run("r2c", [u], dtype)
+    assert rel_l2(got, oracle.forward(ref_input(u, dtype))) < tol(dtype, N, 1e-13)
+    uh = rng.standard_normal((3, N, N, N // 2 + 1)) + 1j * rng.standard_normal((3, N, N, N // 2 + 1))
+    (got,) = run("c2r", [uh], dtype)
+    assert rel_l2(got, oracle.inverse(ref_input(uh, dtype), N)) < tol(dtype, N, 1e-13)
+    uh = inputs.rough_random(N, N)
+    (got,) = run("rhs", [uh], dtype, nu=NU)
+    assert rel_l2(got, oracle.rhs(ref_input(uh, dtype), NU)) < tol(dtype, N)
+    (got,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1)
+    assert rel_l2(got, oracle.rk4(ref_input(uh, dtype), NU, DT, 1)) < tol(dtype, N)
