@@ -95,12 +95,40 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes);
 /* Enqueue the planned operation on stream (a hipStream_t; NULL = default).
  * in[i], out[i]: device pointers of instance i (layouts above; R2C reads
  * physical and writes spectral, C2R the reverse, RHS/RK4 spectral both).
+ * Instances must not overlap each other (in[i] == out[i] is allowed).
  * workspace: device buffer of at least the planned size.  nsteps: RK4 steps
  * (>= 0; ignored by other ops).  Asynchronous; inputs must stay valid until
  * the stream reaches the end of the call.
+ * Batches: for RHS and RK4, instances of equal N run together, each pass as
+ * one launch over all of them (the instance is a grid dimension).  The
+ * device tables of their in/out pointers live in the workspace: hot_run
+ * uploads them, and synchronises the stream, only when the pointers or the
+ * workspace differ from the previous call's; calls with the same pointers
+ * only enqueue kernels.
  * Errors: HOT_E_INVALID (null plan/pointer, nsteps < 0), HOT_E_WORKSPACE,
  * HOT_E_HIP (launch failure; the plan keeps the HIP error code). */
 int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps, void* stream);
+
+/* A captured hot_run: the whole operation (every pass of every instance and
+ * step) recorded once into a HIP graph and replayed with one launch.
+ * hot_graph_create captures on stream, which must not be the legacy default
+ * stream (NULL); the pointer tables are uploaded first, outside the capture.
+ * The graph keeps the pointers it was created with.  Per-pass profiling is
+ * not recorded inside graphs.  Errors as hot_run. */
+typedef struct hot_graph_s* hot_graph_t;
+int hot_graph_create(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
+                     void* stream, hot_graph_t* graph);
+int hot_graph_launch(hot_graph_t graph, void* stream);
+int hot_graph_destroy(hot_graph_t graph);
+
+/* Autotuner: for every distinct N of the plan and every strided pass (y
+ * inverse, y forward, x forward), time each column-width variant reps times
+ * on the workspace (which must be the planned size; the caller's arrays are
+ * not touched) and keep the fastest for later hot_run calls.  Synchronises
+ * the stream.  hot_tuned_width reports the chosen columns per block of a
+ * pass for instance i, or a negative error code. */
+int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t reps);
+int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
 
 /* Release the plan's host state (waits for its pending profiling events).
  * NULL is accepted and ignored. */

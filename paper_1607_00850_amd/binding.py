@@ -81,6 +81,16 @@ def _lib():
         lib.hot_pass_name.restype = ctypes.c_char_p
         lib.hot_pass_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
         lib.hot_pass_bytes.restype = ctypes.c_int
+        lib.hot_graph_create.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32, vp, ctypes.POINTER(vp)]
+        lib.hot_graph_create.restype = ctypes.c_int
+        lib.hot_graph_launch.argtypes = [vp, vp]
+        lib.hot_graph_launch.restype = ctypes.c_int
+        lib.hot_graph_destroy.argtypes = [vp]
+        lib.hot_graph_destroy.restype = ctypes.c_int
+        lib.hot_tune.argtypes = [vp, vp, vp, i32]
+        lib.hot_tune.restype = ctypes.c_int
+        lib.hot_tuned_width.argtypes = [vp, i32, i32]
+        lib.hot_tuned_width.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -111,16 +121,21 @@ def _ptr(x):
     return x.data_ptr()
 
 
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
 def hot_run(plan, ins, outs, workspace, nsteps=0, stream=None):
     """Enqueue the planned op.  ins/outs: sequences of device tensors (or raw
     pointers), one per instance; workspace: device tensor or pointer;
     stream: a torch.cuda.Stream, a raw hipStream_t, or None for torch's
     current stream."""
-    if stream is None:
-        import torch
-        stream = torch.cuda.current_stream().cuda_stream
-    elif not isinstance(stream, int):
-        stream = stream.cuda_stream
+    stream = _stream(stream)
     n = len(ins)
     pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
     pout = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
@@ -177,3 +192,43 @@ def pass_names():
             break
         names.append(s)
     return names
+
+
+def hot_graph_create(plan, ins, outs, workspace, nsteps=0, stream=None):
+    """Capture the whole operation into a HIP graph; returns a graph handle.
+    stream must be a non-default stream (torch.cuda.Stream or hipStream_t)."""
+    stream = _stream(stream)
+    n = len(ins)
+    pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
+    pout = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
+    g = ctypes.c_void_p()
+    rc = _lib().hot_graph_create(plan, pin, pout, _ptr(workspace), int(nsteps), stream, ctypes.byref(g))
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_graph_create", _lib().hot_last_hip_error(plan))
+    return g
+
+
+def hot_graph_launch(graph, stream=None):
+    rc = _lib().hot_graph_launch(graph, _stream(stream))
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_graph_launch")
+
+
+def hot_graph_destroy(graph):
+    _lib().hot_graph_destroy(graph)
+
+
+def hot_tune(plan, workspace, stream=None, reps=3):
+    """Autotune the strided column widths of every size in the plan."""
+    rc = _lib().hot_tune(plan, _ptr(workspace), _stream(stream), int(reps))
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_tune", _lib().hot_last_hip_error(plan))
+
+
+def hot_tuned_width(plan, instance, pass_name):
+    lib = _lib()
+    idx = pass_names().index(pass_name)
+    w = lib.hot_tuned_width(plan, int(instance), idx)
+    if w < 0:
+        raise HotError(w, "hot_tuned_width")
+    return w

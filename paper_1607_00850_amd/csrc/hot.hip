@@ -13,6 +13,25 @@
 
 namespace hot {
 
+enum Pass : int {
+  PASS_GATHER = 0,
+  PASS_X_INV_CURL,
+  PASS_Y_INV,
+  PASS_Z_CROSS,
+  PASS_Y_FWD,
+  PASS_X_FWD,
+  PASS_RK_STAGE,
+  PASS_SCATTER,
+  PASS_Z_R2C,
+  PASS_Z_C2R,
+  PASS_X_INV,
+  NUM_PASSES
+};
+
+static const char* kPassNames[NUM_PASSES] = {
+    "gather", "x_inv_curl", "y_inv", "z_cross", "y_fwd", "x_fwd", "rk_stage", "scatter", "z_r2c", "z_c2r", "x_inv",
+};
+
 template <typename T>
 static bool ops_for(int N, Ops* o) {
   const bool f = std::is_same<T, float>::value;
@@ -28,18 +47,8 @@ static bool ops_for(int N, Ops* o) {
 }
 
 // ---------------------------------------------------------------------------
-// geometry and workspace of one instance
+// geometry
 // ---------------------------------------------------------------------------
-struct Inst {
-  Geo g;      // retained geometry for the op
-  Ops ops;
-  long C;     // compact slots per component, M*M*Mzp
-  long D1;    // per component after the x pass: N*M*Mzp
-  long D2;    // per component after the y pass: N*N*Mzp
-  double lC, lD1, lD2;  // the same counts of live values (Mz instead of Mzp)
-  size_t ws;  // workspace bytes
-};
-
 // mode: 0 = 2/3 rule, 1 = all but Nyquist, 2 = every mode (plain transforms).
 // elem: bytes per complex value; the z pitch is padded to whole 128-byte rows
 // once rows are long enough for the padding to be cheap.
@@ -66,6 +75,28 @@ static Geo make_geo(int N, int mode, int elem) {
   return g;
 }
 
+static const size_t kAlign = 256;
+static inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// All instances of one N.  For the right-hand side and RK4 their workspace is
+// one region laid out batch-major: U0, U1, Acc, Nh = [B][3][C] each,
+// A1 = [B][6][D1], A2 = [B][6][D2] (then, for B > 1, the device tables of the
+// members' input and output pointers).  Plain transforms run one instance at a
+// time in a shared region.
+struct Group {
+  int N = 0;
+  Geo g{};
+  Ops ops{};
+  std::vector<int> members;  // instance indices in descriptor order
+  long C = 0, D1 = 0, D2 = 0;       // slots per component (row pitch Mzp)
+  double lC = 0, lD1 = 0, lD2 = 0;  // live values per component (Mz)
+  size_t off = 0;                   // byte offset of the group's region
+  size_t oU0 = 0, oU1 = 0, oAcc = 0, oNh = 0, oA1 = 0, oA2 = 0, oTab = 0;
+  size_t bytes = 0;
+  int variant[NUM_PASSES];  // strided column-width variant per pass (autotuned)
+  int B() const { return (int)members.size(); }
+};
+
 }  // namespace hot
 
 using namespace hot;
@@ -74,9 +105,14 @@ struct hot_plan_s {
   int op, dtype, dealias;
   double nu, dt;
   size_t elem;  // bytes per complex element
-  std::vector<Inst> inst;
+  int batch;
+  std::vector<int> n;
+  std::vector<Group> groups;
   size_t ws_bytes;
   int last_hip;
+  // device pointer tables: what was last uploaded, and where
+  std::vector<const void*> tab_in, tab_out;
+  void* tab_ws = nullptr;
   // profiling
   bool prof;
   struct Rec {
@@ -87,8 +123,10 @@ struct hot_plan_s {
   std::vector<hipEvent_t> pool;
 };
 
-static const size_t kAlign = 256;
-static inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+struct hot_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -126,34 +164,65 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
   p->nu = d->nu;
   p->dt = d->dt;
   p->elem = d->dtype == HOT_F64 ? 16 : 8;
+  p->batch = d->batch;
+  p->n.assign(d->n, d->n + d->batch);
   p->last_hip = 0;
   p->prof = false;
   p->ws_bytes = 0;
   const bool plain = d->op == HOT_OP_R2C || d->op == HOT_OP_C2R;
+  // group the instances by N, in order of first appearance
   for (int i = 0; i < d->batch; ++i) {
-    Inst I{};
     const int N = d->n[i];
-    const bool ok = d->dtype == HOT_F64 ? ops_for<double>(N, &I.ops) : ops_for<float>(N, &I.ops);
-    if (!ok) {
+    Group* gp = nullptr;
+    for (auto& G : p->groups)
+      if (G.N == N) gp = &G;
+    if (!gp) {
+      Group G;
+      G.N = N;
+      const bool ok = d->dtype == HOT_F64 ? ops_for<double>(N, &G.ops) : ops_for<float>(N, &G.ops);
+      if (!ok) {
+        delete p;
+        return HOT_E_UNSUPPORTED;
+      }
+      G.g = make_geo(N, plain ? 2 : d->dealias, (int)p->elem);
+      for (int k = 0; k < NUM_PASSES; ++k) G.variant[k] = 1;
+      p->groups.push_back(G);
+      gp = &p->groups.back();
+    }
+    gp->members.push_back(i);
+  }
+  size_t off = 0;
+  for (auto& G : p->groups) {
+    if (G.B() > 65535) {  // one grid dimension per batch
       delete p;
       return HOT_E_UNSUPPORTED;
     }
-    I.g = make_geo(N, plain ? 2 : d->dealias, (int)p->elem);
-    I.C = (long)I.g.M * I.g.M * I.g.Mzp;
-    I.D1 = (long)N * I.g.M * I.g.Mzp;
-    I.D2 = (long)N * N * I.g.Mzp;
-    I.lC = (double)I.g.M * I.g.M * I.g.Mz;
-    I.lD1 = (double)N * I.g.M * I.g.Mz;
-    I.lD2 = (double)N * N * I.g.Mz;
+    const long N = G.N;
+    G.C = (long)G.g.M * G.g.M * G.g.Mzp;
+    G.D1 = N * G.g.M * G.g.Mzp;
+    G.D2 = N * N * G.g.Mzp;
+    G.lC = (double)G.g.M * G.g.M * G.g.Mz;
+    G.lD1 = (double)N * G.g.M * G.g.Mz;
+    G.lD2 = (double)N * N * G.g.Mz;
+    const size_t e = p->elem, B = (size_t)G.B();
     if (plain) {
-      I.ws = 2 * align_up(3 * (size_t)I.D2 * p->elem);
-    } else {
-      I.ws = 4 * align_up(3 * (size_t)I.C * p->elem) + align_up(6 * (size_t)I.D1 * p->elem) +
-             align_up(6 * (size_t)I.D2 * p->elem);
+      G.bytes = 2 * align_up(3 * (size_t)G.D2 * e);  // shared by all instances, one at a time
+      if (G.bytes > p->ws_bytes) p->ws_bytes = G.bytes;
+      continue;
     }
-    if (I.ws > p->ws_bytes) p->ws_bytes = I.ws;
-    p->inst.push_back(I);
+    const size_t sC = align_up(B * 3 * (size_t)G.C * e);
+    G.off = off;
+    G.oU0 = 0;
+    G.oU1 = sC;
+    G.oAcc = 2 * sC;
+    G.oNh = 3 * sC;
+    G.oA1 = 4 * sC;
+    G.oA2 = G.oA1 + align_up(B * 6 * (size_t)G.D1 * e);
+    G.oTab = G.oA2 + align_up(B * 6 * (size_t)G.D2 * e);
+    G.bytes = G.oTab + (B > 1 ? align_up(2 * B * sizeof(void*)) : 0);
+    off += G.bytes;
   }
+  if (!plain) p->ws_bytes = off;
   *out = p;
   *workspace_bytes = p->ws_bytes;
   return HOT_OK;
@@ -209,8 +278,11 @@ const char* hot_pass_name(int32_t pass) {
 }
 
 int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) {
-  if (!p || !bytes || instance < 0 || instance >= (int)p->inst.size()) return HOT_E_INVALID;
-  const Inst& I = p->inst[instance];
+  if (!p || !bytes || instance < 0 || instance >= p->batch) return HOT_E_INVALID;
+  const Group* Gp = nullptr;
+  for (const auto& G : p->groups)
+    if (G.N == p->n[instance]) Gp = &G;
+  const Group& I = *Gp;
   const double e = (double)p->elem, C = I.lC, D1 = I.lD1, D2 = I.lD2;
   const double N = I.g.N, canon = 3.0 * N * N * (N / 2 + 1);
   double b = 0;
@@ -241,6 +313,7 @@ namespace {
 struct Runner {
   hot_plan_s* p;
   hipStream_t s;
+  bool record = true;  // profiling events (off while a graph is captured)
   int rc = HOT_OK;
 
   hipEvent_t ev() {
@@ -258,13 +331,14 @@ struct Runner {
   void pass(int id, F&& launch) {
     if (rc != HOT_OK) return;
     hipEvent_t a = nullptr, b = nullptr;
-    if (p->prof) {
+    const bool prof = p->prof && record;
+    if (prof) {
       a = ev();
       b = ev();
       if (a && b) (void)hipEventRecord(a, s);
     }
     hipError_t e = launch();
-    if (p->prof && a && b) {
+    if (prof && a && b) {
       (void)hipEventRecord(b, s);
       p->recs.push_back({id, a, b});
     }
@@ -275,92 +349,291 @@ struct Runner {
   }
 };
 
-// One evaluation of the right-hand side from compact state `src` into Nh.
-void rhs_passes(Runner& r, const Inst& I, const char* src, char* A1, char* A2, char* Nh) {
-  const Geo& g = I.g;
+struct GroupPtrs {
+  char *U0, *U1, *Acc, *Nh, *A1, *A2;
+  const void* const* in_tab;
+  void* const* out_tab;
+};
+
+GroupPtrs group_ptrs(const Group& G, void* workspace) {
+  char* base = (char*)workspace + G.off;
+  GroupPtrs q;
+  q.U0 = base + G.oU0;
+  q.U1 = base + G.oU1;
+  q.Acc = base + G.oAcc;
+  q.Nh = base + G.oNh;
+  q.A1 = base + G.oA1;
+  q.A2 = base + G.oA2;
+  q.in_tab = G.B() > 1 ? (const void* const*)(base + G.oTab) : nullptr;
+  q.out_tab = G.B() > 1 ? (void* const*)(base + G.oTab + G.B() * sizeof(void*)) : nullptr;
+  return q;
+}
+
+// One evaluation of the right-hand side for every instance of a group, from
+// compact state `src` into Nh.
+void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src) {
+  const Geo& g = G.g;
   const long N = g.N, M = g.M, P = g.Mzp;
-  const Ops& o = I.ops;
-  r.pass(PASS_X_INV_CURL, [&] { return o.x_inv_curl(r.s, src, I.C, A1, I.D1, g); });
+  const Ops& o = G.ops;
+  const int nb = G.B();
+  const long isU = 3 * G.C, isA1 = 6 * G.D1, isA2 = 6 * G.D2;
+  r.pass(PASS_X_INV_CURL, [&] { return o.x_inv_curl(r.s, src, G.C, isU, q.A1, G.D1, isA1, nb, g); });
   // y inverse: 6 components, batch over x, rows ky (compact) -> y (all N)
   r.pass(PASS_Y_INV, [&] {
-    return o.strided(r.s, +1, true, false, A1, A2, N * P, P, P, P, M * P, N * P, I.D1, I.D2, 6, g);
+    return o.strided(r.s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1,
+                     G.D2, 6, isA1, isA2, nb, g);
   });
-  r.pass(PASS_Z_CROSS, [&] { return o.z_cross(r.s, A2, I.D2, N * N, g); });
+  r.pass(PASS_Z_CROSS, [&] { return o.z_cross(r.s, q.A2, G.D2, isA2, N * N, nb, g); });
   // y forward: 3 components, y (all N) -> ky (compact)
   r.pass(PASS_Y_FWD, [&] {
-    return o.strided(r.s, -1, false, true, A2, A1, N * P, P, P, P, N * P, M * P, I.D2, I.D1, 3, g);
+    return o.strided(r.s, G.variant[PASS_Y_FWD], -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2,
+                     G.D1, 3, isA2, isA1, nb, g);
   });
   // x forward: rows x (all N) -> kx (compact), columns (ky, kz)
   r.pass(PASS_X_FWD, [&] {
     const long Q = M * P;
-    return o.strided(r.s, -1, false, true, A1, Nh, Q, Q, Q, Q, 0, 0, I.D1, I.C, 3, g);
+    return o.strided(r.s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3, isA1,
+                     isU, nb, g);
   });
+}
+
+// Upload the members' input/output pointer tables of every batched group
+// into the workspace when they differ from the last upload (synchronises the
+// stream when it does).
+int ensure_tables(hot_plan_s* p, void* const* in, void* const* out, void* workspace, hipStream_t s) {
+  bool need = false;
+  for (const auto& G : p->groups) need = need || G.B() > 1;
+  if (!need) return HOT_OK;
+  bool same = p->tab_ws == workspace && (int)p->tab_in.size() == p->batch;
+  for (int i = 0; same && i < p->batch; ++i) same = p->tab_in[i] == in[i] && p->tab_out[i] == out[i];
+  if (same) return HOT_OK;
+  for (const auto& G : p->groups) {
+    if (G.B() < 2) continue;
+    std::vector<const void*> host(2 * G.B());
+    for (int m = 0; m < G.B(); ++m) {
+      host[m] = in[G.members[m]];
+      host[G.B() + m] = out[G.members[m]];
+    }
+    char* dst = (char*)workspace + G.off + G.oTab;
+    hipError_t e = hipMemcpyAsync(dst, host.data(), host.size() * sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      p->last_hip = (int)e;
+      return HOT_E_HIP;
+    }
+  }
+  p->tab_in.assign(in, in + p->batch);
+  p->tab_out.assign(out, out + p->batch);
+  p->tab_ws = workspace;
+  return HOT_OK;
+}
+
+int check_run_args(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps) {
+  if (!p || !in || !out || nsteps < 0) return HOT_E_INVALID;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
+  for (int i = 0; i < p->batch; ++i) {
+    if (!in[i] || !out[i]) return HOT_E_INVALID;
+    if (((uintptr_t)in[i] % kAlign) != 0 || ((uintptr_t)out[i] % kAlign) != 0) return HOT_E_INVALID;
+  }
+  return HOT_OK;
+}
+
+// Enqueue the whole operation (the pointer tables are already in place).
+int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t stream,
+            bool record) {
+  Runner r{p, stream, record};
+  const size_t e = p->elem;
+  if (p->op == HOT_OP_R2C || p->op == HOT_OP_C2R) {
+    for (const auto& G : p->groups) {
+      const Geo& g = G.g;
+      const Ops& o = G.ops;
+      const long N = g.N, Nh = g.Mz, D2 = G.D2;
+      char* Z1 = (char*)workspace;
+      char* Z2 = Z1 + align_up(3 * (size_t)G.D2 * e);
+      for (int i : G.members) {
+        if (r.rc != HOT_OK) break;
+        if (p->op == HOT_OP_R2C) {
+          r.pass(PASS_Z_R2C, [&] { return o.z_r2c(r.s, in[i], Z1, 3 * N * N, g); });
+          r.pass(PASS_Y_FWD, [&] {
+            return o.strided(r.s, 1, -1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, 0, 0,
+                             1, g);
+          });
+          r.pass(PASS_X_FWD, [&] {
+            const long Q = N * Nh;
+            return o.strided(r.s, 1, -1, false, false, Z2, out[i], Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 1, g);
+          });
+        } else {
+          r.pass(PASS_X_INV, [&] {
+            const long Q = N * Nh;
+            return o.strided(r.s, 1, +1, false, false, in[i], Z1, Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 1, g);
+          });
+          r.pass(PASS_Y_INV, [&] {
+            return o.strided(r.s, 1, +1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, 0, 0,
+                             1, g);
+          });
+          r.pass(PASS_Z_C2R, [&] { return o.z_c2r(r.s, Z2, out[i], 3 * N * N, g); });
+        }
+      }
+    }
+    return r.rc;
+  }
+  // right-hand side / RK4: group by group (a small group's working set can
+  // stay in the device's last-level cache between its passes)
+  for (const auto& G : p->groups) {
+    if (r.rc != HOT_OK) break;
+    const GroupPtrs q = group_ptrs(G, workspace);
+    const Ops& o = G.ops;
+    const Geo& g = G.g;
+    const int nb = G.B();
+    const long isU = 3 * G.C;
+    const void* in0 = in[G.members[0]];
+    void* out0 = out[G.members[0]];
+    r.pass(PASS_GATHER, [&] { return o.gather(r.s, in0, q.in_tab, q.U0, G.C, isU, nb, g); });
+    if (p->op == HOT_OP_RHS) {
+      rhs_passes(r, G, q, q.U0);
+      r.pass(PASS_RK_STAGE, [&] { return o.rk_stage(r.s, q.Nh, q.U0, q.U1, q.Acc, G.C, isU, nb, g, 4, p->nu, p->dt); });
+      r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.Acc, out0, q.out_tab, G.C, isU, nb, g); });
+    } else {
+      for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
+        for (int st = 0; st < 4; ++st) {
+          rhs_passes(r, G, q, st == 0 ? q.U0 : q.U1);
+          r.pass(PASS_RK_STAGE,
+                 [&] { return o.rk_stage(r.s, q.Nh, q.U0, q.U1, q.Acc, G.C, isU, nb, g, st, p->nu, p->dt); });
+        }
+      }
+      r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.U0, out0, q.out_tab, G.C, isU, nb, g); });
+    }
+  }
+  return r.rc;
 }
 
 }  // namespace
 
 extern "C" int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
                        void* stream) {
-  if (!p || !in || !out || nsteps < 0) return HOT_E_INVALID;
-  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
-  for (size_t i = 0; i < p->inst.size(); ++i) {
-    if (!in[i] || !out[i]) return HOT_E_INVALID;
-    if (((uintptr_t)in[i] % kAlign) != 0 || ((uintptr_t)out[i] % kAlign) != 0) return HOT_E_INVALID;
+  int rc = check_run_args(p, in, out, workspace, nsteps);
+  if (rc != HOT_OK) return rc;
+  rc = ensure_tables(p, in, out, workspace, (hipStream_t)stream);
+  if (rc != HOT_OK) return rc;
+  return enqueue(p, in, out, workspace, nsteps, (hipStream_t)stream, true);
+}
+
+extern "C" int hot_graph_create(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
+                                void* stream, hot_graph_t* graph) {
+  if (graph) *graph = nullptr;
+  if (!graph || !stream) return HOT_E_INVALID;  // the legacy default stream cannot be captured
+  int rc = check_run_args(p, in, out, workspace, nsteps);
+  if (rc != HOT_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = ensure_tables(p, in, out, workspace, s);
+  if (rc != HOT_OK) return rc;
+  hot_graph_s* G = new (std::nothrow) hot_graph_s();
+  if (!G) return HOT_E_INVALID;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = enqueue(p, in, out, workspace, nsteps, s, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    G->graph = g;
+    if (rc == HOT_OK && e2 != hipSuccess) e = e2;
+    if (rc == HOT_OK && e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
   }
-  Runner r{p, (hipStream_t)stream};
-  char* ws = (char*)workspace;
-  const size_t e = p->elem;
-  for (size_t i = 0; i < p->inst.size() && r.rc == HOT_OK; ++i) {
-    const Inst& I = p->inst[i];
-    const Geo& g = I.g;
-    const Ops& o = I.ops;
-    const long N = g.N;
-    if (p->op == HOT_OP_R2C || p->op == HOT_OP_C2R) {
-      char* Z1 = ws;
-      char* Z2 = ws + align_up(3 * (size_t)I.D2 * e);
-      const long Nh = g.Mz, D2 = I.D2;
-      if (p->op == HOT_OP_R2C) {
-        r.pass(PASS_Z_R2C, [&] { return o.z_r2c(r.s, in[i], Z1, 3 * N * N, g); });
-        r.pass(PASS_Y_FWD, [&] {
-          return o.strided(r.s, -1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, g);
-        });
-        r.pass(PASS_X_FWD, [&] {
-          const long Q = N * Nh;
-          return o.strided(r.s, -1, false, false, Z2, out[i], Q, Q, Q, Q, 0, 0, D2, D2, 3, g);
-        });
-      } else {
-        r.pass(PASS_X_INV, [&] {
-          const long Q = N * Nh;
-          return o.strided(r.s, +1, false, false, in[i], Z1, Q, Q, Q, Q, 0, 0, D2, D2, 3, g);
-        });
-        r.pass(PASS_Y_INV, [&] {
-          return o.strided(r.s, +1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, g);
-        });
-        r.pass(PASS_Z_C2R, [&] { return o.z_c2r(r.s, Z2, out[i], 3 * N * N, g); });
-      }
-      continue;
-    }
-    const size_t sC = align_up(3 * (size_t)I.C * e);
-    char* U0 = ws;
-    char* U1 = U0 + sC;
-    char* Acc = U1 + sC;
-    char* Nh = Acc + sC;
-    char* A1 = Nh + sC;
-    char* A2 = A1 + align_up(6 * (size_t)I.D1 * e);
-    r.pass(PASS_GATHER, [&] { return o.gather(r.s, in[i], U0, I.C, g); });
-    if (p->op == HOT_OP_RHS) {
-      rhs_passes(r, I, U0, A1, A2, Nh);
-      r.pass(PASS_RK_STAGE, [&] { return o.rk_stage(r.s, Nh, U0, U1, Acc, I.C, g, 4, p->nu, p->dt); });
-      r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, Acc, out[i], I.C, g); });
-    } else {
-      for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
-        for (int st = 0; st < 4; ++st) {
-          rhs_passes(r, I, st == 0 ? U0 : U1, A1, A2, Nh);
-          r.pass(PASS_RK_STAGE, [&] { return o.rk_stage(r.s, Nh, U0, U1, Acc, I.C, g, st, p->nu, p->dt); });
+  if (rc == HOT_OK && e != hipSuccess) {
+    p->last_hip = (int)e;
+    rc = HOT_E_HIP;
+  }
+  if (rc != HOT_OK) {
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return rc;
+  }
+  *graph = G;
+  return HOT_OK;
+}
+
+extern "C" int hot_graph_launch(hot_graph_t graph, void* stream) {
+  if (!graph || !graph->exec) return HOT_E_INVALID;
+  return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? HOT_OK : HOT_E_HIP;
+}
+
+extern "C" int hot_graph_destroy(hot_graph_t graph) {
+  if (!graph) return HOT_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return HOT_OK;
+}
+
+// Autotuner: for every group and strided pass, time each column-width
+// variant on the workspace (the passes only read and write workspace
+// buffers, so the caller's data is untouched) and keep the fastest.
+extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t reps) {
+  if (!p || reps < 1) return HOT_E_INVALID;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
+  if (p->op != HOT_OP_RHS && p->op != HOT_OP_RK4) return HOT_OK;  // nothing to tune
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HOT_E_HIP;
+  int rc = HOT_OK;
+  const bool was_prof = p->prof;
+  p->prof = false;
+  for (auto& G : p->groups) {
+    const GroupPtrs q = group_ptrs(G, workspace);
+    const int pass_ids[3] = {PASS_Y_INV, PASS_Y_FWD, PASS_X_FWD};
+    for (int pid : pass_ids) {
+      float best = 1e30f;
+      int best_v = 1;
+      for (int v = 0; v < G.ops.strided_variants && rc == HOT_OK; ++v) {
+        if (v != 1 && G.ops.strided_width[v] == G.ops.strided_width[1]) continue;  // same kernel
+        G.variant[pid] = v;
+        float t = 0.f;
+        for (int rep = 0; rep <= reps && rc == HOT_OK; ++rep) {
+          Runner r{p, s, false};
+          if (rep == 1) (void)hipEventRecord(a, s);
+          // one launch of just this pass
+          const Geo& g = G.g;
+          const long N = g.N, M = g.M, P = g.Mzp;
+          const long isA1 = 6 * G.D1, isA2 = 6 * G.D2, isU = 3 * G.C;
+          r.pass(pid, [&] {
+            if (pid == PASS_Y_INV)
+              return G.ops.strided(s, v, +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2, 6,
+                                   isA1, isA2, G.B(), g);
+            if (pid == PASS_Y_FWD)
+              return G.ops.strided(s, v, -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1, 3,
+                                   isA2, isA1, G.B(), g);
+            const long Q = M * P;
+            return G.ops.strided(s, v, -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3, isA1, isU, G.B(),
+                                 g);
+          });
+          rc = r.rc;
+        }
+        if (rc != HOT_OK) break;
+        hipError_t e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+        if (e != hipSuccess) {
+          p->last_hip = (int)e;
+          rc = HOT_E_HIP;
+          break;
+        }
+        if (t < best) {
+          best = t;
+          best_v = v;
         }
       }
-      r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, U0, out[i], I.C, g); });
+      G.variant[pid] = best_v;
     }
   }
-  return r.rc;
+  p->prof = was_prof;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
+  if (!p || instance < 0 || instance >= p->batch || pass < 0 || pass >= NUM_PASSES) return HOT_E_INVALID;
+  for (const auto& G : p->groups)
+    if (G.N == p->n[instance]) return G.ops.strided_width[G.variant[pass]];
+  return HOT_E_INVALID;
 }

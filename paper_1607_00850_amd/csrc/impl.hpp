@@ -35,23 +35,14 @@ template <int N>
 struct LPz {
   using P = typename LP<N>::P;
 };
-#ifndef HOT_Z1024_R
-#define HOT_Z1024_R 16
-#endif
-#if HOT_Z1024_R == 8
-template <> struct LPz<1024> { using P = LinePlan<1024, 8, 8, 8, 8, 2>; };
-#endif
 
 // Columns per block of a strided pass: at least one 128-byte segment per row
 // (16 FP32 / 8 FP64 complex values), more while the LDS tile stays within
 // 64 KB; never above 1024 threads or a 128 KB tile.
-#ifndef HOT_SEG_BYTES
-#define HOT_SEG_BYTES 128
-#endif
 template <typename T, int N>
 constexpr int cols_per_block() {
   constexpr int tl = LP<N>::P::Tl;
-  constexpr int seg = int(HOT_SEG_BYTES / sizeof(cx<T>));
+  constexpr int seg = int(128 / sizeof(cx<T>));
   int w = int(65536 / (N * sizeof(cx<T>)));
   if (w > 64) w = 64;
   if (w < seg) w = seg;
@@ -59,27 +50,26 @@ constexpr int cols_per_block() {
   return w;
 }
 
-enum Pass : int {
-  PASS_GATHER = 0,
-  PASS_X_INV_CURL,
-  PASS_Y_INV,
-  PASS_Z_CROSS,
-  PASS_Y_FWD,
-  PASS_X_FWD,
-  PASS_RK_STAGE,
-  PASS_SCATTER,
-  PASS_Z_R2C,
-  PASS_Z_C2R,
-  PASS_X_INV,
-  NUM_PASSES
-};
-
-static const char* kPassNames[NUM_PASSES] = {
-    "gather", "x_inv_curl", "y_inv", "z_cross", "y_fwd", "x_fwd", "rk_stage", "scatter", "z_r2c", "z_c2r", "x_inv",
-};
-
-struct Launch {
-  hipStream_t s;
+// Kernel launchers for one (element type, N).  Every function enqueues one
+// kernel on the stream for nb instances of a batch (instance strides is*)
+// and returns hipGetLastError().
+struct Ops {
+  hipError_t (*strided)(hipStream_t, int variant, int dir, bool inc, bool outc, const void* in, void* out,
+                        long ncols, long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in,
+                        long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo&);
+  hipError_t (*x_inv_curl)(hipStream_t, const void* U, long csU, long isU, void* A, long csA, long isA, int nb,
+                           const Geo&);
+  hipError_t (*z_cross)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&);
+  hipError_t (*z_c2r)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
+  hipError_t (*z_r2c)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
+  hipError_t (*rk_stage)(hipStream_t, const void* Nh, void* U0, void* U1, void* Acc, long C, long is, int nb,
+                         const Geo&, int mode, double nu, double dt);
+  hipError_t (*gather)(hipStream_t, const void* in0, const void* const* in_tab, void* out, long C, long is, int nb,
+                       const Geo&);
+  hipError_t (*scatter)(hipStream_t, const void* in, void* out0, void* const* out_tab, long C, long is, int nb,
+                        const Geo&);
+  int strided_variants;       // number of column widths the autotuner may pick from
+  int strided_width[3];       // columns per block of each variant
 };
 
 static inline unsigned grid_1d(long work, int block) {
@@ -90,42 +80,36 @@ static inline unsigned grid_1d(long work, int block) {
   return (unsigned)g;
 }
 
-// Kernel launchers for one (element type, N).  Every function enqueues one
-// kernel on the stream and returns hipGetLastError().
-struct Ops {
-  hipError_t (*strided)(hipStream_t, int dir, bool inc, bool outc, const void* in, void* out, long ncols, long Qp,
-                        long ld_in, long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, int ncomp,
-                        const Geo&);
-  hipError_t (*x_inv_curl)(hipStream_t, const void* U, long csU, void* A, long csA, const Geo&);
-  hipError_t (*z_cross)(hipStream_t, void* A, long csA, long nlines, const Geo&);
-  hipError_t (*z_c2r)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
-  hipError_t (*z_r2c)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
-  hipError_t (*rk_stage)(hipStream_t, const void* Nh, void* U0, void* U1, void* Acc, long C, const Geo&, int mode,
-                         double nu, double dt);
-  hipError_t (*gather)(hipStream_t, const void* in, void* out, long C, const Geo&);
-  hipError_t (*scatter)(hipStream_t, const void* in, void* out, long C, const Geo&);
-};
-
 template <typename T, int N>
 struct Impl {
   using P = typename LP<N>::P;
   static constexpr int W = cols_per_block<T, N>();
   static constexpr int Tl = P::Tl;
 
-  template <int DIR, bool IC, bool OC>
-  static void go(hipStream_t s, const void* in, void* out, long ncols, long Qp, long ld_in, long ld_out, long bs_in,
-                 long bs_out, long cs_in, long cs_out, int ncomp, const Geo& g) {
-    constexpr int pair = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
-    const long ntiles = (ncols + W - 1) / W;
-    const long group = 8L * pair;
-    dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)ncomp);
-    hipLaunchKernelGGL((k_strided<T, P, DIR, W, IC, OC>), grid, dim3(W * Tl), 0, s, (const cx<T>*)in, (cx<T>*)out,
-                       ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, g);
+  // strided column widths the autotuner chooses from: W/2, W, 2W when the
+  // block stays within 1024 threads, at least one wave and 160 KB of LDS
+  static constexpr bool fits(int w) {
+    return w >= 1 && w * Tl <= 1024 && w * Tl >= 64 && (long)N * w * (long)sizeof(cx<T>) <= 163840;
   }
-  static hipError_t strided(hipStream_t s, int dir, bool inc, bool outc, const void* in, void* out, long ncols,
-                            long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in, long cs_out,
-                            int ncomp, const Geo& g) {
-#define HOT_GO(D, I, O) go<D, I, O>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, g)
+  static constexpr int WV0 = fits(W / 2) ? W / 2 : W;
+  static constexpr int WV2 = fits(2 * W) ? 2 * W : W;
+
+  template <int WW, int DIR, bool IC, bool OC>
+  static void go(hipStream_t s, const void* in, void* out, long ncols, long Qp, long ld_in, long ld_out, long bs_in,
+                 long bs_out, long cs_in, long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo& g) {
+    constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
+    const long ntiles = (ncols + WW - 1) / WW;
+    const long group = 8L * pair;
+    dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)ncomp, (unsigned)nb);
+    hipLaunchKernelGGL((k_strided<T, P, DIR, WW, IC, OC>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)in, (cx<T>*)out,
+                       ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in, is_out, g);
+  }
+  template <int WW>
+  static hipError_t strided_w(hipStream_t s, int dir, bool inc, bool outc, const void* in, void* out, long ncols,
+                              long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in, long cs_out,
+                              int ncomp, long is_in, long is_out, int nb, const Geo& g) {
+#define HOT_GO(D, I, O) \
+  go<WW, D, I, O>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, is_in, is_out, nb, g)
     if (dir > 0) {
       if (inc && !outc) HOT_GO(+1, true, false);
       else if (!inc && !outc) HOT_GO(+1, false, false);
@@ -138,27 +122,41 @@ struct Impl {
 #undef HOT_GO
     return hipGetLastError();
   }
-  static hipError_t x_inv_curl(hipStream_t s, const void* U, long csU, void* A, long csA, const Geo& g) {
+  static hipError_t strided(hipStream_t s, int variant, int dir, bool inc, bool outc, const void* in, void* out,
+                            long ncols, long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in,
+                            long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo& g) {
+    switch (variant) {
+      case 0: return strided_w<WV0>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
+                                    cs_out, ncomp, is_in, is_out, nb, g);
+      case 2: return strided_w<WV2>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
+                                    cs_out, ncomp, is_in, is_out, nb, g);
+      default: return strided_w<W>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
+                                   cs_out, ncomp, is_in, is_out, nb, g);
+    }
+  }
+  static hipError_t x_inv_curl(hipStream_t s, const void* U, long csU, long isU, void* A, long csA, long isA, int nb,
+                               const Geo& g) {
     const long Q = (long)g.M * g.Mzp;
     const int ntiles = (int)((Q + W - 1) / W);
     constexpr int pair = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
     const unsigned nblk = 8u * 6u * (unsigned)((ntiles + 8 * pair - 1) / (8 * pair) * pair);
-    hipLaunchKernelGGL((k_x_inv_curl<T, P, W>), dim3(nblk), dim3(W * Tl), 0, s, (const cx<T>*)U, csU, (cx<T>*)A,
-                       csA, ntiles, g);
+    hipLaunchKernelGGL((k_x_inv_curl<T, P, W>), dim3(nblk, (unsigned)nb), dim3(W * Tl), 0, s, (const cx<T>*)U, csU,
+                       isU, (cx<T>*)A, csA, isA, ntiles, g);
     return hipGetLastError();
   }
   using PZ = typename LPz<N>::P;
   static constexpr int lines_per_block() { return ZShape<PZ>::LPB; }
-  static hipError_t z_cross(hipStream_t s, void* A, long csA, long nlines, const Geo& g) {
+  static hipError_t z_cross(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const double n3 = double(N) * N * N;
     const T scale = T(1.0 / (n3 * n3));
+    const dim3 grid(nblk, (unsigned)nb);
     // coefficients per lane: the 2/3-rule count, or the all-but-Nyquist one
     constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
     if (g.Mz <= KL23 * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23>), dim3(nblk), dim3(256), 0, s, (cx<T>*)A, csA, nlines, g, scale);
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale);
     else if (g.Mz <= KLall * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall>), dim3(nblk), dim3(256), 0, s, (cx<T>*)A, csA, nlines, g, scale);
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
@@ -174,24 +172,27 @@ struct Impl {
     hipLaunchKernelGGL((k_z_r2c<T, PZ>), dim3(nblk), dim3(256), 0, s, (const T*)in, (cx<T>*)out, nlines, g);
     return hipGetLastError();
   }
-  static hipError_t rk_stage(hipStream_t s, const void* Nh, void* U0, void* U1, void* Acc, long C, const Geo& g,
-                             int mode, double nu, double dt) {
-    hipLaunchKernelGGL((k_rk_stage<T>), dim3(grid_1d(C, 256)), dim3(256), 0, s, (const cx<T>*)Nh, (cx<T>*)U0,
-                       (cx<T>*)U1, (cx<T>*)Acc, C, g, mode, T(nu), T(dt));
+  static hipError_t rk_stage(hipStream_t s, const void* Nh, void* U0, void* U1, void* Acc, long C, long is, int nb,
+                             const Geo& g, int mode, double nu, double dt) {
+    hipLaunchKernelGGL((k_rk_stage<T>), dim3(grid_1d(C, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)Nh,
+                       (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, is, g, mode, T(nu), T(dt));
     return hipGetLastError();
   }
-  static hipError_t gather(hipStream_t s, const void* in, void* out, long C, const Geo& g) {
-    hipLaunchKernelGGL((k_gather<T>), dim3(grid_1d(3 * C, 256)), dim3(256), 0, s, (const cx<T>*)in, (cx<T>*)out, C, g);
+  static hipError_t gather(hipStream_t s, const void* in0, const void* const* in_tab, void* out, long C, long is,
+                           int nb, const Geo& g) {
+    hipLaunchKernelGGL((k_gather<T>), dim3(grid_1d(3 * C, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in0,
+                       (const cx<T>* const*)in_tab, (cx<T>*)out, C, is, g);
     return hipGetLastError();
   }
-  static hipError_t scatter(hipStream_t s, const void* in, void* out, long C, const Geo& g) {
+  static hipError_t scatter(hipStream_t s, const void* in, void* out0, void* const* out_tab, long C, long is, int nb,
+                            const Geo& g) {
     const long total = 3L * g.N * g.N * (g.N / 2 + 1);
-    hipLaunchKernelGGL((k_scatter<T>), dim3(grid_1d(total, 256)), dim3(256), 0, s, (const cx<T>*)in, (cx<T>*)out, C,
-                       g);
+    hipLaunchKernelGGL((k_scatter<T>), dim3(grid_1d(total, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in,
+                       (cx<T>*)out0, (cx<T>* const*)out_tab, C, is, g);
     return hipGetLastError();
   }
   static Ops ops() {
-    return Ops{&strided, &x_inv_curl, &z_cross, &z_c2r, &z_r2c, &rk_stage, &gather, &scatter};
+    return Ops{&strided, &x_inv_curl, &z_cross, &z_c2r, &z_r2c, &rk_stage, &gather, &scatter, 3, {WV0, W, WV2}};
   }
 };
 

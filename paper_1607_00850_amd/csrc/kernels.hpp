@@ -136,11 +136,14 @@ __device__ __forceinline__ long tile_of_block(long b) {
 // The array is a batch of [rows][Qp] blocks (global column gc = b*Qp + q);
 // a column is live iff (q mod Mzp) < Mz (the rest is row padding).
 // IN_C / OUT_C: rows are compact (retained positions only) or all N.
+// blockIdx.y selects the component (stride cs_*), blockIdx.z the instance of
+// a batch of equal-size instances (stride is_*).
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int DIR, int W, bool IN_C, bool OUT_C>
 __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                          long ncols, long Qp, long ld_in, long ld_out, long bs_in,
-                                                         long bs_out, long cs_in, long cs_out, Geo g) {
+                                                         long bs_out, long cs_in, long cs_out, long is_in,
+                                                         long is_out, Geo g) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
@@ -152,8 +155,9 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
   const long b = gc / Qp;
   const long q = gc - b * Qp;
   const bool valid = gc < ncols && (int)(q % g.Mzp) < g.Mz;
-  const long ib = valid ? blockIdx.y * cs_in + b * bs_in + q : 0;
-  const long ob = valid ? blockIdx.y * cs_out + b * bs_out + q : 0;
+  // blockIdx.y: component, blockIdx.z: instance of a batch
+  const long ib = valid ? blockIdx.z * is_in + blockIdx.y * cs_in + b * bs_in + q : 0;
+  const long ob = valid ? blockIdx.z * is_out + blockIdx.y * cs_out + b * bs_out + q : 0;
   cx<T> v[R];
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
@@ -184,12 +188,12 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
 // components (u_x, u_y, u_z, w_x, w_y, w_z).  One block per (tile, output
 // component); the 6 components of a tile go to blocks with equal b mod 8
 // (one XCD) so that their shared input rows are read from HBM once and then
-// served by that XCD's L2.
+// served by that XCD's L2.  blockIdx.y is the instance of a batch.
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int W>
-__global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restrict__ U, long csU,
-                                                            cx<T>* __restrict__ A, long csA, int ntiles,
-                                                            Geo g) {
+__global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restrict__ U, long csU, long isU,
+                                                            cx<T>* __restrict__ A, long csA, long isA,
+                                                            int ntiles, Geo g) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
@@ -209,6 +213,8 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
   const T ky = T(kwave(cpos(valid ? iy : 0, g), N));
   const T kzf = T(kz);
   const long qq = valid ? q : 0;
+  U += blockIdx.y * isU;  // instance of a batch
+  A += blockIdx.y * isA;
   const cx<T>* u0 = U + qq;
   const cx<T>* u1 = U + csU + qq;
   const cx<T>* u2 = U + 2 * csU + qq;
@@ -306,7 +312,8 @@ __device__ __forceinline__ void stage_twiddles(cx<T>* tws) {
 // next component pair are issued before the current pair's FFT.
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int KL>
-__global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA, long nlines, Geo g, T scale) {
+__global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA, long isA, long nlines, Geo g,
+                                                 T scale) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
   constexpr int LS = Plan::line_slots;
@@ -323,6 +330,7 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
   const TwTab<T> tw{tws};
   const long base = valid ? line * g.Mzp : 0;
+  A += blockIdx.y * isA;  // instance of a batch
 
   cx<T> la[KL], lb[KL];
   load_line<T, Plan, KL>(la, A + base, j, Mz, valid);
@@ -448,8 +456,13 @@ __global__ __launch_bounds__(256) void k_z_r2c(const T* __restrict__ in, cx<T>* 
 template <typename T>
 __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, cx<T>* __restrict__ U0,
                                                   cx<T>* __restrict__ U1, cx<T>* __restrict__ Acc, long C,
-                                                  Geo g, int mode, T nu, T dt) {
+                                                  long is, Geo g, int mode, T nu, T dt) {
   const long stride = (long)gridDim.x * blockDim.x;
+  const long ib = blockIdx.y * is;  // instance of a batch (all four arrays share the stride)
+  Nh += ib;
+  U0 += ib;
+  U1 += ib;
+  Acc += ib;
   const long MMz = (long)g.M * g.Mzp;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < C; e += stride) {
     const int ix = (int)(e / MMz);
@@ -507,10 +520,15 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
 // Canonical <-> compact.  Canonical: [3][N][N][N/2+1].  Compact:
 // [3][M][M][Mzp].  Gather drops the modes outside the retained set
 // (projection onto the Galerkin space); scatter writes zeros there.
+// blockIdx.y is the instance of a batch; the canonical array of instance b
+// is tab[b] when a device pointer table is given.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long C,
-                                                Geo g) {
+__global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in0, const cx<T>* const* __restrict__ in_tab,
+                                                cx<T>* __restrict__ out, long C, long is, Geo g) {
+  // instance blockIdx.y: its canonical input from the table (or in0 alone)
+  const cx<T>* __restrict__ in = in_tab ? in_tab[blockIdx.y] : in0;
+  out += blockIdx.y * is;
   const long stride = (long)gridDim.x * blockDim.x;
   const long Nh = g.N / 2 + 1;
   const long MMz = (long)g.M * g.Mzp;
@@ -528,8 +546,10 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in, cx
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long C,
-                                                 Geo g) {
+__global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, cx<T>* out0, cx<T>* const* __restrict__ out_tab,
+                                                 long C, long is, Geo g) {
+  cx<T>* __restrict__ out = out_tab ? out_tab[blockIdx.y] : out0;
+  in += blockIdx.y * is;
   const long stride = (long)gridDim.x * blockDim.x;
   const long Nh = g.N / 2 + 1;
   const long plane = (long)g.N * Nh;

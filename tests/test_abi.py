@@ -137,3 +137,29 @@ def test_error_strings():
     lib = binding.library()
     for code in (0, -1, -2, -3, -4, -99):
         assert lib.hot_error_string(code)
+
+
+def test_graph_and_tune_reject_bad_arguments_without_the_gpu():
+    lib = binding.library()
+    h, wsb = binding.hot_plan([16, 24, 16], "rk4", "f32", nu=0.01, dt=1e-3)
+    try:
+        arr = (ctypes.c_void_p * 3)(256 * 1000, 256 * 2000, 256 * 3000)
+        g = ctypes.c_void_p()
+        # the legacy default stream cannot be captured
+        assert lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, None, ctypes.byref(g)) == \
+            binding.HOT_E_INVALID
+        assert not g.value
+        assert lib.hot_tune(h, ctypes.c_void_p(256 * 9), None, 0) == binding.HOT_E_INVALID
+        assert lib.hot_tune(h, None, None, 1) == binding.HOT_E_WORKSPACE
+        assert lib.hot_graph_launch(None, None) == binding.HOT_E_INVALID
+        assert lib.hot_graph_destroy(None) == 0
+    finally:
+        binding.hot_destroy(h)
+
+
+def test_batched_workspace_is_the_sum_over_sizes():
+    # instances of equal N share one batch-major region; different N add up
+    _, w16 = binding.hot_plan([16], "rk4", "f32", nu=0.01, dt=1e-3)
+    _, w24 = binding.hot_plan([24], "rk4", "f32", nu=0.01, dt=1e-3)
+    _, wb = binding.hot_plan([16, 24, 16, 16], "rk4", "f32", nu=0.01, dt=1e-3)
+    assert wb >= 3 * w16 + w24 - 4 * 256 * 8 and wb <= 3 * w16 + w24 + 2 * 256 * 8
