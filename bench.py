@@ -113,6 +113,150 @@ def device_field(N, dtype, seed=0):
     return x
 
 
+def _r1_modes(args):
+    from paper_1607_00850_amd import inputs
+    N, seed = args
+    return inputs.smooth_random_modes(N, seed)
+
+
+def batch_fields(sizes, dtype, first_seed=1000):
+    """R1 (seed first_seed + i) for every instance, laid out per size in one
+    device buffer with 256-byte aligned instance slices."""
+    import concurrent.futures
+
+    import numpy as np
+    import torch
+
+    cdt = torch.complex64 if dtype == "f32" else torch.complex128
+    esz = 8 if dtype == "f32" else 16
+    with concurrent.futures.ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        modes = list(ex.map(_r1_modes, [(int(N), first_seed + i) for i, N in enumerate(sizes)], chunksize=64))
+    ins, outs, keep = [None] * len(sizes), [None] * len(sizes), []
+    for N in sorted(set(int(v) for v in sizes)):
+        idx = [i for i, v in enumerate(sizes) if int(v) == N]
+        n = 3 * N * N * (N // 2 + 1)
+        stride = -(-n * esz // 256) * 256 // esz
+        host = np.zeros((len(idx), stride), dtype=np.complex64 if dtype == "f32" else np.complex128)
+        for b, i in enumerate(idx):
+            ix, iy, iz, vals = modes[i]
+            for c in range(3):
+                host[b, ((c * N + ix) * N + iy) * (N // 2 + 1) + iz] = vals[c]
+        dev_in = torch.from_numpy(host).to("cuda")
+        dev_out = torch.empty_like(dev_in)
+        keep += [dev_in, dev_out]
+        for b, i in enumerate(idx):
+            ins[i] = dev_in[b, :n]
+            outs[i] = dev_out[b, :n]
+    return ins, outs, keep
+
+
+def bench_batch(a):
+    """Many uneven instances: one RK4 step of every instance per call."""
+    import numpy as np
+    import torch
+
+    from paper_1607_00850_amd import binding, inputs
+
+    sizes = inputs.batch_sizes(a.batch, 0)
+    t_gen = time.perf_counter()
+    ins, outs, keep = batch_fields(sizes, a.dtype)
+    t_gen = time.perf_counter() - t_gen
+    plan, wsb = binding.hot_plan([int(v) for v in sizes], "rk4", a.dtype, "two_thirds", NU, DT)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    res = {}
+    try:
+        with torch.cuda.stream(s):
+            binding.hot_tune(plan, ws, s)
+            for _ in range(a.warmup):
+                binding.hot_run(plan, ins, outs, ws, 1, s)
+            torch.cuda.synchronize()
+            # eager: one hot_run per batch step, per-pass events on
+            binding.hot_profile_enable(plan, True)
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                binding.hot_run(plan, ins, outs, ws, 1, s)
+            torch.cuda.synchronize()
+            t_eager = (time.perf_counter() - t0) / a.steps
+            prof = binding.hot_profile_read(plan)
+            binding.hot_profile_enable(plan, False)
+            # graph: the whole batch step as one replayed HIP graph
+            g = binding.hot_graph_create(plan, ins, outs, ws, 1, s)
+            binding.hot_graph_launch(g, s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                binding.hot_graph_launch(g, s)
+            torch.cuda.synchronize()
+            t_graph = (time.perf_counter() - t0) / a.steps
+            binding.hot_graph_destroy(g)
+        pass_bytes = {}
+        for k in prof:
+            pass_bytes[k] = sum(binding.hot_pass_bytes(plan, i, k) for i in range(len(sizes)))
+        widths = {int(N): binding.hot_tuned_width(plan, int(np.argmax(sizes == N)), "y_inv") for N in set(sizes)}
+    finally:
+        binding.hot_destroy(plan)
+    del ws
+    # one instance per call: a plan per size, every instance run alone
+    plans = {}
+    try:
+        for N in set(int(v) for v in sizes):
+            h, w = binding.hot_plan(N, "rk4", a.dtype, "two_thirds", NU, DT)
+            plans[N] = (h, torch.empty(w, dtype=torch.uint8, device="cuda"))
+        with torch.cuda.stream(s):
+            for i, N in enumerate(sizes[:64]):  # warm-up
+                h, w = plans[int(N)]
+                binding.hot_run(h, [ins[i]], [outs[i]], w, 1, s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i, N in enumerate(sizes):
+                h, w = plans[int(N)]
+                binding.hot_run(h, [ins[i]], [outs[i]], w, 1, s)
+            torch.cuda.synchronize()
+            t_single = time.perf_counter() - t0
+    finally:
+        for h, _ in plans.values():
+            binding.hot_destroy(h)
+    B = len(sizes)
+    dom = max(prof, key=lambda k: prof[k][0])
+    step_bytes = sum(pass_bytes[k] * prof[k][1] for k in prof) / a.steps / 1.0
+    # launches per call of a pass = (#sizes) x (uses per call); bytes summed over instances per call
+    uses = {k: prof[k][1] / a.steps / len(set(sizes)) for k in prof}
+    call_bytes = {k: pass_bytes[k] * uses[k] for k in prof}
+    dom_time = prof[dom][0] / a.steps / 1e3
+    achieved = call_bytes[dom] / dom_time / 1e9
+    step_bytes = sum(call_bytes.values())
+    line = {
+        "metric": "instances/sec",
+        "value": B / t_graph,
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": t_graph * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.dtype,
+        "data": "synthetic (R1 per instance, seeds 1000+i; sizes log-uniform over [16, 64], seed 0)",
+        "config": {"workload": f"rk4_batch_{B}_uneven_16-64_{a.dtype}", "instances": B,
+                   "sizes": {int(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))},
+                   "points": int((sizes.astype(np.int64) ** 3).sum()), "nu": NU, "dt": DT,
+                   "launch": "one HIP graph replay per batch step (one launch per pass per size inside)"},
+        "elements_per_sec": float((sizes.astype(np.float64) ** 3).sum()) / t_graph,
+        "eager_instances_per_sec": B / t_eager,
+        "one_instance_per_call_instances_per_sec": B / t_single,
+        "tuned_y_inv_columns": widths,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / t_graph / 1e9,
+                          "frac": step_bytes / t_graph / 1e9 / HBM_PEAK_GBS},
+        "setup_seconds": {"fields": t_gen},
+    }
+    print(json.dumps(line), flush=True)
+    del keep
+
+
 def cpu_baseline(N_work, seconds=12.0):
     """Time the CPU oracle (one core) on RK4 steps at N = 128 and scale to
     instances/s of an N_work^3 step by the FFT cost N^3 log2 N."""
@@ -163,6 +307,9 @@ def main():
                     help="write profiles/counters.json from two rocprofv3 --pmc counter_collection.csv files "
                          "(no GPU needed); use with --calibrate-copy MIB and --pmc-command")
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded with the counters")
+    ap.add_argument("--workload", default="single", choices=["single", "batch"],
+                    help="single: one N^3 field (default); batch: many uneven instances, one RK4 step each")
+    ap.add_argument("--batch", type=int, default=4096, help="instances of the batch workload")
     a = ap.parse_args()
 
     if a.ingest_counters:
@@ -179,6 +326,10 @@ def main():
     import torch
 
     from paper_1607_00850_amd import binding
+
+    if a.workload == "batch":
+        bench_batch(a)
+        return
 
     if a.calibrate_copy > 0:
         nbytes = a.calibrate_copy << 20

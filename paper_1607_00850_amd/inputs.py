@@ -26,6 +26,8 @@ does not depend on N where stated.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 __all__ = [
@@ -148,6 +150,18 @@ def _retained(N, k, dealias):
     raise ValueError(dealias)
 
 
+@functools.lru_cache(maxsize=4)
+def _band_basis(band: int):
+    """The band cube's wavenumbers, their R1 spectral shape and plane bases
+    (independent of the seed, so computed once per band)."""
+    k = _band_vectors(band)
+    nz = np.any(k != 0, axis=-1)
+    k2 = np.sum(k * k, axis=-1).astype(np.float64)
+    shape = np.where(nz, k2 * np.exp(-k2 / 9.0), 0.0)
+    e1, e2 = _plane_basis(k[nz])
+    return k, nz, shape, e1, e2
+
+
 def smooth_random_modes(N: int, seed: int, dealias: str = "two_thirds", band: int = 16):
     """R1 in sparse form: FFT indices (ix, iy, iz) and values (3, n) of the
     nonzero half-spectrum entries.  Spectrum |k|^4 exp(-2|k|^2/9), random
@@ -155,15 +169,11 @@ def smooth_random_modes(N: int, seed: int, dealias: str = "two_thirds", band: in
     cover the whole band cube in a fixed order, so the field does not depend
     on N (beyond truncation by the retained set)."""
     rng = np.random.default_rng(seed)
-    k = _band_vectors(band)
+    k, nz, shape, e1, e2 = _band_basis(band)
     n = len(k)
     a1 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     a2 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
-    nz = np.any(k != 0, axis=-1)
-    k2 = np.sum(k * k, axis=-1).astype(np.float64)
-    shape = np.where(nz, k2 * np.exp(-k2 / 9.0), 0.0)
     amp = np.zeros((n, 3), dtype=np.complex128)
-    e1, e2 = _plane_basis(k[nz])
     amp[nz] = (a1[nz, None] * e1 + a2[nz, None] * e2) * shape[nz, None]
     # the cube is ordered lexicographically and symmetric, so -k sits at n-1-m;
     # on kz = 0 take u(k) = (a(k) + conj a(-k))/2 so that u(-k) = conj u(k)
@@ -248,3 +258,17 @@ def beltrami(N: int, K2: int, seed: int, sign: int = 1) -> np.ndarray:
     uh = np.zeros(_half_shape(N), dtype=np.complex128)
     uh[:, ix, iy, iz] = vals
     return uh
+
+
+BATCH_SIZES = (16, 18, 24, 32, 36, 48, 54, 64)
+
+
+def batch_sizes(count: int, seed: int, sizes=BATCH_SIZES) -> np.ndarray:
+    """Sizes of a batch of uneven instances: N log-uniform over [min, max] of
+    `sizes` (so N^3 spans a factor 64 for 16..64), each rounded in log space
+    to the nearest allowed size (2^a 3^b)."""
+    allowed = np.asarray(sizes)
+    rng = np.random.default_rng(seed)
+    logn = rng.uniform(np.log(allowed.min()), np.log(allowed.max()), count)
+    pick = np.argmin(np.abs(np.log(allowed)[None, :] - logn[:, None]), axis=1)
+    return allowed[pick]
