@@ -4,4 +4,8 @@ Only the tests, the package's smoke check and the benchmark's CPU-baseline leg
 may import this package.  The GPU library never imports, links or calls it.
 """
 from .spectral_ns import *  # noqa: F401,F403
-from .spectral_ns import __all__  # noqa: F401
+from .implicit_midpoint import *  # noqa: F401,F403
+from .spectral_ns import __all__ as _a
+from .implicit_midpoint import __all__ as _b
+
+__all__ = list(_a) + list(_b)

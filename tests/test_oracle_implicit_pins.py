@@ -1,0 +1,145 @@
+"""Pins of the implicit-midpoint oracle (CPU).
+
+Each test checks the oracle against a fact fixed by the mathematics, not by
+its own code:
+  * Beltrami fields: the nonlinear term vanishes, so one step multiplies each
+    mode by the Crank-Nicolson factor (1 - a)/(1 + a), a = dt nu |k|^2 / 2;
+  * the converged step satisfies the defining equation
+    u1 - u0 = dt F((u0 + u1)/2), with F the right-hand side of Eq. NSfinal
+    (pinned separately against the closed-form Taylor-Green right-hand side);
+  * time symmetry: the implicit midpoint rule is self-adjoint, so a step of
+    -dt from u1 returns u0;
+  * the discrete energy budget of the midpoint rule (exact for quadratic
+    invariants): E1 - E0 = -dt nu sum w |k|^2 |m|^2 / N^6, m = (u0 + u1)/2;
+  * global error of order 2 against a fine RK4 reference.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_00850_amd import inputs
+
+NU = 1.0 / 1600.0
+
+
+def _k2(N):
+    kx, ky, kz = oracle.wavenumbers(N)
+    return kx * kx + ky * ky + kz * kz
+
+
+@pytest.mark.parametrize("N,K2", [(16, 9), (16, 3), (24, 14)])
+def test_beltrami_crank_nicolson_factor(N, K2):
+    nu, dt = 0.05, 0.1
+    u0 = inputs.beltrami(N, K2, seed=3)
+    u1, sweeps, ok, _ = oracle.implicit_midpoint_step(u0, nu, dt, tau=1e-12)
+    a = 0.5 * dt * nu * K2
+    assert ok
+    assert sweeps == 2  # the first sweep is exact, the second sees no update
+    assert oracle.half_norm(u1 - (1 - a) / (1 + a) * u0) <= 1e-13 * oracle.half_norm(u0)
+
+
+@pytest.mark.parametrize("gen,N", [("smooth", 16), ("rough", 12), ("tg", 8)])
+def test_step_satisfies_the_midpoint_equation(gen, N):
+    u0 = {"smooth": lambda: inputs.smooth_random(N, 1), "rough": lambda: inputs.rough_random(N, 2),
+          "tg": lambda: inputs.taylor_green(N)}[gen]()
+    dt = 0.02
+    u1, _, ok, _ = oracle.implicit_midpoint_step(u0, NU, dt, tau=1e-13)
+    assert ok
+    resid = (u1 - u0) - dt * oracle.rhs(0.5 * (u0 + u1), NU)
+    assert oracle.half_norm(resid) <= 1e-11 * oracle.half_norm(u1 - u0)
+
+
+@pytest.mark.parametrize("nu", [0.0, 0.01])
+def test_time_symmetry(nu):
+    N, dt = 16, 0.05
+    u0 = inputs.rough_random(N, 5)
+    u1, _, ok1, _ = oracle.implicit_midpoint_step(u0, nu, dt, tau=1e-13)
+    back, _, ok2, _ = oracle.implicit_midpoint_step(u1, nu, -dt, tau=1e-13)
+    assert ok1 and ok2
+    assert oracle.half_norm(back - u0) <= 1e-11 * oracle.half_norm(u0)
+
+
+@pytest.mark.parametrize("nu", [0.0, 0.02])
+def test_discrete_energy_budget(nu):
+    N, dt = 16, 0.05
+    u0 = inputs.smooth_random(N, 6)
+    u1, _, ok, _ = oracle.implicit_midpoint_step(u0, nu, dt, tau=1e-13)
+    assert ok
+    m = 0.5 * (u0 + u1)
+    w = np.full(N // 2 + 1, 2.0)
+    w[0] = w[-1] = 1.0
+    budget = -dt * nu * float(np.sum(w * np.sum(_k2(N) * np.sum(np.abs(m) ** 2, axis=0), axis=(0, 1))))
+    budget /= float(N) ** 6
+    dE = oracle.energy(u1) - oracle.energy(u0)
+    assert abs(dE - budget) <= 1e-12 * oracle.energy(u0)
+    if nu == 0.0:
+        assert abs(dE) <= 1e-12 * oracle.energy(u0)
+
+
+def test_second_order_convergence():
+    N, T = 12, 0.08
+    u0 = inputs.smooth_random(N, 7) * 8.0  # faster dynamics, visible error
+    ref = oracle.rk4(u0, 0.01, T / 64, 64)
+    errs = []
+    for n in (4, 8, 16):
+        u, _, _, _ = oracle.implicit_midpoint(u0, 0.01, T / n, n, tau=1e-13)
+        errs.append(oracle.half_norm(u - ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, errs
+
+
+def test_picard_stops_at_tolerance_and_extrapolation_saves_sweeps():
+    N, dt = 16, 0.02
+    u0 = inputs.smooth_random(N, 8) * 4.0
+    u, sweeps, incs, _ = oracle.implicit_midpoint(u0, NU, dt, 4, tau=1e-10)
+    # the stopping test is met by the returned iterate of the last step
+    pred = oracle.extrapolation_predictor(u - incs[-1], incs[-3:-1])
+    _, s_plain, _, _ = oracle.implicit_midpoint_step(u - incs[-1], NU, dt, 1e-10, 50, None)
+    _, s_pred, _, _ = oracle.implicit_midpoint_step(u - incs[-1], NU, dt, 1e-10, 50, pred)
+    assert s_pred == sweeps[-1]
+    assert s_pred < s_plain
+    # a contraction: with a cap of one sweep fewer the test fails
+    _, s_cap, ok, _ = oracle.implicit_midpoint_step(u - incs[-1], NU, dt, 1e-10, s_pred - 1, pred)
+    assert not ok and s_cap == s_pred - 1
+
+
+def test_zero_field_converges_in_one_sweep():
+    N = 8
+    u0 = np.zeros((3, N, N, N // 2 + 1), complex)
+    u1, sweeps, ok, _ = oracle.implicit_midpoint_step(u0, NU, 0.01)
+    assert ok and sweeps == 1 and not np.any(u1)
+
+
+def test_half_norm_is_parseval():
+    # ||x||^2 over the full spectrum = N^3 sum_x |u(x)|^2 for the real field u
+    N = 8
+    u = np.random.default_rng(0).standard_normal((3, N, N, N))
+    x = oracle.forward(u)
+    assert abs(oracle.half_norm(x) ** 2 - N**3 * np.sum(u**2)) <= 1e-12 * N**3 * np.sum(u**2)
+
+
+def test_extrapolation_predictor_is_exact_on_quadratic_trajectories():
+    # u(t) = A + B t + C t^2 sampled at t = 0, 1, 2: the predictor must give u(3)
+    rng = np.random.default_rng(1)
+    A, B, C = (rng.standard_normal((3, 4, 4, 3)) for _ in range(3))
+    u = [A + B * t + C * t * t for t in range(4)]
+    pred = oracle.extrapolation_predictor(u[2], [u[1] - u[0], u[2] - u[1]])
+    assert np.allclose(pred, u[3], rtol=0, atol=1e-12)
+    # one increment of history: exact on linear trajectories
+    pred1 = oracle.extrapolation_predictor(A + B, [B])
+    assert np.allclose(pred1, A + 2 * B, rtol=0, atol=1e-12)
+
+
+def test_stopping_rule_is_update_over_increment():
+    # iterates taken with max_iter caps; the test on them is written out here
+    N, dt, tau = 16, 0.05, 1e-9
+    u0 = inputs.smooth_random(N, 9) * 4.0
+    w, s, ok, _ = oracle.implicit_midpoint_step(u0, NU, dt, tau)
+    assert ok and s >= 3
+    it = [oracle.implicit_midpoint_step(u0, NU, dt, tau, k)[0] for k in (s - 2, s - 1)]
+
+    def norm(x):  # Parseval norm of the real field, up to N^3
+        return np.sqrt(N**3 * np.sum(oracle.inverse(x, N) ** 2))
+
+    assert norm(w - it[1]) <= tau * norm(w - u0)
+    assert norm(it[1] - it[0]) > tau * norm(it[1] - u0)
