@@ -299,6 +299,7 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default column widths (no hot_tune)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (a known-size kernel "
@@ -346,6 +347,10 @@ def main():
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     try:
+        widths = {}
+        if not a.no_tune:
+            binding.hot_tune(plan, ws, stream)
+            widths = {k: binding.hot_tuned_width(plan, 0, k) for k in ("x_inv_curl", "y_inv", "y_fwd", "x_fwd")}
         binding.hot_run(plan, [x], [y], ws, a.warmup, stream)
         torch.cuda.synchronize()
         binding.hot_profile_enable(plan, True)
@@ -393,6 +398,7 @@ def main():
         "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (ms_step / 1e3) / 1e9,
                           "frac": step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "passes": passes,
+        "tuned_columns": widths,
     }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(N, a.cpu_seconds)

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define HOT_ABI_VERSION 1
+#define HOT_ABI_VERSION 2
 
 /* Return codes. */
 #define HOT_OK 0
@@ -44,6 +44,7 @@ extern "C" {
 #define HOT_E_UNSUPPORTED (-2) /* valid request this build does not implement (e.g. an N) */
 #define HOT_E_WORKSPACE (-3)   /* workspace pointer null or misaligned */
 #define HOT_E_HIP (-4)         /* a HIP call failed; hot_last_hip_error() has the code */
+#define HOT_E_NOCONVERGE (-6)  /* IMPLICIT: an instance hit max_iter sweeps (its last iterate is kept) */
 
 /* Element type. */
 #define HOT_F64 0
@@ -65,22 +66,40 @@ extern "C" {
  *       projected onto the retained modes (the Galerkin space of the
  *       dealiased method); the output is zero outside them.
  *  RK4  spectral uhat -> spectral uhat after nsteps classical RK4 steps of
- *       size dt (Sec. 2), input projected as for RHS.  in == out allowed. */
+ *       size dt (Sec. 2), input projected as for RHS.  in == out allowed.
+ *  IMPLICIT  spectral uhat -> spectral uhat after nsteps implicit-midpoint
+ *       steps (Crank-Nicolson on the viscous term), an implicit alternative
+ *       to the RK4 integration of Sec. 2: with m = (u^n + u^{n+1})/2,
+ *       u^{n+1} - u^n = dt F(m), F the right-hand side of Eq. NSfinal.  Each
+ *       step is solved by Picard sweeps on the increment d = u^{n+1} - u^n,
+ *         d <- [dt F_NL(u^n + d/2) - 2a u^n] / (1 + a),  a = dt nu |k|^2 / 2,
+ *       F_NL the projected, dealiased nonlinear term, until
+ *       ||d_new - d|| <= tol ||d_new|| (L2 norms of the real field) or
+ *       max_iter sweeps.  The first sweep starts from the predictor 0 at the
+ *       first step of a call, the previous increment at the second, and the
+ *       extrapolation 2 d^{n-1} - d^{n-2} after that.  Each instance stops on
+ *       its own.  The call synchronises the stream once per sweep (to read
+ *       the stopping flags); it cannot be captured in a graph.  in == out
+ *       allowed. */
 #define HOT_OP_R2C 0
 #define HOT_OP_C2R 1
 #define HOT_OP_RHS 2
 #define HOT_OP_RK4 3
+#define HOT_OP_IMPLICIT 4
 
 typedef struct hot_desc {
   int32_t abi_version; /* HOT_ABI_VERSION */
   int32_t batch;       /* number of instances, >= 1 */
   const int32_t* n;    /* host array [batch]: points per axis of each instance */
   double nu;           /* kinematic viscosity (>= 0); Sec. 4 uses Re = 1600 -> nu = 1/1600 */
-  double dt;           /* RK4 step (> 0, RK4 only); Sec. 4 uses 0.001 */
+  double dt;           /* time step (> 0, RK4 and IMPLICIT); Sec. 4 uses 0.001 */
   int32_t dtype;       /* HOT_F64 or HOT_F32 */
   int32_t dealias;     /* HOT_DEALIAS_* (RHS and RK4) */
   int32_t op;          /* HOT_OP_* */
   int32_t flags;       /* reserved, must be 0 */
+  double tol;          /* IMPLICIT: relative stopping tolerance (> 0); ignored otherwise */
+  int32_t max_iter;    /* IMPLICIT: sweeps per step at most (>= 1); ignored otherwise */
+  int32_t reserved;    /* must be 0 */
 } hot_desc;
 
 typedef struct hot_plan_s* hot_plan_t;
@@ -94,19 +113,22 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes);
 
 /* Enqueue the planned operation on stream (a hipStream_t; NULL = default).
  * in[i], out[i]: device pointers of instance i (layouts above; R2C reads
- * physical and writes spectral, C2R the reverse, RHS/RK4 spectral both).
- * Instances must not overlap each other (in[i] == out[i] is allowed).
- * workspace: device buffer of at least the planned size.  nsteps: RK4 steps
- * (>= 0; ignored by other ops).  Asynchronous; inputs must stay valid until
- * the stream reaches the end of the call.
- * Batches: for RHS and RK4, instances of equal N run together, each pass as
+ * physical and writes spectral, C2R the reverse, RHS/RK4/IMPLICIT spectral
+ * both).  Instances must not overlap each other (in[i] == out[i] is allowed).
+ * workspace: device buffer of at least the planned size.  nsteps: RK4 or
+ * IMPLICIT steps (>= 0; ignored by other ops).  Asynchronous except for
+ * IMPLICIT (see HOT_OP_IMPLICIT); inputs must stay valid until the stream
+ * reaches the end of the call.
+ * Batches: for RHS, RK4 and IMPLICIT, instances of equal N run together, each pass as
  * one launch over all of them (the instance is a grid dimension).  The
  * device tables of their in/out pointers live in the workspace: hot_run
  * uploads them, and synchronises the stream, only when the pointers or the
  * workspace differ from the previous call's; calls with the same pointers
  * only enqueue kernels.
  * Errors: HOT_E_INVALID (null plan/pointer, nsteps < 0), HOT_E_WORKSPACE,
- * HOT_E_HIP (launch failure; the plan keeps the HIP error code). */
+ * HOT_E_HIP (launch failure; the plan keeps the HIP error code),
+ * HOT_E_NOCONVERGE (IMPLICIT only: the whole call ran, some step of some
+ * instance stopped at max_iter; hot_implicit_stats says which). */
 int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps, void* stream);
 
 /* A captured hot_run: the whole operation (every pass of every instance and
@@ -114,21 +136,29 @@ int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, in
  * hot_graph_create captures on stream, which must not be the legacy default
  * stream (NULL); the pointer tables are uploaded first, outside the capture.
  * The graph keeps the pointers it was created with.  Per-pass profiling is
- * not recorded inside graphs.  Errors as hot_run. */
+ * not recorded inside graphs.  Errors as hot_run; HOT_E_UNSUPPORTED for
+ * IMPLICIT, whose sweep count is decided on the host. */
 typedef struct hot_graph_s* hot_graph_t;
 int hot_graph_create(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
                      void* stream, hot_graph_t* graph);
 int hot_graph_launch(hot_graph_t graph, void* stream);
 int hot_graph_destroy(hot_graph_t graph);
 
-/* Autotuner: for every distinct N of the plan and every strided pass (y
- * inverse, y forward, x forward), time each column-width variant reps times
+/* Autotuner: for every distinct N of the plan and every column-tiled pass
+ * (x inverse with the curl, y inverse, y forward, x forward), time each
+ * column-width variant reps times
  * on the workspace (which must be the planned size; the caller's arrays are
  * not touched) and keep the fastest for later hot_run calls.  Synchronises
  * the stream.  hot_tuned_width reports the chosen columns per block of a
  * pass for instance i, or a negative error code. */
 int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t reps);
 int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
+
+/* IMPLICIT statistics of the plan's last hot_run, per instance i (host
+ * arrays of p's batch size, either may be NULL): sweeps[i] = Picard sweeps
+ * summed over the call's steps, nonconv[i] = steps that stopped at max_iter.
+ * Host only.  Errors: HOT_E_INVALID (null plan, op not IMPLICIT). */
+int hot_implicit_stats(hot_plan_t p, int32_t* sweeps, int32_t* nonconv);
 
 /* Release the plan's host state (waits for its pending profiling events).
  * NULL is accepted and ignored. */

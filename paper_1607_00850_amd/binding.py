@@ -12,20 +12,21 @@ import os
 
 from .build import LIB
 
-HOT_ABI_VERSION = 1
+HOT_ABI_VERSION = 2
 HOT_OK = 0
 HOT_E_INVALID = -1
 HOT_E_UNSUPPORTED = -2
 HOT_E_WORKSPACE = -3
 HOT_E_HIP = -4
+HOT_E_NOCONVERGE = -6
 
 HOT_F64, HOT_F32 = 0, 1
 HOT_DEALIAS_TWO_THIRDS, HOT_DEALIAS_NONE = 0, 1
-HOT_OP_R2C, HOT_OP_C2R, HOT_OP_RHS, HOT_OP_RK4 = 0, 1, 2, 3
+HOT_OP_R2C, HOT_OP_C2R, HOT_OP_RHS, HOT_OP_RK4, HOT_OP_IMPLICIT = 0, 1, 2, 3, 4
 
 DTYPES = {"f64": HOT_F64, "f32": HOT_F32}
 DEALIAS = {"two_thirds": HOT_DEALIAS_TWO_THIRDS, "none": HOT_DEALIAS_NONE}
-OPS = {"r2c": HOT_OP_R2C, "c2r": HOT_OP_C2R, "rhs": HOT_OP_RHS, "rk4": HOT_OP_RK4}
+OPS = {"r2c": HOT_OP_R2C, "c2r": HOT_OP_C2R, "rhs": HOT_OP_RHS, "rk4": HOT_OP_RK4, "implicit": HOT_OP_IMPLICIT}
 
 
 class HotDesc(ctypes.Structure):
@@ -39,6 +40,9 @@ class HotDesc(ctypes.Structure):
         ("dealias", ctypes.c_int32),
         ("op", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -91,6 +95,8 @@ def _lib():
         lib.hot_tune.restype = ctypes.c_int
         lib.hot_tuned_width.argtypes = [vp, i32, i32]
         lib.hot_tuned_width.restype = ctypes.c_int
+        lib.hot_implicit_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        lib.hot_implicit_stats.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -100,11 +106,13 @@ def library():
     return _lib()
 
 
-def hot_plan(n, op, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0):
-    """Plan an operation; returns (handle, workspace_bytes).  n: int or list."""
+def hot_plan(n, op, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0, tol=1e-10, max_iter=50):
+    """Plan an operation; returns (handle, workspace_bytes).  n: int or list.
+    tol, max_iter: stopping rule of the implicit step (ignored otherwise)."""
     ns = [int(n)] if isinstance(n, int) else [int(v) for v in n]
     arr = (ctypes.c_int32 * len(ns))(*ns)
-    d = HotDesc(HOT_ABI_VERSION, len(ns), arr, float(nu), float(dt), DTYPES[dtype], DEALIAS[dealias], OPS[op], 0)
+    d = HotDesc(HOT_ABI_VERSION, len(ns), arr, float(nu), float(dt), DTYPES[dtype], DEALIAS[dealias], OPS[op], 0,
+                float(tol), int(max_iter), 0)
     h = ctypes.c_void_p()
     ws = ctypes.c_size_t()
     rc = _lib().hot_plan(ctypes.byref(d), ctypes.byref(h), ctypes.byref(ws))
@@ -134,14 +142,16 @@ def hot_run(plan, ins, outs, workspace, nsteps=0, stream=None):
     """Enqueue the planned op.  ins/outs: sequences of device tensors (or raw
     pointers), one per instance; workspace: device tensor or pointer;
     stream: a torch.cuda.Stream, a raw hipStream_t, or None for torch's
-    current stream."""
+    current stream.  Returns HOT_OK, or HOT_E_NOCONVERGE when an implicit
+    step stopped at max_iter (see hot_implicit_stats); raises otherwise."""
     stream = _stream(stream)
     n = len(ins)
     pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
     pout = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
     rc = _lib().hot_run(plan, pin, pout, _ptr(workspace), int(nsteps), stream)
-    if rc != HOT_OK:
+    if rc not in (HOT_OK, HOT_E_NOCONVERGE):
         raise HotError(rc, "hot_run", _lib().hot_last_hip_error(plan))
+    return rc
 
 
 def hot_destroy(plan):
@@ -232,3 +242,14 @@ def hot_tuned_width(plan, instance, pass_name):
     if w < 0:
         raise HotError(w, "hot_tuned_width")
     return w
+
+
+def hot_implicit_stats(plan, batch):
+    """Per instance of the last implicit call: (sweeps summed over its steps,
+    steps that stopped at max_iter), as two lists."""
+    sw = (ctypes.c_int32 * batch)()
+    nc = (ctypes.c_int32 * batch)()
+    rc = _lib().hot_implicit_stats(plan, sw, nc)
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_implicit_stats")
+    return list(sw), list(nc)

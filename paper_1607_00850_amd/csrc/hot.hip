@@ -25,11 +25,16 @@ enum Pass : int {
   PASS_Z_R2C,
   PASS_Z_C2R,
   PASS_X_INV,
+  PASS_IMP_PREDICT,
+  PASS_IMP_UPDATE,
+  PASS_IMP_DECIDE,
+  PASS_IMP_ADVANCE,
   NUM_PASSES
 };
 
 static const char* kPassNames[NUM_PASSES] = {
     "gather", "x_inv_curl", "y_inv", "z_cross", "y_fwd", "x_fwd", "rk_stage", "scatter", "z_r2c", "z_c2r", "x_inv",
+    "imp_predict", "imp_update", "imp_decide", "imp_advance",
 };
 
 template <typename T>
@@ -78,11 +83,13 @@ static Geo make_geo(int N, int mode, int elem) {
 static const size_t kAlign = 256;
 static inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// All instances of one N.  For the right-hand side and RK4 their workspace is
-// one region laid out batch-major: U0, U1, Acc, Nh = [B][3][C] each,
-// A1 = [B][6][D1], A2 = [B][6][D2] (then, for B > 1, the device tables of the
-// members' input and output pointers).  Plain transforms run one instance at a
-// time in a shared region.
+// All instances of one N.  For the right-hand side, RK4 and the implicit step
+// their workspace is one region laid out batch-major: U0, U1, Acc, Nh =
+// [B][3][C] each, A1 = [B][6][D1], A2 = [B][6][D2], then for B > 1 the device
+// tables of the members' input and output pointers.  The implicit step adds
+// two increment histories H1, H2 = [B][3][C] (its iterate d lives in Acc),
+// the stopping flags act[B] and the partial sums part[B][nparts][2].  Plain
+// transforms run one instance at a time in a shared region.
 struct Group {
   int N = 0;
   Geo g{};
@@ -92,6 +99,8 @@ struct Group {
   double lC = 0, lD1 = 0, lD2 = 0;  // live values per component (Mz)
   size_t off = 0;                   // byte offset of the group's region
   size_t oU0 = 0, oU1 = 0, oAcc = 0, oNh = 0, oA1 = 0, oA2 = 0, oTab = 0;
+  size_t oH[2] = {0, 0}, oAct = 0, oPart = 0;  // implicit step only
+  int nparts = 0;                             // blocks of the implicit update
   size_t bytes = 0;
   int variant[NUM_PASSES];  // strided column-width variant per pass (autotuned)
   int B() const { return (int)members.size(); }
@@ -104,6 +113,9 @@ using namespace hot;
 struct hot_plan_s {
   int op, dtype, dealias;
   double nu, dt;
+  double tol;    // implicit step: stopping tolerance
+  int max_iter;  // implicit step: sweeps per step at most
+  std::vector<int> imp_sweeps, imp_nonconv;  // implicit step: last call, per instance
   size_t elem;  // bytes per complex element
   int batch;
   std::vector<int> n;
@@ -137,6 +149,7 @@ const char* hot_error_string(int code) {
     case HOT_E_UNSUPPORTED: return "unsupported request";
     case HOT_E_WORKSPACE: return "workspace missing or misaligned";
     case HOT_E_HIP: return "HIP error";
+    case HOT_E_NOCONVERGE: return "implicit step stopped at max_iter sweeps";
     default: return "unknown error";
   }
 }
@@ -147,11 +160,12 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
   if (d->abi_version != HOT_ABI_VERSION) return HOT_E_INVALID;
   if (d->batch < 1 || !d->n) return HOT_E_INVALID;
   if (d->dtype != HOT_F64 && d->dtype != HOT_F32) return HOT_E_INVALID;
-  if (d->op < HOT_OP_R2C || d->op > HOT_OP_RK4) return HOT_E_INVALID;
+  if (d->op < HOT_OP_R2C || d->op > HOT_OP_IMPLICIT) return HOT_E_INVALID;
   if (d->dealias != HOT_DEALIAS_TWO_THIRDS && d->dealias != HOT_DEALIAS_NONE) return HOT_E_INVALID;
-  if (d->flags != 0) return HOT_E_INVALID;
+  if (d->flags != 0 || d->reserved != 0) return HOT_E_INVALID;
   if (!(d->nu >= 0.0)) return HOT_E_INVALID;  // also rejects NaN
-  if (d->op == HOT_OP_RK4 && !(d->dt > 0.0)) return HOT_E_INVALID;
+  if ((d->op == HOT_OP_RK4 || d->op == HOT_OP_IMPLICIT) && !(d->dt > 0.0)) return HOT_E_INVALID;
+  if (d->op == HOT_OP_IMPLICIT && (!(d->tol > 0.0) || d->max_iter < 1)) return HOT_E_INVALID;
   for (int i = 0; i < d->batch; ++i) {
     const int N = d->n[i];
     if (N < 8 || (N & 1)) return HOT_E_INVALID;
@@ -163,6 +177,8 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
   p->dealias = d->dealias;
   p->nu = d->nu;
   p->dt = d->dt;
+  p->tol = d->tol;
+  p->max_iter = d->max_iter;
   p->elem = d->dtype == HOT_F64 ? 16 : 8;
   p->batch = d->batch;
   p->n.assign(d->n, d->n + d->batch);
@@ -220,6 +236,14 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
     G.oA2 = G.oA1 + align_up(B * 6 * (size_t)G.D1 * e);
     G.oTab = G.oA2 + align_up(B * 6 * (size_t)G.D2 * e);
     G.bytes = G.oTab + (B > 1 ? align_up(2 * B * sizeof(void*)) : 0);
+    if (d->op == HOT_OP_IMPLICIT) {
+      G.nparts = (int)grid_1d(G.C, 256);
+      G.oH[0] = G.bytes;
+      G.oH[1] = G.oH[0] + sC;
+      G.oAct = G.oH[1] + sC;
+      G.oPart = G.oAct + align_up(B * sizeof(int));
+      G.bytes = G.oPart + align_up(B * (size_t)G.nparts * 2 * sizeof(double));
+    }
     off += G.bytes;
   }
   if (!plain) p->ws_bytes = off;
@@ -295,11 +319,17 @@ int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) 
     case PASS_Y_FWD: b = plain ? (p->op == HOT_OP_R2C ? 6 * D2 : 0) : 3 * D2 + 3 * D1; break;
     case PASS_X_FWD: b = plain ? (p->op == HOT_OP_R2C ? 6 * D2 : 0) : 3 * D1 + 3 * C; break;
     // RK4 stages move 12C, 18C, 18C, 12C (mean 15C); the plain RHS 9C
-    case PASS_RK_STAGE: b = plain ? 0 : (p->op == HOT_OP_RHS ? 9 * C : 15 * C); break;
+    case PASS_RK_STAGE: b = (p->op == HOT_OP_RHS ? 9 * C : (p->op == HOT_OP_RK4 ? 15 * C : 0)); break;
     case PASS_SCATTER: b = plain ? 0 : 3 * C + canon; break;
     case PASS_Z_R2C: b = p->op == HOT_OP_R2C ? 3 * D2 + 3 * N * N * N / 2 : 0; break;  // reals count half
     case PASS_Z_C2R: b = p->op == HOT_OP_C2R ? 3 * D2 + 3 * N * N * N / 2 : 0; break;
     case PASS_X_INV: b = p->op == HOT_OP_C2R ? 6 * D2 : 0; break;
+    // implicit step: the predictor at its widest (reads U0, H1, H2; writes d, U1),
+    // the update (reads Nh, U0, d; writes d, U1), the advance (U0 += d)
+    case PASS_IMP_PREDICT: b = p->op == HOT_OP_IMPLICIT ? 15 * C : 0; break;
+    case PASS_IMP_UPDATE: b = p->op == HOT_OP_IMPLICIT ? 15 * C : 0; break;
+    case PASS_IMP_DECIDE: b = 0; break;
+    case PASS_IMP_ADVANCE: b = p->op == HOT_OP_IMPLICIT ? 9 * C : 0; break;
     default: return HOT_E_INVALID;
   }
   *bytes = b * e;
@@ -351,6 +381,9 @@ struct Runner {
 
 struct GroupPtrs {
   char *U0, *U1, *Acc, *Nh, *A1, *A2;
+  char* H[2];  // implicit step: increment histories
+  int* act;
+  double* part;
   const void* const* in_tab;
   void* const* out_tab;
 };
@@ -364,6 +397,10 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
   q.Nh = base + G.oNh;
   q.A1 = base + G.oA1;
   q.A2 = base + G.oA2;
+  q.H[0] = base + G.oH[0];
+  q.H[1] = base + G.oH[1];
+  q.act = (int*)(base + G.oAct);
+  q.part = (double*)(base + G.oPart);
   q.in_tab = G.B() > 1 ? (const void* const*)(base + G.oTab) : nullptr;
   q.out_tab = G.B() > 1 ? (void* const*)(base + G.oTab + G.B() * sizeof(void*)) : nullptr;
   return q;
@@ -371,29 +408,31 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
 
 // One evaluation of the right-hand side for every instance of a group, from
 // compact state `src` into Nh.
-void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src) {
+void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, const int* act = nullptr) {
   const Geo& g = G.g;
   const long N = g.N, M = g.M, P = g.Mzp;
   const Ops& o = G.ops;
   const int nb = G.B();
   const long isU = 3 * G.C, isA1 = 6 * G.D1, isA2 = 6 * G.D2;
-  r.pass(PASS_X_INV_CURL, [&] { return o.x_inv_curl(r.s, src, G.C, isU, q.A1, G.D1, isA1, nb, g); });
+  r.pass(PASS_X_INV_CURL, [&] {
+    return o.x_inv_curl(r.s, G.variant[PASS_X_INV_CURL], src, G.C, isU, q.A1, G.D1, isA1, nb, g, act);
+  });
   // y inverse: 6 components, batch over x, rows ky (compact) -> y (all N)
   r.pass(PASS_Y_INV, [&] {
     return o.strided(r.s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1,
-                     G.D2, 6, isA1, isA2, nb, g);
+                     G.D2, 6, isA1, isA2, nb, g, act);
   });
-  r.pass(PASS_Z_CROSS, [&] { return o.z_cross(r.s, q.A2, G.D2, isA2, N * N, nb, g); });
+  r.pass(PASS_Z_CROSS, [&] { return o.z_cross(r.s, q.A2, G.D2, isA2, N * N, nb, g, act); });
   // y forward: 3 components, y (all N) -> ky (compact)
   r.pass(PASS_Y_FWD, [&] {
     return o.strided(r.s, G.variant[PASS_Y_FWD], -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2,
-                     G.D1, 3, isA2, isA1, nb, g);
+                     G.D1, 3, isA2, isA1, nb, g, act);
   });
   // x forward: rows x (all N) -> kx (compact), columns (ky, kz)
   r.pass(PASS_X_FWD, [&] {
     const long Q = M * P;
     return o.strided(r.s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3, isA1,
-                     isU, nb, g);
+                     isU, nb, g, act);
   });
 }
 
@@ -456,20 +495,20 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
           r.pass(PASS_Z_R2C, [&] { return o.z_r2c(r.s, in[i], Z1, 3 * N * N, g); });
           r.pass(PASS_Y_FWD, [&] {
             return o.strided(r.s, 1, -1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, 0, 0,
-                             1, g);
+                             1, g, nullptr);
           });
           r.pass(PASS_X_FWD, [&] {
             const long Q = N * Nh;
-            return o.strided(r.s, 1, -1, false, false, Z2, out[i], Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 1, g);
+            return o.strided(r.s, 1, -1, false, false, Z2, out[i], Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 1, g, nullptr);
           });
         } else {
           r.pass(PASS_X_INV, [&] {
             const long Q = N * Nh;
-            return o.strided(r.s, 1, +1, false, false, in[i], Z1, Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 1, g);
+            return o.strided(r.s, 1, +1, false, false, in[i], Z1, Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 1, g, nullptr);
           });
           r.pass(PASS_Y_INV, [&] {
             return o.strided(r.s, 1, +1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, 0, 0,
-                             1, g);
+                             1, g, nullptr);
           });
           r.pass(PASS_Z_C2R, [&] { return o.z_c2r(r.s, Z2, out[i], 3 * N * N, g); });
         }
@@ -507,7 +546,91 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
   return r.rc;
 }
 
+// The implicit step, group by group and step by step.  Each step: the
+// predictor, then Picard sweeps (the right-hand-side passes on the midpoint,
+// the update of d, the stopping test) until every instance of the group has
+// stopped or max_iter sweeps have run.  The stopping flags come back to the
+// host after every sweep; instances that stopped skip the later sweeps.
+// The iterate d lives in Acc and the two increment histories in H1, H2; the
+// three buffers rotate at the end of a step (d becomes the newest history).
+int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t s) {
+  Runner r{p, s, true};
+  p->imp_sweeps.assign(p->batch, 0);
+  p->imp_nonconv.assign(p->batch, 0);
+  bool stalled = false;
+  std::vector<int> flags, live;
+  for (const auto& G : p->groups) {
+    if (r.rc != HOT_OK) break;
+    const GroupPtrs q = group_ptrs(G, workspace);
+    const Ops& o = G.ops;
+    const Geo& g = G.g;
+    const int nb = G.B();
+    const long isU = 3 * G.C;
+    const void* in0 = in[G.members[0]];
+    void* out0 = out[G.members[0]];
+    r.pass(PASS_GATHER, [&] { return o.gather(r.s, in0, q.in_tab, q.U0, G.C, isU, nb, g); });
+    char *D = q.Acc, *H1 = q.H[0], *H2 = q.H[1];
+    flags.assign(nb, 0);
+    for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
+      const int hist = step < 2 ? step : 2;
+      r.pass(PASS_IMP_PREDICT,
+             [&] { return o.imp_predict(r.s, q.U0, D, q.U1, H1, H2, G.C, isU, nb, g, hist, q.act); });
+      live.assign(nb, 1);
+      for (int sw = 0; sw < p->max_iter && r.rc == HOT_OK; ++sw) {
+        rhs_passes(r, G, q, q.U1, q.act);
+        r.pass(PASS_IMP_UPDATE, [&] {
+          return o.imp_update(r.s, q.Nh, q.U0, D, q.U1, q.part, G.C, isU, nb, g, p->nu, p->dt, q.act);
+        });
+        r.pass(PASS_IMP_DECIDE, [&] {
+          hipLaunchKernelGGL(k_imp_decide<>, dim3(nb), dim3(64), 0, r.s, (const double*)q.part, G.nparts, q.act,
+                             p->tol * p->tol);
+          return hipGetLastError();
+        });
+        if (r.rc != HOT_OK) break;
+        hipError_t e = hipMemcpyAsync(flags.data(), q.act, nb * sizeof(int), hipMemcpyDeviceToHost, r.s);
+        if (e == hipSuccess) e = hipStreamSynchronize(r.s);
+        if (e != hipSuccess) {
+          p->last_hip = (int)e;
+          r.rc = HOT_E_HIP;
+          break;
+        }
+        int running = 0;
+        for (int m = 0; m < nb; ++m) {
+          if (!live[m]) continue;
+          p->imp_sweeps[G.members[m]] += 1;
+          live[m] = flags[m];
+          running += live[m];
+        }
+        if (running == 0) break;
+      }
+      for (int m = 0; m < nb; ++m)
+        if (live[m]) {
+          p->imp_nonconv[G.members[m]] += 1;
+          stalled = true;
+        }
+      r.pass(PASS_IMP_ADVANCE, [&] { return o.imp_advance(r.s, q.U0, D, G.C, isU, nb, g); });
+      char* t = H2;
+      H2 = H1;
+      H1 = D;
+      D = t;
+    }
+    r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.U0, out0, q.out_tab, G.C, isU, nb, g); });
+  }
+  if (r.rc == HOT_OK && stalled) return HOT_E_NOCONVERGE;
+  return r.rc;
+}
+
 }  // namespace
+
+extern "C" int hot_implicit_stats(hot_plan_t p, int32_t* sweeps, int32_t* nonconv) {
+  if (!p || p->op != HOT_OP_IMPLICIT) return HOT_E_INVALID;
+  for (int i = 0; i < p->batch; ++i) {
+    const bool ran = (int)p->imp_sweeps.size() == p->batch;
+    if (sweeps) sweeps[i] = ran ? p->imp_sweeps[i] : 0;
+    if (nonconv) nonconv[i] = ran ? p->imp_nonconv[i] : 0;
+  }
+  return HOT_OK;
+}
 
 extern "C" int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
                        void* stream) {
@@ -515,6 +638,7 @@ extern "C" int hot_run(hot_plan_t p, void* const* in, void* const* out, void* wo
   if (rc != HOT_OK) return rc;
   rc = ensure_tables(p, in, out, workspace, (hipStream_t)stream);
   if (rc != HOT_OK) return rc;
+  if (p->op == HOT_OP_IMPLICIT) return run_implicit(p, in, out, workspace, nsteps, (hipStream_t)stream);
   return enqueue(p, in, out, workspace, nsteps, (hipStream_t)stream, true);
 }
 
@@ -524,6 +648,7 @@ extern "C" int hot_graph_create(hot_plan_t p, void* const* in, void* const* out,
   if (!graph || !stream) return HOT_E_INVALID;  // the legacy default stream cannot be captured
   int rc = check_run_args(p, in, out, workspace, nsteps);
   if (rc != HOT_OK) return rc;
+  if (p->op == HOT_OP_IMPLICIT) return HOT_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   rc = ensure_tables(p, in, out, workspace, s);
   if (rc != HOT_OK) return rc;
@@ -565,13 +690,13 @@ extern "C" int hot_graph_destroy(hot_graph_t graph) {
   return HOT_OK;
 }
 
-// Autotuner: for every group and strided pass, time each column-width
+// Autotuner: for every group and column-tiled pass, time each column-width
 // variant on the workspace (the passes only read and write workspace
 // buffers, so the caller's data is untouched) and keep the fastest.
 extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t reps) {
   if (!p || reps < 1) return HOT_E_INVALID;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
-  if (p->op != HOT_OP_RHS && p->op != HOT_OP_RK4) return HOT_OK;  // nothing to tune
+  if (p->op != HOT_OP_RHS && p->op != HOT_OP_RK4 && p->op != HOT_OP_IMPLICIT) return HOT_OK;  // nothing to tune
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HOT_E_HIP;
@@ -580,7 +705,7 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
   p->prof = false;
   for (auto& G : p->groups) {
     const GroupPtrs q = group_ptrs(G, workspace);
-    const int pass_ids[3] = {PASS_Y_INV, PASS_Y_FWD, PASS_X_FWD};
+    const int pass_ids[4] = {PASS_X_INV_CURL, PASS_Y_INV, PASS_Y_FWD, PASS_X_FWD};
     for (int pid : pass_ids) {
       float best = 1e30f;
       int best_v = 1;
@@ -596,15 +721,17 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
           const long N = g.N, M = g.M, P = g.Mzp;
           const long isA1 = 6 * G.D1, isA2 = 6 * G.D2, isU = 3 * G.C;
           r.pass(pid, [&] {
+            if (pid == PASS_X_INV_CURL)
+              return G.ops.x_inv_curl(s, v, q.U0, G.C, isU, q.A1, G.D1, isA1, G.B(), g, nullptr);
             if (pid == PASS_Y_INV)
               return G.ops.strided(s, v, +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2, 6,
-                                   isA1, isA2, G.B(), g);
+                                   isA1, isA2, G.B(), g, nullptr);
             if (pid == PASS_Y_FWD)
               return G.ops.strided(s, v, -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1, 3,
-                                   isA2, isA1, G.B(), g);
+                                   isA2, isA1, G.B(), g, nullptr);
             const long Q = M * P;
             return G.ops.strided(s, v, -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3, isA1, isU, G.B(),
-                                 g);
+                                 g, nullptr);
           });
           rc = r.rc;
         }

@@ -54,12 +54,13 @@ constexpr int cols_per_block() {
 // kernel on the stream for nb instances of a batch (instance strides is*)
 // and returns hipGetLastError().
 struct Ops {
+  // act: per-instance flags of an implicit step (NULL: every instance runs)
   hipError_t (*strided)(hipStream_t, int variant, int dir, bool inc, bool outc, const void* in, void* out,
                         long ncols, long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in,
-                        long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo&);
-  hipError_t (*x_inv_curl)(hipStream_t, const void* U, long csU, long isU, void* A, long csA, long isA, int nb,
-                           const Geo&);
-  hipError_t (*z_cross)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&);
+                        long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo&, const int* act);
+  hipError_t (*x_inv_curl)(hipStream_t, int variant, const void* U, long csU, long isU, void* A, long csA, long isA,
+                           int nb, const Geo&, const int* act);
+  hipError_t (*z_cross)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&, const int* act);
   hipError_t (*z_c2r)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
   hipError_t (*z_r2c)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
   hipError_t (*rk_stage)(hipStream_t, const void* Nh, void* U0, void* U1, void* Acc, long C, long is, int nb,
@@ -68,6 +69,12 @@ struct Ops {
                        const Geo&);
   hipError_t (*scatter)(hipStream_t, const void* in, void* out0, void* const* out_tab, long C, long is, int nb,
                         const Geo&);
+  // implicit midpoint step
+  hipError_t (*imp_predict)(hipStream_t, const void* U0, void* D, void* U1, const void* H1, const void* H2, long C,
+                            long is, int nb, const Geo&, int hist, int* act);
+  hipError_t (*imp_update)(hipStream_t, const void* Nh, const void* U0, void* D, void* U1, double* part, long C,
+                           long is, int nb, const Geo&, double nu, double dt, const int* act);
+  hipError_t (*imp_advance)(hipStream_t, void* U0, const void* D, long C, long is, int nb, const Geo&);
   int strided_variants;       // number of column widths the autotuner may pick from
   int strided_width[3];       // columns per block of each variant
 };
@@ -89,27 +96,28 @@ struct Impl {
   // strided column widths the autotuner chooses from: W/2, W, 2W when the
   // block stays within 1024 threads, at least one wave and 160 KB of LDS
   static constexpr bool fits(int w) {
-    return w >= 1 && w * Tl <= 1024 && w * Tl >= 64 && (long)N * w * (long)sizeof(cx<T>) <= 163840;
+    return w >= 1 && w * Tl <= 1024 && w * Tl >= 64 && (long)N * (w + 1) * (long)sizeof(cx<T>) <= 163840;
   }
   static constexpr int WV0 = fits(W / 2) ? W / 2 : W;
   static constexpr int WV2 = fits(2 * W) ? 2 * W : W;
 
   template <int WW, int DIR, bool IC, bool OC>
   static void go(hipStream_t s, const void* in, void* out, long ncols, long Qp, long ld_in, long ld_out, long bs_in,
-                 long bs_out, long cs_in, long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo& g) {
+                 long bs_out, long cs_in, long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo& g,
+                 const int* act) {
     constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
     const long ntiles = (ncols + WW - 1) / WW;
     const long group = 8L * pair;
     dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)ncomp, (unsigned)nb);
     hipLaunchKernelGGL((k_strided<T, P, DIR, WW, IC, OC>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)in, (cx<T>*)out,
-                       ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in, is_out, g);
+                       ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in, is_out, g, act);
   }
   template <int WW>
   static hipError_t strided_w(hipStream_t s, int dir, bool inc, bool outc, const void* in, void* out, long ncols,
                               long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in, long cs_out,
-                              int ncomp, long is_in, long is_out, int nb, const Geo& g) {
+                              int ncomp, long is_in, long is_out, int nb, const Geo& g, const int* act) {
 #define HOT_GO(D, I, O) \
-  go<WW, D, I, O>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, is_in, is_out, nb, g)
+  go<WW, D, I, O>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, is_in, is_out, nb, g, act)
     if (dir > 0) {
       if (inc && !outc) HOT_GO(+1, true, false);
       else if (!inc && !outc) HOT_GO(+1, false, false);
@@ -124,29 +132,39 @@ struct Impl {
   }
   static hipError_t strided(hipStream_t s, int variant, int dir, bool inc, bool outc, const void* in, void* out,
                             long ncols, long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in,
-                            long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo& g) {
+                            long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo& g, const int* act) {
     switch (variant) {
       case 0: return strided_w<WV0>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
-                                    cs_out, ncomp, is_in, is_out, nb, g);
+                                    cs_out, ncomp, is_in, is_out, nb, g, act);
       case 2: return strided_w<WV2>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
-                                    cs_out, ncomp, is_in, is_out, nb, g);
+                                    cs_out, ncomp, is_in, is_out, nb, g, act);
       default: return strided_w<W>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
-                                   cs_out, ncomp, is_in, is_out, nb, g);
+                                   cs_out, ncomp, is_in, is_out, nb, g, act);
     }
   }
-  static hipError_t x_inv_curl(hipStream_t s, const void* U, long csU, long isU, void* A, long csA, long isA, int nb,
-                               const Geo& g) {
+  template <int WW>
+  static hipError_t x_inv_curl_w(hipStream_t s, const void* U, long csU, long isU, void* A, long csA, long isA,
+                                 int nb, const Geo& g, const int* act) {
     const long Q = (long)g.M * g.Mzp;
-    const int ntiles = (int)((Q + W - 1) / W);
-    constexpr int pair = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+    const int ntiles = (int)((Q + WW - 1) / WW);
+    constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
     const unsigned nblk = 8u * 6u * (unsigned)((ntiles + 8 * pair - 1) / (8 * pair) * pair);
-    hipLaunchKernelGGL((k_x_inv_curl<T, P, W>), dim3(nblk, (unsigned)nb), dim3(W * Tl), 0, s, (const cx<T>*)U, csU,
-                       isU, (cx<T>*)A, csA, isA, ntiles, g);
+    hipLaunchKernelGGL((k_x_inv_curl<T, P, WW>), dim3(nblk, (unsigned)nb), dim3(WW * Tl), 0, s, (const cx<T>*)U, csU,
+                       isU, (cx<T>*)A, csA, isA, ntiles, g, act);
     return hipGetLastError();
+  }
+  static hipError_t x_inv_curl(hipStream_t s, int variant, const void* U, long csU, long isU, void* A, long csA,
+                               long isA, int nb, const Geo& g, const int* act) {
+    switch (variant) {
+      case 0: return x_inv_curl_w<WV0>(s, U, csU, isU, A, csA, isA, nb, g, act);
+      case 2: return x_inv_curl_w<WV2>(s, U, csU, isU, A, csA, isA, nb, g, act);
+      default: return x_inv_curl_w<W>(s, U, csU, isU, A, csA, isA, nb, g, act);
+    }
   }
   using PZ = typename LPz<N>::P;
   static constexpr int lines_per_block() { return ZShape<PZ>::LPB; }
-  static hipError_t z_cross(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g) {
+  static hipError_t z_cross(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
+                            const int* act) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const double n3 = double(N) * N * N;
     const T scale = T(1.0 / (n3 * n3));
@@ -154,9 +172,11 @@ struct Impl {
     // coefficients per lane: the 2/3-rule count, or the all-but-Nyquist one
     constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
     if (g.Mz <= KL23 * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale);
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale,
+                         act);
     else if (g.Mz <= KLall * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale);
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale,
+                         act);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
@@ -191,8 +211,26 @@ struct Impl {
                        (cx<T>*)out0, (cx<T>* const*)out_tab, C, is, g);
     return hipGetLastError();
   }
+  static hipError_t imp_predict(hipStream_t s, const void* U0, void* D, void* U1, const void* H1, const void* H2,
+                                long C, long is, int nb, const Geo& g, int hist, int* act) {
+    hipLaunchKernelGGL((k_imp_predict<T>), dim3(grid_1d(C, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)U0,
+                       (cx<T>*)D, (cx<T>*)U1, (const cx<T>*)H1, (const cx<T>*)H2, C, is, g, hist, act);
+    return hipGetLastError();
+  }
+  static hipError_t imp_update(hipStream_t s, const void* Nh, const void* U0, void* D, void* U1, double* part, long C,
+                               long is, int nb, const Geo& g, double nu, double dt, const int* act) {
+    hipLaunchKernelGGL((k_imp_update<T>), dim3(grid_1d(C, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)Nh,
+                       (const cx<T>*)U0, (cx<T>*)D, (cx<T>*)U1, part, C, is, g, T(nu), T(dt), act);
+    return hipGetLastError();
+  }
+  static hipError_t imp_advance(hipStream_t s, void* U0, const void* D, long C, long is, int nb, const Geo& g) {
+    hipLaunchKernelGGL((k_imp_advance<T>), dim3(grid_1d(C, 256), (unsigned)nb), dim3(256), 0, s, (cx<T>*)U0,
+                       (const cx<T>*)D, C, is, g);
+    return hipGetLastError();
+  }
   static Ops ops() {
-    return Ops{&strided, &x_inv_curl, &z_cross, &z_c2r, &z_r2c, &rk_stage, &gather, &scatter, 3, {WV0, W, WV2}};
+    return Ops{&strided,     &x_inv_curl, &z_cross,     &z_c2r, &z_r2c, &rk_stage, &gather, &scatter,
+               &imp_predict, &imp_update, &imp_advance, 3,      {WV0, W, WV2}};
   }
 };
 

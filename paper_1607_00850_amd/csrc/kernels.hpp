@@ -118,6 +118,35 @@ struct ZShape {
   }
 };
 
+// Copy the plan's stage-major twiddles into LDS (once per block).
+template <typename T, class Plan>
+__device__ __forceinline__ void stage_twiddles(cx<T>* tws) {
+  const cx<T>* tab = g_stage_tw<T, Plan>.w;
+  for (int e = threadIdx.x; e < Plan::N; e += blockDim.x) tws[e] = tab[e];
+}
+
+// The same in two halves for blocks of NT threads: fetch() issues the loads,
+// put() writes LDS.  Issuing the pass's data loads in between keeps the two
+// sets of loads in flight together.
+template <typename T, class Plan, int NT>
+struct TwStage {
+  static constexpr int K = (Plan::N + NT - 1) / NT;
+  cx<T> r[K];
+  __device__ __forceinline__ void fetch(int tid) {
+    const cx<T>* tab = g_stage_tw<T, Plan>.w;
+    static_for<0, K>([&](auto t) {
+      const int e = tid + t * NT;
+      r[t] = tab[e < Plan::N ? e : 0];
+    });
+  }
+  __device__ __forceinline__ void put(cx<T>* tws, int tid) const {
+    static_for<0, K>([&](auto t) {
+      const int e = tid + t * NT;
+      if (e < Plan::N) tws[e] = r[t];
+    });
+  }
+};
+
 // Tile of block b when PAIR consecutive tiles share one 128-byte row segment:
 // the tiles of a segment go to blocks with equal b mod 8 (one XCD, one L2),
 // back to back, so the L2 merges their half-line reads and writes.
@@ -143,13 +172,19 @@ template <typename T, class Plan, int DIR, int W, bool IN_C, bool OUT_C>
 __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                          long ncols, long Qp, long ld_in, long ld_out, long bs_in,
                                                          long bs_out, long cs_in, long cs_out, long is_in,
-                                                         long is_out, Geo g) {
+                                                         long is_out, Geo g, const int* __restrict__ act) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
+  __shared__ cx<T> tws[N];
   const long tile = tile_of_block<PAIR>(blockIdx.x);
-  if (tile * W >= ncols) return;  // whole block leaves together
+  if (tile * W >= ncols) return;          // whole block leaves together
+  if (act && !act[blockIdx.z]) return;  // instance no longer iterating
   const int tid = threadIdx.x;
+  // the stage twiddles go to LDS; the first exchange barrier orders them
+  // before their first use
+  TwStage<T, Plan, W * Tl> tw;
+  tw.fetch(tid);
   const int c = tid % W, j = tid / W;
   const long gc = tile * W + c;
   const long b = gc / Qp;
@@ -161,16 +196,19 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
   cx<T> v[R];
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
-    cx<T> x = {T(0), T(0)};
+    // branch-free: load from a valid address, select afterwards
     if (IN_C) {
-      if (valid && kept(p, g)) x = in[ib + (long)crow(p, g) * ld_in];
+      const bool kp = valid && kept(p, g);
+      const cx<T> x = in[ib + (kp ? (long)crow(p, g) * ld_in : 0)];
+      v[s] = kp ? x : cx<T>{T(0), T(0)};
     } else {
-      if (valid) x = in[ib + (long)p * ld_in];
+      const cx<T> x = in[ib + (valid ? (long)p * ld_in : 0)];
+      v[s] = valid ? x : cx<T>{T(0), T(0)};
     }
-    v[s] = x;
   });
+  tw.put(tws, tid);
   LdsCols<T, N, W> lds{sm, c};
-  Plan::template fft<T, DIR>(v, j, lds, TwTab<T>{g_stage_tw<T, Plan>.w});
+  Plan::template fft<T, DIR>(v, j, lds, TwTab<T>{tws});
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
     if (OUT_C) {
@@ -193,17 +231,21 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
 template <typename T, class Plan, int W>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restrict__ U, long csU, long isU,
                                                             cx<T>* __restrict__ A, long csA, long isA,
-                                                            int ntiles, Geo g) {
+                                                            int ntiles, Geo g, const int* __restrict__ act) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
+  __shared__ cx<T> tws[N];
   const int blk = blockIdx.x;
   const int xcd = blk & 7, slot = blk >> 3;
   const int o = slot % 6;
   const int rest = slot / 6;
   const int tile = ((rest / PAIR) * 8 + xcd) * PAIR + rest % PAIR;
-  if (tile >= ntiles) return;  // whole block leaves together
+  if (tile >= ntiles) return;           // whole block leaves together
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
   const int tid = threadIdx.x;
+  TwStage<T, Plan, W * Tl> tw;  // to LDS, ordered before use by the first exchange barrier
+  tw.fetch(tid);
   const int c = tid % W, j = tid / W;
   const long Q = (long)g.M * g.Mzp;
   const long q = (long)tile * W + c;
@@ -215,29 +257,38 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
   const long qq = valid ? q : 0;
   U += blockIdx.y * isU;  // instance of a batch
   A += blockIdx.y * isA;
-  const cx<T>* u0 = U + qq;
-  const cx<T>* u1 = U + csU + qq;
-  const cx<T>* u2 = U + 2 * csU + qq;
+  // Velocity outputs read one component; vorticity outputs two:
+  //   w_x = i (ky u_z - kz u_y), w_y = i (kz u_x - kx u_z), w_z = i (kx u_y - ky u_x).
+  // Every lane loads from a valid address (row 0 when the position is not
+  // retained) and selects afterwards, so that the loads carry no branches and
+  // are all in flight together.
+  const int ca = o < 3 ? o : (o == 3 ? 2 : (o == 4 ? 0 : 1));
+  const int cb = o == 3 ? 1 : (o == 4 ? 2 : 0);
+  const cx<T>* pa = U + ca * csU + qq;
+  const cx<T>* pb = U + cb * csU + qq;
   cx<T> v[R];
-  static_for<0, R>([&](auto s) {
-    const int p = j + s * Tl;
-    cx<T> x = {T(0), T(0)};
-    if (valid && kept(p, g)) {
-      const long off = (long)crow(p, g) * Q;
+  if (o < 3) {
+    static_for<0, R>([&](auto s) {
+      const int p = j + s * Tl;
+      const bool kp = valid && kept(p, g);
+      const cx<T> x = pa[kp ? (long)crow(p, g) * Q : 0];
+      v[s] = kp ? x : cx<T>{T(0), T(0)};
+    });
+  } else {
+    static_for<0, R>([&](auto s) {
+      const int p = j + s * Tl;
+      const bool kp = valid && kept(p, g);
+      const long off = kp ? (long)crow(p, g) * Q : 0;
+      const cx<T> a = pa[off], b = pb[off];
       const T kx = T(kwave(p, N));
-      switch (o) {
-        case 0: x = u0[off]; break;
-        case 1: x = u1[off]; break;
-        case 2: x = u2[off]; break;
-        case 3: x = mul_i(u2[off] * ky - u1[off] * kzf); break;
-        case 4: x = mul_i(u0[off] * kzf - u2[off] * kx); break;
-        default: x = mul_i(u1[off] * kx - u0[off] * ky); break;
-      }
-    }
-    v[s] = x;
-  });
+      const T fa = o == 3 ? ky : (o == 4 ? kzf : kx);
+      const T fb = o == 3 ? kzf : (o == 4 ? kx : ky);
+      v[s] = kp ? mul_i(a * fa - b * fb) : cx<T>{T(0), T(0)};
+    });
+  }
+  tw.put(tws, tid);
   LdsCols<T, N, W> lds{sm, c};
-  Plan::template fft<T, +1>(v, j, lds, TwTab<T>{g_stage_tw<T, Plan>.w});
+  Plan::template fft<T, +1>(v, j, lds, TwTab<T>{tws});
   if (valid) {
     cx<T>* dst = A + o * csA + q;
     static_for<0, R>([&](auto s) { store_stream(dst + (long)(j + s * Tl) * Q, v[s]); });
@@ -296,13 +347,6 @@ __device__ __forceinline__ void load_line(cx<T> (&la)[KL], const cx<T>* __restri
   });
 }
 
-// Copy the plan's stage-major twiddles into LDS (once per block).
-template <typename T, class Plan>
-__device__ __forceinline__ void stage_twiddles(cx<T>* tws) {
-  const cx<T>* tab = g_stage_tw<T, Plan>.w;
-  for (int e = threadIdx.x; e < Plan::N; e += blockDim.x) tws[e] = tab[e];
-}
-
 // ---------------------------------------------------------------------------
 // P3: per z-line, inverse real transforms of u and omega (three complex FFTs,
 // two real lines each), the cross product c = u x omega (component formula of
@@ -313,14 +357,15 @@ __device__ __forceinline__ void stage_twiddles(cx<T>* tws) {
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int KL>
 __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA, long isA, long nlines, Geo g,
-                                                 T scale) {
+                                                 T scale, const int* __restrict__ act) {
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
   constexpr int LS = Plan::line_slots;
   __shared__ cx<T> sm[ZShape<Plan>::SLOTS * LS];
   __shared__ cx<T> tws[N];
-  stage_twiddles<T, Plan>(tws);
-  __syncthreads();
+  TwStage<T, Plan, 256> twst;
+  twst.fetch(threadIdx.x);
   int li, j;
   bool live;
   ZShape<Plan>::place(threadIdx.x, li, j, live);
@@ -335,6 +380,10 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   cx<T> la[KL], lb[KL];
   load_line<T, Plan, KL>(la, A + base, j, Mz, valid);
   load_line<T, Plan, KL>(lb, A + csA + base, j, Mz, valid);
+  // twiddles to LDS while the line loads are in flight (an LDS-only barrier
+  // leaves them in flight)
+  twst.put(tws, threadIdx.x);
+  lds_barrier();
   cx<T> ph[3][R];
   static_for<0, 3>([&](auto pr) {
     put_completed<T, Plan, KL>(lds, la, lb, j, Mz);
@@ -513,6 +562,158 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
     store_stream(U1 + e, a0 + d0 * hu);
     store_stream(U1 + C + e, a1 + d1 * hu);
     store_stream(U1 + 2 * C + e, a2 + d2 * hu);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Implicit midpoint step (Crank-Nicolson on the viscous term), an implicit
+// alternative to the RK4 integration of Sec. 2, solved by Picard sweeps on the
+// increment d = u^{n+1} - u^n:
+//   d <- [dt F_NL(u^n + d/2) - 2 a u^n] / (1 + a),   a = dt nu |k|^2 / 2,
+// with F_NL = Nh - k (k.Nh)/|k|^2, the right-hand side of Eq. NSfinal without
+// its viscous term.  Iterating on d rather than on u^{n+1} keeps the rounding
+// relative to the increment, so the stopping test ||d_new - d|| <= tau ||d_new||
+// stays decidable in FP32 when the increment is far below the state.  Norms
+// are those of the real field: weight 1 on the kz = 0 plane, 2 elsewhere.
+// act[b] == 0 marks an instance whose iteration has stopped; every pass
+// kernel leaves such an instance alone.
+// ---------------------------------------------------------------------------
+
+// Compact element e of a [M][M][Mzp] component: its wavenumbers, or false for
+// row padding.
+struct ModeK {
+  int kx, ky, kz;
+};
+__device__ __forceinline__ bool mode_of(long e, const Geo& g, ModeK& m) {
+  const long MMz = (long)g.M * g.Mzp;
+  const int ix = (int)(e / MMz);
+  const long r = e - ix * MMz;
+  const int iy = (int)(r / g.Mzp);
+  m.kz = (int)(r - (long)iy * g.Mzp);
+  if (m.kz >= g.Mz) return false;
+  m.kx = kwave(cpos(ix, g), g.N);
+  m.ky = kwave(cpos(iy, g), g.N);
+  return true;
+}
+
+// Predictor from the increments of earlier steps (H1 newest): hist = 0: d = 0;
+// 1: d = H1; 2: d = 2 H1 - H2.  Writes d and the midpoint U1 = U0 + d/2, and
+// marks the instance active.
+template <typename T>
+__global__ __launch_bounds__(256) void k_imp_predict(const cx<T>* __restrict__ U0, cx<T>* __restrict__ D,
+                                                     cx<T>* __restrict__ U1, const cx<T>* __restrict__ H1,
+                                                     const cx<T>* __restrict__ H2, long C, long is, Geo g, int hist,
+                                                     int* __restrict__ act) {
+  const long ib = blockIdx.y * is;
+  if (blockIdx.x == 0 && threadIdx.x == 0) act[blockIdx.y] = 1;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < C; e += stride) {
+    ModeK m;
+    if (!mode_of(e, g, m)) continue;
+    for (int c = 0; c < 3; ++c) {
+      const long i = ib + c * C + e;
+      cx<T> d = {T(0), T(0)};
+      if (hist == 1) d = H1[i];
+      if (hist >= 2) d = H1[i] * T(2) - H2[i];
+      D[i] = d;
+      U1[i] = U0[i] + d * T(0.5);
+    }
+  }
+}
+
+// Sum of a double over a 256-thread block (fixed order: deterministic); the
+// result is valid in thread 0.
+__device__ __forceinline__ double block_sum_256(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// One Picard update of d from the nonlinear term Nh of the midpoint, plus the
+// block's partial sums of ||d_new - d||^2 and ||d_new||^2 in part[b][block].
+template <typename T>
+__global__ __launch_bounds__(256) void k_imp_update(const cx<T>* __restrict__ Nh, const cx<T>* __restrict__ U0,
+                                                    cx<T>* __restrict__ D, cx<T>* __restrict__ U1,
+                                                    double* __restrict__ part, long C, long is, Geo g, T nu, T dt,
+                                                    const int* __restrict__ act) {
+  __shared__ double red[4];
+  if (!act[blockIdx.y]) return;  // whole block leaves together
+  const long ib = blockIdx.y * is;
+  const long stride = (long)gridDim.x * blockDim.x;
+  double su = 0.0, si = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < C; e += stride) {
+    ModeK m;
+    if (!mode_of(e, g, m)) continue;
+    const long i0 = ib + e, i1 = i0 + C, i2 = i0 + 2 * C;
+    const int k2i = m.kx * m.kx + m.ky * m.ky + m.kz * m.kz;
+    const T kx = T(m.kx), ky = T(m.ky), kz = T(m.kz);
+    const cx<T> n0 = Nh[i0], n1 = Nh[i1], n2 = Nh[i2];
+    cx<T> kn = {T(0), T(0)};
+    if (k2i != 0) kn = (n0 * kx + n1 * ky + n2 * kz) * (T(1) / T(k2i));
+    const T a = T(0.5) * dt * nu * T(k2i);
+    const T inv = T(1) / (T(1) + a);
+    const cx<T> u0 = U0[i0], u1 = U0[i1], u2 = U0[i2];
+    const cx<T> d0 = ((n0 - kn * kx) * dt - u0 * (T(2) * a)) * inv;
+    const cx<T> d1 = ((n1 - kn * ky) * dt - u1 * (T(2) * a)) * inv;
+    const cx<T> d2 = ((n2 - kn * kz) * dt - u2 * (T(2) * a)) * inv;
+    const cx<T> o0 = D[i0], o1 = D[i1], o2 = D[i2];
+    const double w = m.kz == 0 ? 1.0 : 2.0;
+    const cx<T> e0 = d0 - o0, e1 = d1 - o1, e2 = d2 - o2;
+    su += w * ((double)e0.x * e0.x + (double)e0.y * e0.y + (double)e1.x * e1.x + (double)e1.y * e1.y +
+               (double)e2.x * e2.x + (double)e2.y * e2.y);
+    si += w * ((double)d0.x * d0.x + (double)d0.y * d0.y + (double)d1.x * d1.x + (double)d1.y * d1.y +
+               (double)d2.x * d2.x + (double)d2.y * d2.y);
+    D[i0] = d0;
+    D[i1] = d1;
+    D[i2] = d2;
+    U1[i0] = u0 + d0 * T(0.5);
+    U1[i1] = u1 + d1 * T(0.5);
+    U1[i2] = u2 + d2 * T(0.5);
+  }
+  su = block_sum_256(su, red);
+  si = block_sum_256(si, red);
+  if (threadIdx.x == 0) {
+    double* q = part + 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
+    q[0] = su;
+    q[1] = si;
+  }
+}
+
+// Stopping test of instance blockIdx.x (one wave): sum its nparts partial
+// sums in a fixed order and clear act when ||d_new - d|| <= tau ||d_new||.
+template <int Unused = 0>
+__global__ __launch_bounds__(64) void k_imp_decide(const double* __restrict__ part, int nparts, int* __restrict__ act,
+                                                   double tau2) {
+  const int b = blockIdx.x;
+  if (!act[b]) return;
+  double su = 0.0, si = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 64) {
+    su += part[2 * ((long)b * nparts + i)];
+    si += part[2 * ((long)b * nparts + i) + 1];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    su += __shfl_xor(su, o, 64);
+    si += __shfl_xor(si, o, 64);
+  }
+  if (threadIdx.x == 0 && su <= tau2 * si) act[b] = 0;
+}
+
+// End of a step: U0 += D.
+template <typename T>
+__global__ __launch_bounds__(256) void k_imp_advance(cx<T>* __restrict__ U0, const cx<T>* __restrict__ D, long C,
+                                                     long is, Geo g) {
+  const long ib = blockIdx.y * is;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < C; e += stride) {
+    ModeK m;
+    if (!mode_of(e, g, m)) continue;
+    for (int c = 0; c < 3; ++c) {
+      const long i = ib + c * C + e;
+      U0[i] = U0[i] + D[i];
+    }
   }
 }
 

@@ -74,3 +74,22 @@ def fp32_tol(N, C=10.0):
 def round32(x):
     """The FP32-rounded input, upcast back to FP64 (what the FP32 path sees)."""
     return x.astype(np.complex64).astype(np.complex128) if np.iscomplexobj(x) else x.astype(np.float32).astype(np.float64)
+
+
+def run_implicit(arrays, dtype="f64", nu=0.0, dt=1e-3, nsteps=1, tol=1e-10, max_iter=50, inplace=False,
+                 dealias="two_thirds"):
+    """The implicit step through the C ABI.  Returns (outputs, sweeps per
+    instance, max_iter stops per instance, return code)."""
+    torch = _torch()
+    ns = [a.shape[1] for a in arrays]
+    h, wsb = binding.hot_plan(ns, "implicit", dtype, dealias, nu, dt, tol, max_iter)
+    try:
+        ins = [to_dev(a, dtype) for a in arrays]
+        outs = ins if inplace else [empty_spectral(N, dtype) for N in ns]
+        ws = workspace(wsb)
+        rc = binding.hot_run(h, ins, outs, ws, nsteps)
+        torch.cuda.synchronize()
+        sweeps, nonconv = binding.hot_implicit_stats(h, len(arrays))
+        return [o.cpu().numpy() for o in outs], sweeps, nonconv, rc
+    finally:
+        binding.hot_destroy(h)

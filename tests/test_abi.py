@@ -69,8 +69,10 @@ def test_plan_rejects_bad_descriptor_fields():
     n = (ctypes.c_int32 * 1)(64)
     h = ctypes.c_void_p()
     ws = ctypes.c_size_t()
-    good = dict(abi_version=1, batch=1, n=n, nu=0.0, dt=1e-3, dtype=0, dealias=0, op=3, flags=0)
-    for field, bad in [("abi_version", 2), ("batch", 0), ("dtype", 7), ("dealias", 5), ("op", 9), ("flags", 1)]:
+    good = dict(abi_version=2, batch=1, n=n, nu=0.0, dt=1e-3, dtype=0, dealias=0, op=3, flags=0, tol=1e-6,
+                max_iter=10, reserved=0)
+    for field, bad in [("abi_version", 1), ("batch", 0), ("dtype", 7), ("dealias", 5), ("op", 9), ("flags", 1),
+                       ("reserved", 1)]:
         kw = dict(good)
         kw[field] = bad
         d = binding.HotDesc(**kw)
@@ -163,3 +165,40 @@ def test_batched_workspace_is_the_sum_over_sizes():
     _, w24 = binding.hot_plan([24], "rk4", "f32", nu=0.01, dt=1e-3)
     _, wb = binding.hot_plan([16, 24, 16, 16], "rk4", "f32", nu=0.01, dt=1e-3)
     assert wb >= 3 * w16 + w24 - 4 * 256 * 8 and wb <= 3 * w16 + w24 + 2 * 256 * 8
+
+
+def test_implicit_plan_validation_and_workspace():
+    _expect(binding.HOT_E_INVALID, op="implicit", tol=0.0)
+    _expect(binding.HOT_E_INVALID, op="implicit", tol=float("nan"))
+    _expect(binding.HOT_E_INVALID, op="implicit", max_iter=0)
+    _expect(binding.HOT_E_INVALID, op="implicit", dt=0.0)
+    N, elem = 32, 16
+    K = (N - 1) // 3
+    M, Mz = 2 * K + 1, K + 1
+    C, D1, D2 = M * M * Mz, N * M * Mz, N * N * Mz
+    h, ws = binding.hot_plan(N, "implicit", "f64", nu=0.01, dt=1e-3, tol=1e-8, max_iter=20)
+    binding.hot_destroy(h)
+    nparts = -(-C // 256)
+    base = 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem)
+    assert ws == base + 2 * _align(3 * C * elem) + _align(4) + _align(nparts * 16)
+
+
+def test_implicit_stats_and_graph_rules_without_the_gpu():
+    lib = binding.library()
+    h, _ = binding.hot_plan(16, "rk4", "f64", nu=0.01, dt=1e-3)
+    try:
+        assert lib.hot_implicit_stats(h, None, None) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    h, _ = binding.hot_plan([16, 32], "implicit", "f32", nu=0.01, dt=1e-3, tol=1e-5, max_iter=8)
+    try:
+        # nothing ran yet: zero sweeps
+        assert binding.hot_implicit_stats(h, 2) == ([0, 0], [0, 0])
+        # the sweep count is decided on the host: no graph capture
+        arr = (ctypes.c_void_p * 2)(256 * 1000, 256 * 2000)
+        g = ctypes.c_void_p()
+        rc = lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, ctypes.c_void_p(256), ctypes.byref(g))
+        assert rc == binding.HOT_E_UNSUPPORTED and not g.value
+    finally:
+        binding.hot_destroy(h)
+    assert lib.hot_error_string(binding.HOT_E_NOCONVERGE) != lib.hot_error_string(-99)
