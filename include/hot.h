@@ -77,7 +77,9 @@ extern "C" {
  *       ||d_new - d|| <= tol ||d_new|| (L2 norms of the real field) or
  *       max_iter sweeps.  The first sweep starts from the predictor 0 at the
  *       first step of a call, the previous increment at the second, and the
- *       extrapolation 2 d^{n-1} - d^{n-2} after that.  Each instance stops on
+ *       extrapolation 2 d^{n-1} - d^{n-2} after that (or the surrogate's
+ *       warm start, see hot_set_surrogate; with HOT_FLAG_KEEP_HISTORY the
+ *       history carries over from the previous call).  Each instance stops on
  *       its own.  The call synchronises the stream once per sweep (to read
  *       the stopping flags); it cannot be captured in a graph.  in == out
  *       allowed. */
@@ -86,6 +88,13 @@ extern "C" {
 #define HOT_OP_RHS 2
 #define HOT_OP_RK4 3
 #define HOT_OP_IMPLICIT 4
+
+/* Flags (hot_desc.flags).
+ * KEEP_HISTORY (IMPLICIT only): the increments of earlier steps stay in the
+ * workspace between calls, so a call continues the predictor history of the
+ * previous call on the same plan and workspace; the caller passes the state
+ * that call returned.  Without it every call starts without history. */
+#define HOT_FLAG_KEEP_HISTORY 1
 
 typedef struct hot_desc {
   int32_t abi_version; /* HOT_ABI_VERSION */
@@ -96,7 +105,7 @@ typedef struct hot_desc {
   int32_t dtype;       /* HOT_F64 or HOT_F32 */
   int32_t dealias;     /* HOT_DEALIAS_* (RHS and RK4) */
   int32_t op;          /* HOT_OP_* */
-  int32_t flags;       /* reserved, must be 0 */
+  int32_t flags;       /* HOT_FLAG_* (0 or KEEP_HISTORY for IMPLICIT) */
   double tol;          /* IMPLICIT: relative stopping tolerance (> 0); ignored otherwise */
   int32_t max_iter;    /* IMPLICIT: sweeps per step at most (>= 1); ignored otherwise */
   int32_t reserved;    /* must be 0 */
@@ -159,6 +168,54 @@ int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
  * summed over the call's steps, nonconv[i] = steps that stopped at max_iter.
  * Host only.  Errors: HOT_E_INVALID (null plan, op not IMPLICIT). */
 int hot_implicit_stats(hot_plan_t p, int32_t* sweeps, int32_t* nonconv);
+
+/* ------------------------------------------------------------------------
+ * Per-mode MLP surrogate for the implicit step (not in the paper: Sec. 2
+ * leaves the integrator open, and a Picard iteration needs a starting
+ * guess).  Once two earlier increments D1 (newest) and D2 exist, the first
+ * sweep of a step starts from
+ *     d = 2 D1 - D2 + s MLP(f),   s = ||D1_k|| over the 3 complex components,
+ * instead of the plain extrapolation 2 D1 - D2.  MLP: 32 -> 256 -> 256 ->
+ * 256 -> 6, tanh hidden layers, BF16 MFMA operands with FP32 accumulation.
+ * Features f of mode k, a = dt nu |k|^2 / 2 (all 0 when s = 0):
+ *   f[0:6] D1/s, f[6:12] D2/s, f[12:18] ((1 - a) D1 + 2 a u)/s,
+ *   f[18:24] u/||u_k||, f[24] s/||u_k||, f[25:28] k/N, f[28] a, f[29:32] 0
+ * (re, im of components x, y, z; u the state at the start of the step).
+ * The output y holds the correction in the same (re, im) x 3 order.
+ *
+ * Parameters: one device FP32 vector of hot_mlp_param_count() values,
+ *   W1[256][32] b1[256] W2[256][256] b2[256] W3[256][256] b3[256]
+ *   W4[6][256] b4[6]    (weights W[out][in], row-major).
+ * All pointers are device pointers, 16-byte aligned (workspaces 256). */
+
+/* Number of FP32 parameters, and bytes of the packed inference copy. */
+int32_t hot_mlp_param_count(void);
+size_t hot_mlp_packed_bytes(void);
+
+/* params -> packed (BF16 weights, FP32 biases), enqueued on stream. */
+int hot_mlp_pack(const float* params, void* packed, void* stream);
+
+/* y[rows][6] = MLP(x[rows][32]) with the packed parameters (the fused
+ * inference kernel the implicit step uses).  Errors: HOT_E_INVALID. */
+int hot_mlp_forward(const void* packed, const float* x, float* y, int64_t rows, void* stream);
+
+/* Training.  hot_mlp_grad: mean squared error of MLP(x) against t[rows][6]
+ * into *loss (device float) and its gradient with respect to params into
+ * grad (hot_mlp_param_count floats), by backpropagation with BF16 MFMA
+ * products; ws: device workspace of hot_mlp_train_bytes(rows) bytes.
+ * hot_mlp_adam: one bias-corrected Adam update (step >= 1) of params with
+ * moment buffers m, v (param_count floats each, zero before step 1). */
+size_t hot_mlp_train_bytes(int32_t rows);
+int hot_mlp_grad(const float* params, const float* x, const float* t, int32_t rows, float* grad, float* loss,
+                 void* ws, void* stream);
+int hot_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                 float beta2, float eps, void* stream);
+
+/* Use the packed surrogate (hot_mlp_pack output, device memory the caller
+ * keeps alive) for the warm start of an IMPLICIT plan's later hot_run calls;
+ * NULL returns to the plain extrapolation.  Host only.
+ * Errors: HOT_E_INVALID (null plan, op not IMPLICIT, misaligned pointer). */
+int hot_set_surrogate(hot_plan_t p, const void* packed);
 
 /* Release the plan's host state (waits for its pending profiling events).
  * NULL is accepted and ignored. */

@@ -24,6 +24,8 @@ HOT_F64, HOT_F32 = 0, 1
 HOT_DEALIAS_TWO_THIRDS, HOT_DEALIAS_NONE = 0, 1
 HOT_OP_R2C, HOT_OP_C2R, HOT_OP_RHS, HOT_OP_RK4, HOT_OP_IMPLICIT = 0, 1, 2, 3, 4
 
+HOT_FLAG_KEEP_HISTORY = 1
+
 DTYPES = {"f64": HOT_F64, "f32": HOT_F32}
 DEALIAS = {"two_thirds": HOT_DEALIAS_TWO_THIRDS, "none": HOT_DEALIAS_NONE}
 OPS = {"r2c": HOT_OP_R2C, "c2r": HOT_OP_C2R, "rhs": HOT_OP_RHS, "rk4": HOT_OP_RK4, "implicit": HOT_OP_IMPLICIT}
@@ -97,6 +99,23 @@ def _lib():
         lib.hot_tuned_width.restype = ctypes.c_int
         lib.hot_implicit_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.hot_implicit_stats.restype = ctypes.c_int
+        lib.hot_set_surrogate.argtypes = [vp, vp]
+        lib.hot_set_surrogate.restype = ctypes.c_int
+        lib.hot_mlp_param_count.argtypes = []
+        lib.hot_mlp_param_count.restype = i32
+        lib.hot_mlp_packed_bytes.argtypes = []
+        lib.hot_mlp_packed_bytes.restype = sz
+        lib.hot_mlp_pack.argtypes = [vp, vp, vp]
+        lib.hot_mlp_pack.restype = ctypes.c_int
+        lib.hot_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+        lib.hot_mlp_forward.restype = ctypes.c_int
+        lib.hot_mlp_train_bytes.argtypes = [i32]
+        lib.hot_mlp_train_bytes.restype = sz
+        lib.hot_mlp_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+        lib.hot_mlp_grad.restype = ctypes.c_int
+        lib.hot_mlp_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, vp]
+        lib.hot_mlp_adam.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -106,13 +125,15 @@ def library():
     return _lib()
 
 
-def hot_plan(n, op, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0, tol=1e-10, max_iter=50):
+def hot_plan(n, op, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0, tol=1e-10, max_iter=50,
+             keep_history=False):
     """Plan an operation; returns (handle, workspace_bytes).  n: int or list.
-    tol, max_iter: stopping rule of the implicit step (ignored otherwise)."""
+    tol, max_iter, keep_history: the implicit step (ignored otherwise)."""
     ns = [int(n)] if isinstance(n, int) else [int(v) for v in n]
     arr = (ctypes.c_int32 * len(ns))(*ns)
-    d = HotDesc(HOT_ABI_VERSION, len(ns), arr, float(nu), float(dt), DTYPES[dtype], DEALIAS[dealias], OPS[op], 0,
-                float(tol), int(max_iter), 0)
+    flags = HOT_FLAG_KEEP_HISTORY if keep_history else 0
+    d = HotDesc(HOT_ABI_VERSION, len(ns), arr, float(nu), float(dt), DTYPES[dtype], DEALIAS[dealias], OPS[op],
+                flags, float(tol), int(max_iter), 0)
     h = ctypes.c_void_p()
     ws = ctypes.c_size_t()
     rc = _lib().hot_plan(ctypes.byref(d), ctypes.byref(h), ctypes.byref(ws))
@@ -156,6 +177,7 @@ def hot_run(plan, ins, outs, workspace, nsteps=0, stream=None):
 
 def hot_destroy(plan):
     _lib().hot_destroy(plan)
+    _KEEP.pop(plan.value, None)
 
 
 def hot_profile_enable(plan, enable=True):
@@ -253,3 +275,52 @@ def hot_implicit_stats(plan, batch):
     if rc != HOT_OK:
         raise HotError(rc, "hot_implicit_stats")
     return list(sw), list(nc)
+
+
+_KEEP = {}  # plan handle -> packed surrogate tensor the plan points to
+
+
+def hot_set_surrogate(plan, packed):
+    """Warm-start an implicit plan with a packed MLP (device tensor or
+    pointer; None for the plain extrapolation).  The plan keeps only the
+    pointer, so a tensor passed here is held until the plan is destroyed or
+    given another surrogate."""
+    rc = _lib().hot_set_surrogate(plan, _ptr(packed))
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_set_surrogate")
+    _KEEP[plan.value] = packed
+
+
+def hot_mlp_param_count():
+    return int(_lib().hot_mlp_param_count())
+
+
+def hot_mlp_packed_bytes():
+    return int(_lib().hot_mlp_packed_bytes())
+
+
+def hot_mlp_train_bytes(rows):
+    return int(_lib().hot_mlp_train_bytes(int(rows)))
+
+
+def _check(rc, where):
+    if rc != HOT_OK:
+        raise HotError(rc, where)
+
+
+def hot_mlp_pack(params, packed, stream=None):
+    _check(_lib().hot_mlp_pack(_ptr(params), _ptr(packed), _stream(stream)), "hot_mlp_pack")
+
+
+def hot_mlp_forward(packed, x, y, rows, stream=None):
+    _check(_lib().hot_mlp_forward(_ptr(packed), _ptr(x), _ptr(y), int(rows), _stream(stream)), "hot_mlp_forward")
+
+
+def hot_mlp_grad(params, x, t, rows, grad, loss, workspace, stream=None):
+    _check(_lib().hot_mlp_grad(_ptr(params), _ptr(x), _ptr(t), int(rows), _ptr(grad), _ptr(loss), _ptr(workspace),
+                               _stream(stream)), "hot_mlp_grad")
+
+
+def hot_mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_lib().hot_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                               float(beta2), float(eps), _stream(stream)), "hot_mlp_adam")

@@ -10,6 +10,7 @@
 
 #include "../../include/hot.h"
 #include "impl.hpp"
+#include "mlp_launch.hpp"
 
 namespace hot {
 
@@ -101,6 +102,7 @@ struct Group {
   size_t oU0 = 0, oU1 = 0, oAcc = 0, oNh = 0, oA1 = 0, oA2 = 0, oTab = 0;
   size_t oH[2] = {0, 0}, oAct = 0, oPart = 0;  // implicit step only
   int nparts = 0;                             // blocks of the implicit update
+  int rot = 0, hist = 0;                      // implicit step: buffer rotation, history depth
   size_t bytes = 0;
   int variant[NUM_PASSES];  // strided column-width variant per pass (autotuned)
   int B() const { return (int)members.size(); }
@@ -116,6 +118,9 @@ struct hot_plan_s {
   double tol;    // implicit step: stopping tolerance
   int max_iter;  // implicit step: sweeps per step at most
   std::vector<int> imp_sweeps, imp_nonconv;  // implicit step: last call, per instance
+  int flags = 0;
+  const void* surrogate = nullptr;  // packed MLP for the implicit warm start
+  void* hist_ws = nullptr;          // workspace holding the kept history
   size_t elem;  // bytes per complex element
   int batch;
   std::vector<int> n;
@@ -162,7 +167,8 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
   if (d->dtype != HOT_F64 && d->dtype != HOT_F32) return HOT_E_INVALID;
   if (d->op < HOT_OP_R2C || d->op > HOT_OP_IMPLICIT) return HOT_E_INVALID;
   if (d->dealias != HOT_DEALIAS_TWO_THIRDS && d->dealias != HOT_DEALIAS_NONE) return HOT_E_INVALID;
-  if (d->flags != 0 || d->reserved != 0) return HOT_E_INVALID;
+  if (d->reserved != 0) return HOT_E_INVALID;
+  if (d->flags != 0 && !(d->op == HOT_OP_IMPLICIT && d->flags == HOT_FLAG_KEEP_HISTORY)) return HOT_E_INVALID;
   if (!(d->nu >= 0.0)) return HOT_E_INVALID;  // also rejects NaN
   if ((d->op == HOT_OP_RK4 || d->op == HOT_OP_IMPLICIT) && !(d->dt > 0.0)) return HOT_E_INVALID;
   if (d->op == HOT_OP_IMPLICIT && (!(d->tol > 0.0) || d->max_iter < 1)) return HOT_E_INVALID;
@@ -179,6 +185,7 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
   p->dt = d->dt;
   p->tol = d->tol;
   p->max_iter = d->max_iter;
+  p->flags = d->flags;
   p->elem = d->dtype == HOT_F64 ? 16 : 8;
   p->batch = d->batch;
   p->n.assign(d->n, d->n + d->batch);
@@ -559,8 +566,13 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
   p->imp_nonconv.assign(p->batch, 0);
   bool stalled = false;
   std::vector<int> flags, live;
-  for (const auto& G : p->groups) {
+  const bool keep = (p->flags & HOT_FLAG_KEEP_HISTORY) && p->hist_ws == workspace;
+  for (auto& G : p->groups) {
     if (r.rc != HOT_OK) break;
+    if (!keep) {
+      G.rot = 0;
+      G.hist = 0;
+    }
     const GroupPtrs q = group_ptrs(G, workspace);
     const Ops& o = G.ops;
     const Geo& g = G.g;
@@ -569,12 +581,23 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
     const void* in0 = in[G.members[0]];
     void* out0 = out[G.members[0]];
     r.pass(PASS_GATHER, [&] { return o.gather(r.s, in0, q.in_tab, q.U0, G.C, isU, nb, g); });
-    char *D = q.Acc, *H1 = q.H[0], *H2 = q.H[1];
+    // the iterate d and the histories H1 (newest), H2 rotate through three buffers
+    char* buf[3] = {q.Acc, q.H[0], q.H[1]};
     flags.assign(nb, 0);
     for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
-      const int hist = step < 2 ? step : 2;
-      r.pass(PASS_IMP_PREDICT,
-             [&] { return o.imp_predict(r.s, q.U0, D, q.U1, H1, H2, G.C, isU, nb, g, hist, q.act); });
+      char *D = buf[G.rot], *H1 = buf[(G.rot + 1) % 3], *H2 = buf[(G.rot + 2) % 3];
+      const int hist = G.hist;
+      if (hist == 2 && p->surrogate)
+        r.pass(PASS_IMP_PREDICT, [&] {
+          return p->dtype == HOT_F64
+                     ? mlp_predict<double>(r.s, p->surrogate, q.U0, H1, H2, D, q.U1, q.act, G.C, isU, nb, g, p->nu,
+                                           p->dt)
+                     : mlp_predict<float>(r.s, p->surrogate, q.U0, H1, H2, D, q.U1, q.act, G.C, isU, nb, g, p->nu,
+                                          p->dt);
+        });
+      else
+        r.pass(PASS_IMP_PREDICT,
+               [&] { return o.imp_predict(r.s, q.U0, D, q.U1, H1, H2, G.C, isU, nb, g, hist, q.act); });
       live.assign(nb, 1);
       for (int sw = 0; sw < p->max_iter && r.rc == HOT_OK; ++sw) {
         rhs_passes(r, G, q, q.U1, q.act);
@@ -609,18 +632,23 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
           stalled = true;
         }
       r.pass(PASS_IMP_ADVANCE, [&] { return o.imp_advance(r.s, q.U0, D, G.C, isU, nb, g); });
-      char* t = H2;
-      H2 = H1;
-      H1 = D;
-      D = t;
+      G.rot = (G.rot + 2) % 3;  // d becomes H1, H1 becomes H2, H2's buffer the next d
+      if (G.hist < 2) ++G.hist;
     }
     r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.U0, out0, q.out_tab, G.C, isU, nb, g); });
   }
+  p->hist_ws = workspace;
   if (r.rc == HOT_OK && stalled) return HOT_E_NOCONVERGE;
   return r.rc;
 }
 
 }  // namespace
+
+extern "C" int hot_set_surrogate(hot_plan_t p, const void* packed) {
+  if (!p || p->op != HOT_OP_IMPLICIT || ((uintptr_t)packed & 15) != 0) return HOT_E_INVALID;
+  p->surrogate = packed;
+  return HOT_OK;
+}
 
 extern "C" int hot_implicit_stats(hot_plan_t p, int32_t* sweeps, int32_t* nonconv) {
   if (!p || p->op != HOT_OP_IMPLICIT) return HOT_E_INVALID;

@@ -202,3 +202,28 @@ def test_implicit_stats_and_graph_rules_without_the_gpu():
     finally:
         binding.hot_destroy(h)
     assert lib.hot_error_string(binding.HOT_E_NOCONVERGE) != lib.hot_error_string(-99)
+
+
+def test_mlp_sizes_and_surrogate_rules_without_the_gpu():
+    import oracle
+    lib = binding.library()
+    assert binding.hot_mlp_param_count() == oracle.mlp_param_count()
+    # BF16 weights (the output layer padded to 16 rows) and FP32 biases (b4 padded to 16)
+    assert binding.hot_mlp_packed_bytes() == 2 * (256 * 32 + 2 * 256 * 256 + 16 * 256) + 4 * (3 * 256 + 16)
+    assert binding.hot_mlp_train_bytes(0) == 0
+    assert binding.hot_mlp_train_bytes(1000) > 5 * 1000 * 256 * 4
+    h, _ = binding.hot_plan(16, "rk4", "f64", nu=0.01, dt=1e-3)
+    try:
+        assert lib.hot_set_surrogate(h, ctypes.c_void_p(256)) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    h, _ = binding.hot_plan(16, "implicit", "f64", nu=0.01, dt=1e-3, keep_history=True)
+    try:
+        assert lib.hot_set_surrogate(h, ctypes.c_void_p(256 + 8)) == binding.HOT_E_INVALID
+        assert lib.hot_set_surrogate(h, ctypes.c_void_p(256)) == binding.HOT_OK
+        assert lib.hot_set_surrogate(h, None) == binding.HOT_OK
+    finally:
+        binding.hot_destroy(h)
+    _expect(binding.HOT_E_INVALID, op="rk4", keep_history=True)
+    assert lib.hot_mlp_forward(None, None, None, 1, None) == binding.HOT_E_INVALID
+    assert lib.hot_mlp_adam(None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, None) == binding.HOT_E_INVALID

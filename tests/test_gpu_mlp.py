@@ -1,0 +1,204 @@
+"""GPU parity of the MLP surrogate kernels (BF16 MFMA, FP32 accumulation)
+against the FP64 reference, through the C ABI.
+
+The reference runs in its BF16 mode: every product operand rounded to
+bfloat16 at the points where the kernels round theirs, products summed in
+FP64 (FP32 on the GPU).  What remains is FP32 accumulation order and the
+rare BF16 rounding flip of an operand that differs in its last FP32 bits,
+so the bars are 1e-3 (relative L2) for outputs and gradients and 1e-5 for
+the loss.  Against the plain FP64 reference the BF16 arithmetic itself
+shows (a few 1e-3), bounded at 5e-2.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_00850_amd import binding, inputs
+from hotrun import run_implicit, to_dev, workspace
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev32(x):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _packed(theta):
+    torch = _torch()
+    pk = torch.empty(binding.hot_mlp_packed_bytes(), dtype=torch.uint8, device="cuda")
+    binding.hot_mlp_pack(_dev32(theta), pk)
+    return pk
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("rows", [1, 255, 1000])
+def test_fused_forward_matches_reference(rows):
+    print(f"mlp forward rows={rows}", flush=True)
+    torch = _torch()
+    rng = np.random.default_rng(rows)
+    theta = oracle.mlp_init(7) * 2.0
+    theta = theta.astype(np.float32).astype(np.float64)
+    X = rng.standard_normal((rows, 32))
+    X32 = X.astype(np.float32).astype(np.float64)
+    y = torch.empty((rows, 6), dtype=torch.float32, device="cuda")
+    binding.hot_mlp_forward(_packed(theta), _dev32(X), y, rows)
+    got = y.cpu().numpy().astype(np.float64)
+    ref, _ = oracle.mlp_forward(theta, X32, bf16=True)
+    assert _rel(got, ref) < 1e-3
+    ref64, _ = oracle.mlp_forward(theta, X32)
+    assert _rel(got, ref64) < 5e-2
+
+
+@pytest.mark.parametrize("rows", [64, 300])
+def test_gradient_matches_reference(rows):
+    print(f"mlp grad rows={rows}", flush=True)
+    torch = _torch()
+    rng = np.random.default_rng(100 + rows)
+    theta = (oracle.mlp_init(8) * 2.0).astype(np.float32).astype(np.float64)
+    X = rng.standard_normal((rows, 32)).astype(np.float32).astype(np.float64)
+    T = rng.standard_normal((rows, 6)).astype(np.float32).astype(np.float64)
+    P = binding.hot_mlp_param_count()
+    grad = torch.empty(P, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    ws = workspace(binding.hot_mlp_train_bytes(rows))
+    binding.hot_mlp_grad(_dev32(theta), _dev32(X), _dev32(T), rows, grad, loss, ws)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    l_ref, g_ref = oracle.mlp_loss_grad(theta, X, T, bf16=True)
+    assert abs(float(loss.item()) - l_ref) <= 1e-5 * l_ref
+    # every parameter block on its own
+    o = 0
+    for name, shape in oracle.mlp_shapes():
+        n = int(np.prod(shape))
+        assert _rel(g[o:o + n], g_ref[o:o + n]) < 1e-3, name
+        o += n
+    _, g64 = oracle.mlp_loss_grad(theta, X, T)
+    assert _rel(g, g64) < 5e-2
+
+
+def test_adam_matches_reference():
+    torch = _torch()
+    P = binding.hot_mlp_param_count()
+    rng = np.random.default_rng(3)
+    th, g, m, v = (rng.standard_normal(P) for _ in range(4))
+    v = np.abs(v)
+    dth, dg, dm, dv = (_dev32(a) for a in (th, g, m, v))
+    binding.hot_mlp_adam(dth, dg, dm, dv, 5, 1e-2)
+    torch.cuda.synchronize()
+    r_th, r_m, r_v = oracle.adam_step(*(a.astype(np.float32).astype(np.float64) for a in (th, g, m, v)), 5, 1e-2)
+    assert _rel(dth.cpu().numpy(), r_th) < 1e-6
+    assert _rel(dm.cpu().numpy(), r_m) < 1e-6
+    assert _rel(dv.cpu().numpy(), r_v) < 1e-6
+
+
+def test_training_reduces_the_loss():
+    # a smooth synthetic regression: 400 Adam steps must cut the loss by 10x
+    torch = _torch()
+    rng = np.random.default_rng(11)
+    rows = 2048
+    X = rng.standard_normal((rows, 32)) * 0.5
+    A = rng.standard_normal((32, 6)) / 6
+    T = np.tanh(X @ A) + 0.1 * np.sin(3 * X[:, :6])
+    P = binding.hot_mlp_param_count()
+    th = _dev32(oracle.mlp_init(12))
+    grad = torch.empty(P, dtype=torch.float32, device="cuda")
+    m = torch.zeros(P, dtype=torch.float32, device="cuda")
+    v = torch.zeros(P, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    ws = workspace(binding.hot_mlp_train_bytes(rows))
+    dX, dT = _dev32(X), _dev32(T)
+    losses = []
+    for step in range(1, 401):
+        binding.hot_mlp_grad(th, dX, dT, rows, grad, loss, ws)
+        if step == 1 or step == 400:
+            losses.append(float(loss.item()))
+        binding.hot_mlp_adam(th, grad, m, v, step, 1e-3)
+    assert losses[1] < 0.1 * losses[0], losses
+
+
+def test_surrogate_prediction_after_one_capped_sweep():
+    # max_iter = 1: every step is one sweep from its predictor, so the third
+    # step's result shows the surrogate's warm start (features, network and
+    # prediction) through one sweep; the oracle replays the same sequence
+    N, nu, dt = 16, 1.0 / 1600, 0.02
+    u0 = inputs.smooth_random(N, 21) * 4.0
+    theta = (oracle.mlp_init(13) * 1.5).astype(np.float32).astype(np.float64)
+    torch = _torch()
+    pk = _packed(theta)
+    h, wsb = binding.hot_plan(N, "implicit", "f64", nu=nu, dt=dt, tol=1e-12, max_iter=1)
+    try:
+        binding.hot_set_surrogate(h, pk)
+        x = to_dev(u0, "f64")
+        y = torch.empty_like(x)
+        rc = binding.hot_run(h, [x], [y], workspace(wsb), 3)
+        torch.cuda.synchronize()
+        assert rc == binding.HOT_E_NOCONVERGE
+        assert binding.hot_implicit_stats(h, 1) == ([3], [3])
+    finally:
+        binding.hot_destroy(h)
+    u, hist = u0 * oracle.retained_mask(N), []
+    for step in range(3):
+        if step < 2:
+            pred = oracle.extrapolation_predictor(u, hist)
+        else:
+            pred = u + oracle.surrogate_predict(theta, u, hist[-1], hist[-2], nu, dt, bf16=True)
+        u1, _, _, _ = oracle.implicit_midpoint_step(u, nu, dt, 1e-12, 1, pred)
+        hist.append(u1 - u)
+        u = u1
+    got = y.cpu().numpy()
+    assert np.linalg.norm(got - u) <= 1e-4 * np.linalg.norm(hist[-1])
+    # the surrogate changed the third step: it differs from the plain path
+    (plain,), _, _, _ = run_implicit([u0], "f64", nu, dt, 3, 1e-12, 1)
+    assert np.linalg.norm(plain - got) > 1e-3 * np.linalg.norm(hist[-1])
+
+
+def test_surrogate_warm_started_steps_converge_to_the_oracle():
+    N, nu, dt, tol = 24, 1.0 / 1600, 0.02, 1e-10
+    u0 = inputs.rough_random(N, 22) * 3.0
+    theta = (oracle.mlp_init(14) * 0.5).astype(np.float32).astype(np.float64)
+    torch = _torch()
+    h, wsb = binding.hot_plan(N, "implicit", "f64", nu=nu, dt=dt, tol=tol, max_iter=60)
+    pk = _packed(theta)  # the plan keeps only the pointer: the caller keeps the buffer alive
+    try:
+        binding.hot_set_surrogate(h, pk)
+        x = to_dev(u0, "f64")
+        y = torch.empty_like(x)
+        assert binding.hot_run(h, [x], [y], workspace(wsb), 4) == binding.HOT_OK
+        torch.cuda.synchronize()
+    finally:
+        binding.hot_destroy(h)
+    ref, _, incs, _ = oracle.implicit_midpoint(u0, nu, dt, 4, 1e-13)
+    err = np.linalg.norm(y.cpu().numpy() - ref)
+    assert err <= 1e-12 * np.linalg.norm(ref) + 10 * tol * sum(np.linalg.norm(d) for d in incs)
+
+
+def test_keep_history_continues_bitwise():
+    N, nu, dt = 24, 1.0 / 1600, 0.02
+    u0 = inputs.rough_random(N, 31) * 3.0
+    torch = _torch()
+    (one,), s_one, _, _ = run_implicit([u0], "f64", nu, dt, 4, 1e-10)
+    h, wsb = binding.hot_plan(N, "implicit", "f64", nu=nu, dt=dt, tol=1e-10, max_iter=50, keep_history=True)
+    try:
+        ws = workspace(wsb)
+        x = to_dev(u0, "f64")
+        y = torch.empty_like(x)
+        binding.hot_run(h, [x], [y], ws, 2)
+        s_a, _ = binding.hot_implicit_stats(h, 1)
+        z = torch.empty_like(x)
+        binding.hot_run(h, [y], [z], ws, 2)
+        s_b, _ = binding.hot_implicit_stats(h, 1)
+        torch.cuda.synchronize()
+        two = z.cpu().numpy()
+    finally:
+        binding.hot_destroy(h)
+    np.testing.assert_array_equal(two, one)
+    assert s_a[0] + s_b[0] == s_one[0]
