@@ -33,9 +33,10 @@ DT = 1e-3          # Sec. 4
 
 
 def source_hash():
+    """Hash of the sources of the right-hand-side and RK4 kernels."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1607_00850_amd", "csrc", "*"))):
-        h.update(open(p, "rb").read())
+    for name in ("fft_core.hpp", "kernels.hpp", "impl.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1607_00850_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -119,18 +120,24 @@ def _r1_modes(args):
     return inputs.smooth_random_modes(N, seed)
 
 
-def batch_fields(sizes, dtype, first_seed=1000):
-    """R1 (seed first_seed + i) for every instance, laid out per size in one
-    device buffer with 256-byte aligned instance slices."""
+def batch_modes(sizes, first_seed=1000):
+    """R1 modes (seed first_seed + i) of every instance, generated by a
+    process pool; call before the process touches the GPU."""
     import concurrent.futures
 
+    with concurrent.futures.ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(_r1_modes, [(int(N), first_seed + i) for i, N in enumerate(sizes)], chunksize=64))
+
+
+def batch_fields(sizes, dtype, first_seed=1000, modes=None):
+    """R1 (seed first_seed + i) for every instance, laid out per size in one
+    device buffer with 256-byte aligned instance slices."""
     import numpy as np
     import torch
 
-    cdt = torch.complex64 if dtype == "f32" else torch.complex128
     esz = 8 if dtype == "f32" else 16
-    with concurrent.futures.ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
-        modes = list(ex.map(_r1_modes, [(int(N), first_seed + i) for i, N in enumerate(sizes)], chunksize=64))
+    if modes is None:
+        modes = batch_modes(sizes, first_seed)
     ins, outs, keep = [None] * len(sizes), [None] * len(sizes), []
     for N in sorted(set(int(v) for v in sizes)):
         idx = [i for i, v in enumerate(sizes) if int(v) == N]
@@ -257,6 +264,215 @@ def bench_batch(a):
     del keep
 
 
+IMP_DT = 1e-2  # implicit step: 10x the RK4 step of Sec. 4
+BF16_PEAK_TFLOPS = 2500.0
+MLP_FLOP_PER_ROW = 2 * (32 * 256 + 2 * 256 * 256 + 256 * 16)  # the output layer runs 16 padded columns
+
+
+def _implicit_trajectory(binding, torch, N, seed, nsteps, nu, dt):
+    """States u_0 .. u_nsteps of one R1 field (FP64, tol 1e-12) from the
+    GPU implicit solver, one hot_run call per step with the history kept."""
+    from paper_1607_00850_amd import inputs
+
+    u = torch.from_numpy(inputs.smooth_random(N, seed)).to("cuda")
+    h, wsb = binding.hot_plan(N, "implicit", "f64", "two_thirds", nu, dt, 1e-12, 100, keep_history=True)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    states = []
+    try:
+        cur = torch.empty_like(u)
+        binding.hot_run(h, [u], [cur], ws, 0)  # projection onto the retained set
+        states.append(cur.clone())
+        for _ in range(nsteps):
+            binding.hot_run(h, [cur], [cur], ws, 1)
+            states.append(cur.clone())
+        torch.cuda.synchronize()
+    finally:
+        binding.hot_destroy(h)
+    return states
+
+
+def _dataset(binding, torch, fields, nu, dt):
+    """Training rows of the third step of each (N, seed) trajectory."""
+    xs, ts, ss = [], [], []
+    for N, sd in fields:
+        N = int(N)
+        rows = binding.hot_mlp_dataset_rows(N)
+        u = _implicit_trajectory(binding, torch, N, sd, 3, nu, dt)
+        d2, d1, d = u[1] - u[0], u[2] - u[1], u[3] - u[2]
+        x = torch.empty((rows, 32), dtype=torch.float32, device="cuda")
+        t = torch.empty((rows, 6), dtype=torch.float32, device="cuda")
+        sc = torch.empty(rows, dtype=torch.float32, device="cuda")
+        binding.hot_mlp_dataset(N, "f64", u[2], d1, d2, d, nu, dt, x, t, sc)
+        xs.append(x)
+        ts.append(t)
+        ss.append(sc / torch.linalg.vector_norm(sc))  # each field weighs the same (coefficients scale as N^3)
+    torch.cuda.synchronize()
+    return torch.cat(xs), torch.cat(ts), torch.cat(ss)
+
+
+def bench_surrogate(a):
+    """MLP surrogate for the implicit step: train it on GPU trajectories at
+    N = 64, then compare plain and surrogate-assisted implicit steps on a
+    batch of uneven instances at the same tolerance."""
+    import numpy as np
+    import torch
+
+    from paper_1607_00850_amd import binding, inputs
+
+    nu, dt, tol = NU, IMP_DT, 1e-5
+    sizes = inputs.batch_sizes(a.surrogate_batch, 0)
+    modes = batch_modes(sizes)  # host work first: the pool forks before any GPU call
+    # ---- training data: trajectories of the batch's size law (sizes drawn
+    # with seed 1, fields seeds 10000+i) or N = 64 only; held out: sizes
+    # drawn with seed 2 (fields 20000+i) and two N = 64 fields
+    t0 = time.perf_counter()
+    if a.train_sizes == "batch":
+        train = list(zip(inputs.batch_sizes(a.train_fields, 1), range(10000, 10000 + a.train_fields)))
+    else:
+        train = [(64, 10000 + i) for i in range(a.train_fields)]
+    X, T, S = _dataset(binding, torch, train, nu, dt)
+    held = list(zip(inputs.batch_sizes(20, 2), range(20000, 20020)))
+    Xv, Tv, Sv = _dataset(binding, torch, held, nu, dt)
+    Xv64, Tv64, Sv64 = _dataset(binding, torch, [(64, 20100), (64, 20101)], nu, dt)
+    # rows are drawn with probability proportional to s^2: the stopping test
+    # measures the increment's error in the field's L2 norm, where a mode's
+    # error counts as s * |y - t|
+    wrow = (S.double() ** 2)
+    wrow = wrow / wrow.sum()
+    t_data = time.perf_counter() - t0
+    rows = X.shape[0]
+    # ---- training (FP32 master weights, BF16 MFMA products, Adam)
+    P = binding.hot_mlp_param_count()
+    rng = np.random.default_rng(0)
+    blocks = []
+    for fo, fi in ((256, 32), (256, 256), (256, 256), (6, 256)):  # W uniform +-1/sqrt(fan_in), b zero
+        blocks += [rng.uniform(-1 / np.sqrt(fi), 1 / np.sqrt(fi), size=fo * fi), np.zeros(fo)]
+    theta = np.concatenate(blocks).astype(np.float32)
+    assert theta.size == P
+    th = torch.from_numpy(theta).cuda()
+    grad = torch.empty(P, dtype=torch.float32, device="cuda")
+    m = torch.zeros(P, dtype=torch.float32, device="cuda")
+    v = torch.zeros(P, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    mb = a.minibatch
+    tws = torch.empty(binding.hot_mlp_train_bytes(mb), dtype=torch.uint8, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    xb = torch.empty((mb, 32), dtype=torch.float32, device="cuda")
+    tb = torch.empty((mb, 6), dtype=torch.float32, device="cuda")
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    grad_ms = 0.0
+    for step in range(1, a.train_steps + 1):
+        idx = torch.multinomial(wrow, mb, replacement=True, generator=gen)
+        torch.index_select(X, 0, idx, out=xb)
+        torch.index_select(T, 0, idx, out=tb)
+        lr = 1e-3 * (0.5 * (1 + np.cos(np.pi * (step - 1) / a.train_steps)))  # cosine decay
+        if step == a.train_steps // 2:
+            ev0.record()
+        binding.hot_mlp_grad(th, xb, tb, mb, grad, loss, tws)
+        if step == a.train_steps // 2:
+            ev1.record()
+        binding.hot_mlp_adam(th, grad, m, v, step, max(lr, 1e-5))
+        if step % max(1, a.train_steps // 10) == 0:
+            losses.append(float(loss.item()))
+            print(f"train step {step}: loss {losses[-1]:.4g}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    grad_ms = ev0.elapsed_time(ev1)
+    pk = torch.empty(binding.hot_mlp_packed_bytes(), dtype=torch.uint8, device="cuda")
+    binding.hot_mlp_pack(th, pk)
+    # validation: error of the predicted correction relative to the plain
+    # extrapolation's error (1.0 = no better than the extrapolation)
+    val = {"note": "||s (y - t)|| / ||s t||: the increment error of the warm start relative to that of the "
+                   "plain extrapolation (1.0 = no better), over the held-out rows"}
+    for name, xv, tv, sv in (("held_out_batch_sizes", Xv, Tv, Sv), ("held_out_N64", Xv64, Tv64, Sv64)):
+        yv = torch.empty_like(tv)
+        binding.hot_mlp_forward(pk, xv, yv, xv.shape[0])
+        torch.cuda.synchronize()
+        w = sv[:, None]
+        val[name] = {"rows": int(xv.shape[0]),
+                     "rel_l2": float(torch.linalg.vector_norm(w * (yv - tv)) / torch.linalg.vector_norm(w * tv))}
+    # ---- batched comparison (one implicit step per instance, FP32, tol 1e-5)
+    ins, mids, keep = batch_fields(sizes, "f32", modes=modes)  # mids: the states advanced in place
+    B = len(sizes)
+    sample = list(range(0, B, max(1, B // 64)))
+    res = {}
+    ws = None
+    for mode in ("plain", "assisted"):
+        plan, wsb = binding.hot_plan([int(x) for x in sizes], "implicit", "f32", "two_thirds", nu, dt, tol, 50,
+                                     keep_history=True)
+        if ws is None:
+            ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        try:
+            for i in range(B):
+                mids[i].copy_(ins[i])
+            binding.hot_tune(plan, ws)
+            binding.hot_run(plan, mids, mids, ws, 2)  # history: two plain steps
+            if mode == "assisted":
+                binding.hot_set_surrogate(plan, pk)
+            pre = [mids[i].clone() for i in sample]
+            torch.cuda.synchronize()
+            binding.hot_profile_enable(plan, True)
+            t0 = time.perf_counter()
+            rc = binding.hot_run(plan, mids, mids, ws, 1)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            prof = binding.hot_profile_read(plan)
+            binding.hot_profile_enable(plan, False)
+            sweeps, nonconv = binding.hot_implicit_stats(plan, B)
+            res[mode] = {"seconds": el, "instances_per_sec": B / el, "mean_sweeps": float(np.mean(sweeps)),
+                         "max_sweeps": int(np.max(sweeps)), "nonconverged": int(np.sum(nonconv)), "rc": rc,
+                         "predict_ms": prof.get("imp_predict", (0.0, 0))[0],
+                         "sweep_ms": sum(v[0] for k, v in prof.items() if k not in ("imp_predict", "gather",
+                                                                                     "scatter", "imp_advance")),
+                         "state": [mids[i].clone() for i in sample], "pre": pre}
+        finally:
+            binding.hot_destroy(plan)
+    pre = res["plain"].pop("pre")
+    res["assisted"].pop("pre")
+    diffs = [float(torch.linalg.vector_norm(p - q) / max(float(torch.linalg.vector_norm(p - u)), 1e-300))
+             for p, q, u in zip(res["plain"].pop("state"), res["assisted"].pop("state"), pre)]
+    # rows the fused MLP kernel runs: every compact slot (no row padding for N <= 64 in FP32)
+    mlp_rows = int(sum(binding.hot_mlp_dataset_rows(int(n)) for n in sizes))
+    pred_s = res["assisted"]["predict_ms"] / 1e3
+    mlp_tflops = mlp_rows * MLP_FLOP_PER_ROW / pred_s / 1e12 if pred_s > 0 else None
+    grad_tflops = 3 * mb * MLP_FLOP_PER_ROW / (grad_ms / 1e3) / 1e12 if grad_ms > 0 else None
+    line = {
+        "metric": "instances/sec",
+        "value": res["assisted"]["instances_per_sec"],
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 2,
+        "ms_per_step": res["assisted"]["seconds"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (state) / bf16 x bf16 -> f32 (MLP)",
+        "data": "synthetic (R1 per instance, seeds 1000+i; sizes log-uniform over [16, 64], seed 0)",
+        "config": {"workload": f"implicit_surrogate_batch_{B}_uneven_16-64_f32", "instances": B, "nu": nu,
+                   "dt": dt, "tol": tol, "points": int((sizes.astype(np.int64) ** 3).sum()),
+                   "timed": "one implicit step per instance after two plain steps of history"},
+        "plain": res["plain"],
+        "assisted": res["assisted"],
+        "speedup_assisted_over_plain": res["plain"]["seconds"] / res["assisted"]["seconds"],
+        "sweeps_saved_per_instance": res["plain"]["mean_sweeps"] - res["assisted"]["mean_sweeps"],
+        "assisted_vs_plain_diff_rel_to_increment": {"max": max(diffs), "mean": float(np.mean(diffs)),
+                                                    "sampled_instances": len(diffs)},
+        "roofline": {"bound": "mfma", "kernel": "mlp_fused (imp_predict)", "achieved": mlp_tflops,
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (mlp_tflops / BF16_PEAK_TFLOPS) if mlp_tflops else None, "traffic": None},
+        "training": {"sizes": a.train_sizes, "fields": len(train), "train_rows": rows, "steps": a.train_steps,
+                     "minibatch": mb, "seconds": t_train, "data_seconds": t_data, "loss_trace": losses,
+                     "grad_call_ms": grad_ms, "grad_gemm_tflops": grad_tflops,
+                     "grad_mfma_frac": (grad_tflops / BF16_PEAK_TFLOPS) if grad_tflops else None},
+        "validation": val,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(N_work, seconds=12.0):
     """Time the CPU oracle (one core) on RK4 steps at N = 128 and scale to
     instances/s of an N_work^3 step by the FFT cost N^3 log2 N."""
@@ -308,7 +524,13 @@ def main():
                     help="write profiles/counters.json from two rocprofv3 --pmc counter_collection.csv files "
                          "(no GPU needed); use with --calibrate-copy MIB and --pmc-command")
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded with the counters")
-    ap.add_argument("--workload", default="single", choices=["single", "batch"],
+    ap.add_argument("--train-fields", type=int, default=200, help="surrogate: training trajectories")
+    ap.add_argument("--train-sizes", default="batch", choices=["batch", "n64"],
+                    help="surrogate: training sizes drawn like the batch's, or N = 64 only")
+    ap.add_argument("--train-steps", type=int, default=3000, help="surrogate: Adam steps")
+    ap.add_argument("--minibatch", type=int, default=4096, help="surrogate: rows per Adam step")
+    ap.add_argument("--surrogate-batch", type=int, default=16384, help="surrogate: instances compared")
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "surrogate"],
                     help="single: one N^3 field (default); batch: many uneven instances, one RK4 step each")
     ap.add_argument("--batch", type=int, default=4096, help="instances of the batch workload")
     a = ap.parse_args()
@@ -330,6 +552,9 @@ def main():
 
     if a.workload == "batch":
         bench_batch(a)
+        return
+    if a.workload == "surrogate":
+        bench_surrogate(a)
         return
 
     if a.calibrate_copy > 0:

@@ -211,6 +211,18 @@ int hot_mlp_grad(const float* params, const float* x, const float* t, int32_t ro
 int hot_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
                  float beta2, float eps, void* stream);
 
+/* Training data of one N^3 field (2/3 rule): the features of every retained
+ * mode, rows = hot_mlp_dataset_rows(N) of them in canonical (kx, ky, kz)
+ * order, into x[rows][32]; when d is not NULL the targets
+ * (d - (2 d1 - d2)) / s into t[rows][6] (0 where s = 0); when s is not NULL
+ * the scales s = ||d1_k|| into s[rows].  u: the state at
+ * the start of a step; d1, d2: the increments of the two steps before it
+ * (newest first); d: the step's own increment.  Canonical spectral layout,
+ * element type dtype; x, t FP32.  Errors: HOT_E_INVALID. */
+int64_t hot_mlp_dataset_rows(int32_t N);
+int hot_mlp_dataset(int32_t N, int32_t dtype, const void* u, const void* d1, const void* d2, const void* d, double nu,
+                    double dt, float* x, float* t, float* s, void* stream);
+
 /* Use the packed surrogate (hot_mlp_pack output, device memory the caller
  * keeps alive) for the warm start of an IMPLICIT plan's later hot_run calls;
  * NULL returns to the plain extrapolation.  Host only.

@@ -116,6 +116,10 @@ def _lib():
         lib.hot_mlp_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, vp]
         lib.hot_mlp_adam.restype = ctypes.c_int
+        lib.hot_mlp_dataset_rows.argtypes = [i32]
+        lib.hot_mlp_dataset_rows.restype = ctypes.c_int64
+        lib.hot_mlp_dataset.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]
+        lib.hot_mlp_dataset.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -324,3 +328,17 @@ def hot_mlp_grad(params, x, t, rows, grad, loss, workspace, stream=None):
 def hot_mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(_lib().hot_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
                                float(beta2), float(eps), _stream(stream)), "hot_mlp_adam")
+
+
+def hot_mlp_dataset_rows(N):
+    r = int(_lib().hot_mlp_dataset_rows(int(N)))
+    if r < 0:
+        raise HotError(r, "hot_mlp_dataset_rows")
+    return r
+
+
+def hot_mlp_dataset(N, dtype, u, d1, d2, d, nu, dt, x, t=None, s=None, stream=None):
+    """Training features (targets when d is given, scales when s is given)
+    of one field."""
+    _check(_lib().hot_mlp_dataset(int(N), DTYPES[dtype], _ptr(u), _ptr(d1), _ptr(d2), _ptr(d), float(nu), float(dt),
+                                  _ptr(x), _ptr(t), _ptr(s), _stream(stream)), "hot_mlp_dataset")

@@ -149,6 +149,38 @@ int hot_mlp_grad(const float* th, const float* x, const float* t, int32_t rows, 
   return e == hipSuccess ? HOT_OK : HOT_E_HIP;
 }
 
+int64_t hot_mlp_dataset_rows(int32_t N) {
+  if (N < 8 || (N & 1)) return HOT_E_INVALID;
+  const long K = (N - 1) / 3;
+  return (2 * K + 1) * (2 * K + 1) * (K + 1);
+}
+
+int hot_mlp_dataset(int32_t N, int32_t dtype, const void* u, const void* d1, const void* d2, const void* d, double nu,
+                    double dt, float* x, float* t, float* s_out, void* stream) {
+  if (N < 8 || (N & 1) || !u || !d1 || !d2 || !x || (d && !t) || (dtype != HOT_F64 && dtype != HOT_F32))
+    return HOT_E_INVALID;
+  Geo g{};
+  const int K = (N - 1) / 3;
+  g.N = N;
+  g.lo = K + 1;
+  g.hi = K;
+  g.M = 2 * K + 1;
+  g.Mz = g.Mzp = K + 1;
+  const long rows = (long)g.M * g.M * g.Mz;
+  long blocks = (rows + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == HOT_F64)
+    hipLaunchKernelGGL(k_mlp_dataset<double>, dim3((unsigned)blocks), dim3(256), 0, s, (const cx<double>*)u,
+                       (const cx<double>*)d1, (const cx<double>*)d2, (const cx<double>*)d, g, (float)nu, (float)dt, x,
+                       d ? t : nullptr, s_out);
+  else
+    hipLaunchKernelGGL(k_mlp_dataset<float>, dim3((unsigned)blocks), dim3(256), 0, s, (const cx<float>*)u,
+                       (const cx<float>*)d1, (const cx<float>*)d2, (const cx<float>*)d, g, (float)nu, (float)dt, x,
+                       d ? t : nullptr, s_out);
+  return hipGetLastError() == hipSuccess ? HOT_OK : HOT_E_HIP;
+}
+
 int hot_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
                  float beta2, float eps, void* stream) {
   if (!params || !grad || !m || !v || step < 1 || !(lr > 0.f)) return HOT_E_INVALID;

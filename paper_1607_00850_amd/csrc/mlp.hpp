@@ -7,6 +7,9 @@
 //   A (16 x 32): row l % 16, k = 8 (l / 16) .. +8   (8 bf16 per lane)
 //   B (32 x 16): col l % 16, k = 8 (l / 16) .. +8
 //   D (16 x 16): col l % 16, rows 4 (l / 16) .. +4  (4 fp32 per lane)
+// The training GEMM puts activations in A and weights in B; the fused
+// inference kernel the other way round (D = W x act^T), so that a lane's
+// four results are consecutive features of one row.
 //
 // Parameters (one FP32 vector, weights W[out][in]):
 //   W1[256][32] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] W4[6][256] b4[6]
@@ -30,6 +33,7 @@
 namespace hot {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kIn = 32, kHid = 256, kOut = 6, kOutPad = 16;
@@ -42,14 +46,19 @@ constexpr long kPW1 = 0, kPW2 = kPW1 + 2L * kHid * kIn, kPW3 = kPW2 + 2L * kHid 
                kPW4 = kPW3 + 2L * kHid * kHid, kPB1 = kPW4 + 2L * kOutPad * kHid, kPB2 = kPB1 + 4L * kHid,
                kPB3 = kPB2 + 4L * kHid, kPB4 = kPB3 + 4L * kHid, kPackedBytes = kPB4 + 4L * kOutPad;
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ unsigned short bf16_bits(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
+// FP32 -> BF16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950).
 __device__ __forceinline__ unsigned pack2(float a, float b) {
-  return (unsigned)bf16_bits(a) | ((unsigned)bf16_bits(b) << 16);
+  const bf16x2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(unsigned, v);
+}
+__device__ __forceinline__ unsigned short bf16_bits(float f) { return (unsigned short)(pack2(f, 0.f) & 0xFFFFu); }
+
+// tanh(x) = 1 - 2 / (1 + e^{2x}) on the hardware exp2 and reciprocal; its
+// absolute error (a few 1e-7) is far below the BF16 rounding the result
+// then takes.  Saturates to +-1 for large |x|.
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // e^{2x}
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
 }
 __device__ __forceinline__ bf16x8 lds_frag(const unsigned short* p) { return *(const bf16x8*)p; }
 __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -216,27 +225,62 @@ __device__ __forceinline__ void mlp_layer(const unsigned short* __restrict__ Wg,
     __syncthreads();
     const bf16x8 a0 = lds_frag(&act[(row0 + (l & 15)) * kActLd + k0 + 8 * (l >> 4)]);
     const bf16x8 a1 = lds_frag(&act[(row0 + 16 + (l & 15)) * kActLd + k0 + 8 * (l >> 4)]);
+    // weights as the A operand, activations as B: lane l then holds output
+    // features 4 (l / 16) .. +4 of row l % 16, written back as one 8-byte store
     for (int n = 0; n < NT; ++n) {
-      const bf16x8 b = lds_frag(&Ws[(n * 16 + (l & 15)) * kWLd + 8 * (l >> 4)]);
-      acc[0][n] = mfma16(a0, b, acc[0][n]);
-      acc[1][n] = mfma16(a1, b, acc[1][n]);
+      const bf16x8 w = lds_frag(&Ws[(n * 16 + (l & 15)) * kWLd + 8 * (l >> 4)]);
+      acc[0][n] = mfma16(w, a0, acc[0][n]);
+      acc[1][n] = mfma16(w, a1, acc[1][n]);
     }
   }
 }
 
-// Hidden-layer epilogue: the wave's rows <- bf16(tanh(acc + b)).
+// Hidden-layer epilogue: the wave's rows <- bf16(tanh(acc + b)); acc[i][n]
+// holds features n*16 + 4 (l / 16) .. +4 of row row0 + 16 i + l % 16.
 __device__ __forceinline__ void mlp_hidden_out(const f32x4 (&acc)[2][16], const float* __restrict__ bias,
                                                unsigned short* __restrict__ act, int row0) {
   const int l = threadIdx.x & 63;
-  for (int i = 0; i < 2; ++i)
-    for (int n = 0; n < 16; ++n) {
-      const int col = n * 16 + (l & 15);
-      const float bb = bias[col];
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + 16 * i + 4 * (l >> 4) + r;
-        act[row * kActLd + col] = bf16_bits(tanhf(acc[i][n][r] + bb));
-      }
+  for (int n = 0; n < 16; ++n) {
+    const int f0 = n * 16 + 4 * (l >> 4);
+    const float4 bb = *(const float4*)&bias[f0];
+    for (int i = 0; i < 2; ++i) {
+      const int row = row0 + 16 * i + (l & 15);
+      const f32x4 v = acc[i][n];
+      *(uint2*)&act[row * kActLd + f0] = uint2{pack2(fast_tanh(v[0] + bb.x), fast_tanh(v[1] + bb.y)),
+                                               pack2(fast_tanh(v[2] + bb.z), fast_tanh(v[3] + bb.w))};
     }
+  }
+}
+
+// Features of one retained mode (see the top of this file) from the state u
+// and the increments d1 (newest), d2, as (re, im) x 3 FP32 values; returns s.
+__device__ __forceinline__ float surrogate_features(const float (&u)[6], const float (&d1)[6], const float (&d2)[6],
+                                                    const ModeK& m, int N, float nu, float dt, float (&f)[kIn]) {
+  for (int i = 0; i < kIn; ++i) f[i] = 0.f;
+  float ss = 0.f, su = 0.f;
+  for (int i = 0; i < 6; ++i) {
+    ss += d1[i] * d1[i];
+    su += u[i] * u[i];
+  }
+  const float s = sqrtf(ss);
+  if (s > 0.f) {
+    const float inv = 1.f / s;
+    const float a = 0.5f * dt * nu * (float)(m.kx * m.kx + m.ky * m.ky + m.kz * m.kz);
+    const float nrm = sqrtf(su), invu = nrm > 0.f ? 1.f / nrm : 0.f;
+    for (int i = 0; i < 6; ++i) {
+      f[i] = d1[i] * inv;
+      f[6 + i] = d2[i] * inv;
+      f[12 + i] = ((1.f - a) * d1[i] + 2.f * a * u[i]) * inv;
+      f[18 + i] = u[i] * invu;
+    }
+    f[24] = s * invu;
+    const float invN = 1.f / (float)N;
+    f[25] = (float)m.kx * invN;
+    f[26] = (float)m.ky * invN;
+    f[27] = (float)m.kz * invN;
+    f[28] = a;
+  }
+  return s;
 }
 
 // Feature source / result sink of the fused kernel.
@@ -302,29 +346,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fused(const unsigned char* __r
           d2[2 * c] = (float)q.x;
           d2[2 * c + 1] = (float)q.y;
         }
-        float ss = 0.f, su = 0.f;
-        for (int i = 0; i < 6; ++i) {
-          ss += d1[i] * d1[i];
-          su += u[i] * u[i];
-        }
-        s = sqrtf(ss);
-        if (s > 0.f) {
-          const float inv = 1.f / s;
-          const float a = 0.5f * st.dt * st.nu * (float)(m.kx * m.kx + m.ky * m.ky + m.kz * m.kz);
-          const float nrm = sqrtf(su), invu = nrm > 0.f ? 1.f / nrm : 0.f;
-          for (int i = 0; i < 6; ++i) {
-            f[i] = d1[i] * inv;
-            f[6 + i] = d2[i] * inv;
-            f[12 + i] = ((1.f - a) * d1[i] + 2.f * a * u[i]) * inv;
-            f[18 + i] = u[i] * invu;
-          }
-          f[24] = s * invu;
-          const float invN = 1.f / (float)st.g.N;
-          f[25] = (float)m.kx * invN;
-          f[26] = (float)m.ky * invN;
-          f[27] = (float)m.kz * invN;
-          f[28] = a;
-        }
+        s = surrogate_features(u, d1, d2, m, st.g.N, st.nu, st.dt, f);
       }
     }
     srow[t] = s;
@@ -348,10 +370,11 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fused(const unsigned char* __r
   {
     const int l = t & 63;
     const float* b4 = (const float*)(pk + kPB4);
-    const int col = l & 15;
-    if (col < kOut)
-      for (int i = 0; i < 2; ++i)
-        for (int r = 0; r < 4; ++r) yl[(row0 + 16 * i + 4 * (l >> 4) + r) * 8 + col] = out[i][0][r] + b4[col];
+    for (int i = 0; i < 2; ++i)
+      for (int r = 0; r < 4; ++r) {
+        const int f = 4 * (l >> 4) + r;  // output feature; lane l % 16 is the row
+        if (f < kOut) yl[(row0 + 16 * i + (l & 15)) * 8 + f] = out[i][0][r] + b4[f];
+      }
   }
   __syncthreads();
   if (t < kRows) {
@@ -371,6 +394,52 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fused(const unsigned char* __r
           st.D[i] = d;
           st.U1[i] = st.U0[i] + d * T(0.5);
         }
+      }
+    }
+  }
+}
+
+// Training rows of one N^3 field (2/3 rule), one thread per retained mode in
+// canonical (kx, ky, kz) order: x[row][32] features, t[row][6] targets
+// (d - (2 d1 - d2)) / s (0 where s = 0) when d is given, sc[row] = s when
+// sc is given.  Canonical layout
+// [3][N][N][N/2+1].
+template <typename T>
+__global__ __launch_bounds__(256) void k_mlp_dataset(const cx<T>* __restrict__ u, const cx<T>* __restrict__ d1,
+                                                     const cx<T>* __restrict__ d2, const cx<T>* __restrict__ d,
+                                                     Geo g, float nu, float dt, float* __restrict__ x,
+                                                     float* __restrict__ t, float* __restrict__ sc) {
+  const long rows = (long)g.M * g.M * g.Mz;
+  const long Nh = g.N / 2 + 1, comp = (long)g.N * g.N * Nh;
+  for (long r = (long)blockIdx.x * 256 + threadIdx.x; r < rows; r += (long)gridDim.x * 256) {
+    const int ix = (int)(r / ((long)g.M * g.Mz));
+    const long rr = r - (long)ix * g.M * g.Mz;
+    const int iy = (int)(rr / g.Mz);
+    ModeK m;
+    m.kz = (int)(rr - (long)iy * g.Mz);
+    const int px = cpos(ix, g), py = cpos(iy, g);
+    m.kx = kwave(px, g.N);
+    m.ky = kwave(py, g.N);
+    const long at = ((long)px * g.N + py) * Nh + m.kz;
+    float fu[6], f1[6], f2[6];
+    for (int c = 0; c < 3; ++c) {
+      const cx<T> a = u[c * comp + at], b = d1[c * comp + at], q = d2[c * comp + at];
+      fu[2 * c] = (float)a.x;
+      fu[2 * c + 1] = (float)a.y;
+      f1[2 * c] = (float)b.x;
+      f1[2 * c + 1] = (float)b.y;
+      f2[2 * c] = (float)q.x;
+      f2[2 * c + 1] = (float)q.y;
+    }
+    float f[kIn];
+    const float s = surrogate_features(fu, f1, f2, m, g.N, nu, dt, f);
+    for (int i = 0; i < kIn; ++i) x[r * kIn + i] = f[i];
+    if (sc) sc[r] = s;
+    if (t) {
+      for (int c = 0; c < 3; ++c) {
+        const cx<T> e = d[c * comp + at] - (d1[c * comp + at] * T(2) - d2[c * comp + at]);
+        t[r * kOut + 2 * c] = s > 0.f ? (float)(e.x / (T)s) : 0.f;
+        t[r * kOut + 2 * c + 1] = s > 0.f ? (float)(e.y / (T)s) : 0.f;
       }
     }
   }

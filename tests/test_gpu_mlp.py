@@ -202,3 +202,30 @@ def test_keep_history_continues_bitwise():
         binding.hot_destroy(h)
     np.testing.assert_array_equal(two, one)
     assert s_a[0] + s_b[0] == s_one[0]
+
+
+@pytest.mark.parametrize("dtype,N", [("f64", 16), ("f32", 24)])
+def test_dataset_matches_reference_features_and_targets(dtype, N):
+    # a state and three increments from the oracle's implicit steps
+    nu, dt = 1.0 / 1600, 0.02
+    u0 = inputs.smooth_random(N, 40) * 4.0
+    _, _, incs, _ = oracle.implicit_midpoint(u0, nu, dt, 3, 1e-12)
+    u = u0 * oracle.retained_mask(N) + incs[0] + incs[1]  # state at the start of the third step
+    torch = _torch()
+    rows = binding.hot_mlp_dataset_rows(N)
+    x = torch.empty((rows, 32), dtype=torch.float32, device="cuda")
+    t = torch.empty((rows, 6), dtype=torch.float32, device="cuda")
+    sc = torch.empty(rows, dtype=torch.float32, device="cuda")
+    dev = [to_dev(a, dtype) for a in (u, incs[1], incs[0], incs[2])]
+    binding.hot_mlp_dataset(N, dtype, *dev, nu, dt, x, t, sc)
+    torch.cuda.synchronize()
+    c = (lambda a: a.astype(np.complex64).astype(np.complex128)) if dtype == "f32" else (lambda a: a)
+    F, s = oracle.surrogate_features(c(u), c(incs[1]), c(incs[0]), nu, dt)
+    T = oracle.surrogate_target(c(incs[2]), c(incs[1]), c(incs[0]), s)
+    assert x.shape[0] == F.shape[0]
+    assert _rel(x.cpu().numpy(), F) < 1e-6
+    assert _rel(sc.cpu().numpy(), s) < 1e-6
+    # the targets are differences of nearly equal increments: FP32 sees
+    # them to the rounding of the increments relative to the difference
+    bar = 1e-6 if dtype == "f64" else 2e-3  # s itself is an FP32 value on the GPU
+    assert _rel(t.cpu().numpy(), T) < bar
