@@ -157,11 +157,21 @@ int hot_graph_destroy(hot_graph_t graph);
  * (x inverse with the curl, y inverse, y forward, x forward), time each
  * column-width variant reps times
  * on the workspace (which must be the planned size; the caller's arrays are
- * not touched) and keep the fastest for later hot_run calls.  Synchronises
- * the stream.  hot_tuned_width reports the chosen columns per block of a
- * pass for instance i, or a negative error code. */
+ * not touched) and keep the fastest for later hot_run calls.  For RK4 and
+ * RHS it also times the x forward pass fused with the stage update (pass
+ * "x_fwd_rk": the nonlinear term stays in registers) against the two
+ * separate passes and keeps the faster.  Synchronises the stream.
+ * hot_tuned_width reports the chosen columns per block of a pass for
+ * instance i (for x_fwd_rk: 0 when the separate passes were kept), or a
+ * negative error code. */
 int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t reps);
 int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
+
+/* Set what hot_tune would choose, for every size of the plan: for a
+ * column-tiled pass the width variant 0 (narrow), 1 (default) or 2 (wide);
+ * for x_fwd_rk -1 (separate x_fwd and rk_stage passes), 0 or 1 (fused, narrow
+ * or default width).  Host only.  Errors: HOT_E_INVALID. */
+int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant);
 
 /* IMPLICIT statistics of the plan's last hot_run, per instance i (host
  * arrays of p's batch size, either may be NULL): sweeps[i] = Picard sweeps

@@ -97,6 +97,8 @@ def _lib():
         lib.hot_tune.restype = ctypes.c_int
         lib.hot_tuned_width.argtypes = [vp, i32, i32]
         lib.hot_tuned_width.restype = ctypes.c_int
+        lib.hot_set_variant.argtypes = [vp, i32, i32]
+        lib.hot_set_variant.restype = ctypes.c_int
         lib.hot_implicit_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.hot_implicit_stats.restype = ctypes.c_int
         lib.hot_set_surrogate.argtypes = [vp, vp]
@@ -259,6 +261,11 @@ def hot_tune(plan, workspace, stream=None, reps=3):
     rc = _lib().hot_tune(plan, _ptr(workspace), _stream(stream), int(reps))
     if rc != HOT_OK:
         raise HotError(rc, "hot_tune", _lib().hot_last_hip_error(plan))
+
+
+def hot_set_variant(plan, pass_name, variant):
+    """Override the autotuner's choice for a pass (see include/hot.h)."""
+    _check(_lib().hot_set_variant(plan, pass_names().index(pass_name), int(variant)), "hot_set_variant")
 
 
 def hot_tuned_width(plan, instance, pass_name):

@@ -30,12 +30,13 @@ enum Pass : int {
   PASS_IMP_UPDATE,
   PASS_IMP_DECIDE,
   PASS_IMP_ADVANCE,
+  PASS_X_FWD_RK,
   NUM_PASSES
 };
 
 static const char* kPassNames[NUM_PASSES] = {
     "gather", "x_inv_curl", "y_inv", "z_cross", "y_fwd", "x_fwd", "rk_stage", "scatter", "z_r2c", "z_c2r", "x_inv",
-    "imp_predict", "imp_update", "imp_decide", "imp_advance",
+    "imp_predict", "imp_update", "imp_decide", "imp_advance", "x_fwd_rk",
 };
 
 template <typename T>
@@ -103,6 +104,7 @@ struct Group {
   size_t oH[2] = {0, 0}, oAct = 0, oPart = 0;  // implicit step only
   int nparts = 0;                             // blocks of the implicit update
   int rot = 0, hist = 0;                      // implicit step: buffer rotation, history depth
+  int fused = -1;  // RK4/RHS: x_fwd_rk variant fusing the x pass with the stage update, -1 = separate passes
   size_t bytes = 0;
   int variant[NUM_PASSES];  // strided column-width variant per pass (autotuned)
   int B() const { return (int)members.size(); }
@@ -337,6 +339,9 @@ int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) 
     case PASS_IMP_UPDATE: b = p->op == HOT_OP_IMPLICIT ? 15 * C : 0; break;
     case PASS_IMP_DECIDE: b = 0; break;
     case PASS_IMP_ADVANCE: b = p->op == HOT_OP_IMPLICIT ? 9 * C : 0; break;
+    // the x pass fused with the stage update: the stage traffic without the
+    // nonlinear term (which stays in registers)
+    case PASS_X_FWD_RK: b = p->op == HOT_OP_RK4 ? 3 * D1 + 12 * C : (p->op == HOT_OP_RHS ? 3 * D1 + 6 * C : 0); break;
     default: return HOT_E_INVALID;
   }
   *bytes = b * e;
@@ -415,7 +420,8 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
 
 // One evaluation of the right-hand side for every instance of a group, from
 // compact state `src` into Nh.
-void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, const int* act = nullptr) {
+void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, const int* act = nullptr,
+                bool x_fwd = true) {
   const Geo& g = G.g;
   const long N = g.N, M = g.M, P = g.Mzp;
   const Ops& o = G.ops;
@@ -436,11 +442,27 @@ void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, 
                      G.D1, 3, isA2, isA1, nb, g, act);
   });
   // x forward: rows x (all N) -> kx (compact), columns (ky, kz)
+  if (!x_fwd) return;
   r.pass(PASS_X_FWD, [&] {
     const long Q = M * P;
     return o.strided(r.s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3, isA1,
                      isU, nb, g, act);
   });
+}
+
+// One right-hand side plus stage update (mode 0..3 RK4 stage, 4 plain
+// right-hand side into Acc): the x pass and the update fused or separate.
+void stage_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, int mode, double nu, double dt) {
+  const Ops& o = G.ops;
+  const long isU = 3 * G.C;
+  const int nb = G.B();
+  rhs_passes(r, G, q, src, nullptr, G.fused < 0);
+  if (G.fused < 0)
+    r.pass(PASS_RK_STAGE, [&] { return o.rk_stage(r.s, q.Nh, q.U0, q.U1, q.Acc, G.C, isU, nb, G.g, mode, nu, dt); });
+  else
+    r.pass(PASS_X_FWD_RK, [&] {
+      return o.x_fwd_rk(r.s, G.fused, q.A1, G.D1, 6 * G.D1, q.U0, q.U1, q.Acc, G.C, isU, nb, G.g, mode, nu, dt);
+    });
 }
 
 // Upload the members' input/output pointer tables of every batched group
@@ -536,17 +558,11 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
     void* out0 = out[G.members[0]];
     r.pass(PASS_GATHER, [&] { return o.gather(r.s, in0, q.in_tab, q.U0, G.C, isU, nb, g); });
     if (p->op == HOT_OP_RHS) {
-      rhs_passes(r, G, q, q.U0);
-      r.pass(PASS_RK_STAGE, [&] { return o.rk_stage(r.s, q.Nh, q.U0, q.U1, q.Acc, G.C, isU, nb, g, 4, p->nu, p->dt); });
+      stage_passes(r, G, q, q.U0, 4, p->nu, p->dt);
       r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.Acc, out0, q.out_tab, G.C, isU, nb, g); });
     } else {
-      for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
-        for (int st = 0; st < 4; ++st) {
-          rhs_passes(r, G, q, st == 0 ? q.U0 : q.U1);
-          r.pass(PASS_RK_STAGE,
-                 [&] { return o.rk_stage(r.s, q.Nh, q.U0, q.U1, q.Acc, G.C, isU, nb, g, st, p->nu, p->dt); });
-        }
-      }
+      for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step)
+        for (int st = 0; st < 4; ++st) stage_passes(r, G, q, st == 0 ? q.U0 : q.U1, st, p->nu, p->dt);
       r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.U0, out0, q.out_tab, G.C, isU, nb, g); });
     }
   }
@@ -779,6 +795,51 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
       }
       G.variant[pid] = best_v;
     }
+    // RK4 / RHS: the x pass with the stage update fused, or the two passes
+    // (one stage-1 update on the workspace; every variant computes the same)
+    if (rc == HOT_OK && (p->op == HOT_OP_RK4 || p->op == HOT_OP_RHS)) {
+      float best = 1e30f;
+      int best_f = -1;
+      for (int f = -1; f < 2 && rc == HOT_OK; ++f) {
+        if (f == 0 && G.ops.strided_width[0] == G.ops.strided_width[1]) continue;  // same kernel as f = 1
+        G.fused = f;
+        float t = 0.f;
+        for (int rep = 0; rep <= reps && rc == HOT_OK; ++rep) {
+          Runner r{p, s, false};
+          if (rep == 1) (void)hipEventRecord(a, s);
+          if (f < 0) {
+            const long Q = G.g.M * (long)G.g.Mzp;
+            r.pass(PASS_X_FWD, [&] {
+              return G.ops.strided(s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C,
+                                   3, 6 * G.D1, 3 * G.C, G.B(), G.g, nullptr);
+            });
+            r.pass(PASS_RK_STAGE, [&] {
+              return G.ops.rk_stage(s, q.Nh, q.U0, q.U1, q.Acc, G.C, 3 * G.C, G.B(), G.g, 1, p->nu, p->dt);
+            });
+          } else {
+            r.pass(PASS_X_FWD_RK, [&] {
+              return G.ops.x_fwd_rk(s, f, q.A1, G.D1, 6 * G.D1, q.U0, q.U1, q.Acc, G.C, 3 * G.C, G.B(), G.g, 1, p->nu,
+                                    p->dt);
+            });
+          }
+          rc = r.rc;
+        }
+        if (rc != HOT_OK) break;
+        hipError_t e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+        if (e != hipSuccess) {
+          p->last_hip = (int)e;
+          rc = HOT_E_HIP;
+          break;
+        }
+        if (t < best) {
+          best = t;
+          best_f = f;
+        }
+      }
+      G.fused = best_f;
+    }
   }
   p->prof = was_prof;
   (void)hipEventDestroy(a);
@@ -786,9 +847,25 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
   return rc;
 }
 
+extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
+  if (!p) return HOT_E_INVALID;
+  const bool tiled = pass == PASS_X_INV_CURL || pass == PASS_Y_INV || pass == PASS_Y_FWD || pass == PASS_X_FWD;
+  if (pass == PASS_X_FWD_RK) {
+    if (variant < -1 || variant > 1 || (p->op != HOT_OP_RK4 && p->op != HOT_OP_RHS)) return HOT_E_INVALID;
+    for (auto& G : p->groups) G.fused = variant;
+    return HOT_OK;
+  }
+  if (!tiled || variant < 0 || variant > 2) return HOT_E_INVALID;
+  for (auto& G : p->groups) G.variant[pass] = variant;
+  return HOT_OK;
+}
+
 extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
   if (!p || instance < 0 || instance >= p->batch || pass < 0 || pass >= NUM_PASSES) return HOT_E_INVALID;
   for (const auto& G : p->groups)
-    if (G.N == p->n[instance]) return G.ops.strided_width[G.variant[pass]];
+    if (G.N == p->n[instance]) {
+      if (pass == PASS_X_FWD_RK) return G.fused < 0 ? 0 : G.ops.strided_width[G.fused];
+      return G.ops.strided_width[G.variant[pass]];
+    }
   return HOT_E_INVALID;
 }

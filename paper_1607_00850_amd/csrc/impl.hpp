@@ -65,6 +65,9 @@ struct Ops {
   hipError_t (*z_r2c)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
   hipError_t (*rk_stage)(hipStream_t, const void* Nh, void* U0, void* U1, void* Acc, long C, long is, int nb,
                          const Geo&, int mode, double nu, double dt);
+  // x forward transform fused with the stage update (replaces x_fwd + rk_stage)
+  hipError_t (*x_fwd_rk)(hipStream_t, int variant, const void* A, long csA, long isA, void* U0, void* U1, void* Acc,
+                         long C, long isU, int nb, const Geo&, int mode, double nu, double dt);
   hipError_t (*gather)(hipStream_t, const void* in0, const void* const* in_tab, void* out, long C, long is, int nb,
                        const Geo&);
   hipError_t (*scatter)(hipStream_t, const void* in, void* out0, void* const* out_tab, long C, long is, int nb,
@@ -198,6 +201,24 @@ struct Impl {
                        (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, is, g, mode, T(nu), T(dt));
     return hipGetLastError();
   }
+  template <int WW>
+  static hipError_t x_fwd_rk_w(hipStream_t s, const void* A, long csA, long isA, void* U0, void* U1, void* Acc,
+                               long C, long isU, int nb, const Geo& g, int mode, double nu, double dt) {
+    constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
+    const long Q = (long)g.M * g.Mzp;
+    const long ntiles = (Q + WW - 1) / WW;
+    const long group = 8L * pair;
+    const dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)nb);
+    hipLaunchKernelGGL((k_x_fwd_rk<T, P, WW>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)A, csA, isA, (cx<T>*)U0,
+                       (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
+    return hipGetLastError();
+  }
+  // fused variants: W/2 and W (three components in registers)
+  static hipError_t x_fwd_rk(hipStream_t s, int variant, const void* A, long csA, long isA, void* U0, void* U1,
+                             void* Acc, long C, long isU, int nb, const Geo& g, int mode, double nu, double dt) {
+    if (variant == 0) return x_fwd_rk_w<WV0>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
+    return x_fwd_rk_w<W>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
+  }
   static hipError_t gather(hipStream_t s, const void* in0, const void* const* in_tab, void* out, long C, long is,
                            int nb, const Geo& g) {
     hipLaunchKernelGGL((k_gather<T>), dim3(grid_1d(3 * C, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in0,
@@ -229,8 +250,8 @@ struct Impl {
     return hipGetLastError();
   }
   static Ops ops() {
-    return Ops{&strided,     &x_inv_curl, &z_cross,     &z_c2r, &z_r2c, &rk_stage, &gather, &scatter,
-               &imp_predict, &imp_update, &imp_advance, 3,      {WV0, W, WV2}};
+    return Ops{&strided,  &x_inv_curl,  &z_cross,    &z_c2r,       &z_r2c, &rk_stage, &x_fwd_rk,
+               &gather,   &scatter,     &imp_predict, &imp_update, &imp_advance, 3,      {WV0, W, WV2}};
   }
 };
 

@@ -502,6 +502,55 @@ __global__ __launch_bounds__(256) void k_z_r2c(const T* __restrict__ in, cx<T>* 
 //   s=3: U0 = Acc + dt/6 du
 // mode 4: plain right-hand side, Acc = du (stage input U0).
 // ---------------------------------------------------------------------------
+// One mode of the stage update: n0..n2 the dealiased nonlinear term at compact
+// element e (component stride C) with integer wavenumbers kxi, kyi, kz.
+template <typename T>
+__device__ __forceinline__ void rk_update(long e, cx<T> n0, cx<T> n1, cx<T> n2, int kxi, int kyi, int kz,
+                                          cx<T>* __restrict__ U0, cx<T>* __restrict__ U1, cx<T>* __restrict__ Acc,
+                                          long C, int mode, T nu, T dt) {
+  const int k2i = kxi * kxi + kyi * kyi + kz * kz;
+  const T kx = T(kxi), ky = T(kyi), kzf = T(kz), k2 = T(k2i);
+  const cx<T>* us = (mode == 0 || mode == 4) ? U0 : U1;
+  const cx<T> s0 = us[e], s1 = us[C + e], s2 = us[2 * C + e];
+  cx<T> kn = {T(0), T(0)};
+  if (k2i != 0) {
+    const T inv = T(1) / k2;
+    kn = (n0 * kx + n1 * ky + n2 * kzf) * inv;
+  }
+  const T vk = nu * k2;
+  const cx<T> d0 = n0 - kn * kx - s0 * vk;
+  const cx<T> d1 = n1 - kn * ky - s1 * vk;
+  const cx<T> d2 = n2 - kn * kzf - s2 * vk;
+  if (mode == 4) {
+    store_stream(Acc + e, d0);
+    store_stream(Acc + C + e, d1);
+    store_stream(Acc + 2 * C + e, d2);
+    return;
+  }
+  if (mode == 3) {
+    const T h = dt / T(6);
+    store_stream(U0 + e, Acc[e] + d0 * h);
+    store_stream(U0 + C + e, Acc[C + e] + d1 * h);
+    store_stream(U0 + 2 * C + e, Acc[2 * C + e] + d2 * h);
+    return;
+  }
+  const cx<T> a0 = U0[e], a1 = U0[C + e], a2 = U0[2 * C + e];
+  const T ha = (mode == 0) ? dt / T(6) : dt / T(3);
+  const T hu = (mode == 2) ? dt : dt / T(2);
+  if (mode == 0) {
+    store_stream(Acc + e, a0 + d0 * ha);
+    store_stream(Acc + C + e, a1 + d1 * ha);
+    store_stream(Acc + 2 * C + e, a2 + d2 * ha);
+  } else {
+    store_stream(Acc + e, Acc[e] + d0 * ha);
+    store_stream(Acc + C + e, Acc[C + e] + d1 * ha);
+    store_stream(Acc + 2 * C + e, Acc[2 * C + e] + d2 * ha);
+  }
+  store_stream(U1 + e, a0 + d0 * hu);
+  store_stream(U1 + C + e, a1 + d1 * hu);
+  store_stream(U1 + 2 * C + e, a2 + d2 * hu);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, cx<T>* __restrict__ U0,
                                                   cx<T>* __restrict__ U1, cx<T>* __restrict__ Acc, long C,
@@ -519,50 +568,63 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
     const int iy = (int)(r / g.Mzp);
     const int kz = (int)(r - (long)iy * g.Mzp);
     if (kz >= g.Mz) continue;  // row padding
-    const int kxi = kwave(cpos(ix, g), g.N), kyi = kwave(cpos(iy, g), g.N);
-    const int k2i = kxi * kxi + kyi * kyi + kz * kz;
-    const T kx = T(kxi), ky = T(kyi), kzf = T(kz), k2 = T(k2i);
-    const cx<T> n0 = Nh[e], n1 = Nh[C + e], n2 = Nh[2 * C + e];
-    const cx<T>* us = (mode == 0 || mode == 4) ? U0 : U1;
-    const cx<T> s0 = us[e], s1 = us[C + e], s2 = us[2 * C + e];
-    cx<T> kn = {T(0), T(0)};
-    if (k2i != 0) {
-      const T inv = T(1) / k2;
-      kn = (n0 * kx + n1 * ky + n2 * kzf) * inv;
-    }
-    const T vk = nu * k2;
-    const cx<T> d0 = n0 - kn * kx - s0 * vk;
-    const cx<T> d1 = n1 - kn * ky - s1 * vk;
-    const cx<T> d2 = n2 - kn * kzf - s2 * vk;
-    if (mode == 4) {
-      store_stream(Acc + e, d0);
-      store_stream(Acc + C + e, d1);
-      store_stream(Acc + 2 * C + e, d2);
-      continue;
-    }
-    if (mode == 3) {
-      const T h = dt / T(6);
-      store_stream(U0 + e, Acc[e] + d0 * h);
-      store_stream(U0 + C + e, Acc[C + e] + d1 * h);
-      store_stream(U0 + 2 * C + e, Acc[2 * C + e] + d2 * h);
-      continue;
-    }
-    const cx<T> a0 = U0[e], a1 = U0[C + e], a2 = U0[2 * C + e];
-    const T ha = (mode == 0) ? dt / T(6) : dt / T(3);
-    const T hu = (mode == 2) ? dt : dt / T(2);
-    if (mode == 0) {
-      store_stream(Acc + e, a0 + d0 * ha);
-      store_stream(Acc + C + e, a1 + d1 * ha);
-      store_stream(Acc + 2 * C + e, a2 + d2 * ha);
-    } else {
-      store_stream(Acc + e, Acc[e] + d0 * ha);
-      store_stream(Acc + C + e, Acc[C + e] + d1 * ha);
-      store_stream(Acc + 2 * C + e, Acc[2 * C + e] + d2 * ha);
-    }
-    store_stream(U1 + e, a0 + d0 * hu);
-    store_stream(U1 + C + e, a1 + d1 * hu);
-    store_stream(U1 + 2 * C + e, a2 + d2 * hu);
+    rk_update(e, Nh[e], Nh[C + e], Nh[2 * C + e], kwave(cpos(ix, g), g.N), kwave(cpos(iy, g), g.N), kz, U0, U1, Acc,
+              C, mode, nu, dt);
   }
+}
+
+// ---------------------------------------------------------------------------
+// P5 fused with the stage update: forward transform along x of the three
+// components of a tile (one after the other, the first two kept in
+// registers), then the projection, viscous term and RK4 stage update of the
+// retained modes, so that the nonlinear term never goes to HBM.  Input
+// A[3][N rows (x)][Q = M*Mzp cols (ky, kz)]; the state arrays are compact
+// [3][M][Q].  blockIdx.y is the instance of a batch.
+// ---------------------------------------------------------------------------
+template <typename T, class Plan, int W>
+__global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restrict__ A, long csA, long isA,
+                                                          cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
+                                                          cx<T>* __restrict__ Acc, long C, long isU, Geo g, int mode,
+                                                          T nu, T dt) {
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+  __shared__ cx<T> sm[N * W];
+  __shared__ cx<T> tws[N];
+  const long Q = (long)g.M * g.Mzp;
+  const long tile = tile_of_block<PAIR>(blockIdx.x);
+  if (tile * W >= Q) return;  // whole block leaves together
+  const int tid = threadIdx.x;
+  const int c = tid % W, j = tid / W;
+  const long q = tile * W + c;
+  const int iy = (int)(q / g.Mzp);
+  const int kz = (int)(q - (long)iy * g.Mzp);
+  const bool valid = q < Q && kz < g.Mz;
+  const long qq = valid ? q : 0;
+  A += blockIdx.y * isA;
+  U0 += blockIdx.y * isU;
+  U1 += blockIdx.y * isU;
+  Acc += blockIdx.y * isU;
+  TwStage<T, Plan, W * Tl> tw;
+  tw.fetch(tid);
+  cx<T> v[3][R];
+  static_for<0, 3>([&](auto comp) {
+    const cx<T>* a = A + comp * csA + qq;
+    static_for<0, R>([&](auto s) {
+      const cx<T> x = a[(long)(j + s * Tl) * Q];
+      v[comp][s] = valid ? x : cx<T>{T(0), T(0)};
+    });
+    if constexpr (comp == 0) tw.put(tws, tid);
+    LdsCols<T, N, W> lds{sm, c};
+    Plan::template fft<T, -1>(v[comp], j, lds, TwTab<T>{tws});
+  });
+  if (!valid) return;
+  const int kyi = kwave(cpos(iy, g), N);
+  static_for<0, R>([&](auto s) {
+    const int p = j + s * Tl;
+    if (kept(p, g))
+      rk_update((long)crow(p, g) * Q + q, v[0][s], v[1][s], v[2][s], kwave(p, N), kyi, kz, U0, U1, Acc, C, mode,
+                nu, dt);
+  });
 }
 
 // ---------------------------------------------------------------------------

@@ -39,12 +39,15 @@ def workspace(nbytes):
     return ws
 
 
-def run(op, arrays, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0, nsteps=0, inplace=False):
-    """arrays: list of numpy inputs (one per instance).  Returns numpy outputs."""
+def run(op, arrays, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0, nsteps=0, inplace=False, variants=None):
+    """arrays: list of numpy inputs (one per instance).  Returns numpy outputs.
+    variants: {pass name: variant} forced on the plan before the run."""
     torch = _torch()
     ns = [a.shape[1] for a in arrays]
     h, wsb = binding.hot_plan(ns, op, dtype, dealias, nu, dt)
     try:
+        for name, v in (variants or {}).items():
+            binding.hot_set_variant(h, name, v)
         ins = [to_dev(a, dtype) for a in arrays]
         if inplace:
             outs = ins

@@ -227,3 +227,28 @@ def test_mlp_sizes_and_surrogate_rules_without_the_gpu():
     _expect(binding.HOT_E_INVALID, op="rk4", keep_history=True)
     assert lib.hot_mlp_forward(None, None, None, 1, None) == binding.HOT_E_INVALID
     assert lib.hot_mlp_adam(None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, None) == binding.HOT_E_INVALID
+
+
+def test_set_variant_rules_without_the_gpu():
+    lib = binding.library()
+    names = binding.pass_names()
+    h, _ = binding.hot_plan(32, "rk4", "f32", nu=0.01, dt=1e-3)
+    try:
+        for v in (-1, 0, 1):
+            binding.hot_set_variant(h, "x_fwd_rk", v)
+            assert (binding.hot_tuned_width(h, 0, "x_fwd_rk") == 0) == (v < 0)
+        assert lib.hot_set_variant(h, names.index("x_fwd_rk"), 2) == binding.HOT_E_INVALID
+        assert lib.hot_set_variant(h, names.index("y_inv"), 3) == binding.HOT_E_INVALID
+        assert lib.hot_set_variant(h, names.index("z_cross"), 1) == binding.HOT_E_INVALID
+        binding.hot_set_variant(h, "y_inv", 0)
+        binding.hot_set_variant(h, "x_fwd_rk", -1)
+        assert binding.hot_tuned_width(h, 0, "x_fwd_rk") == 0
+        binding.hot_set_variant(h, "x_fwd_rk", 1)
+        assert binding.hot_tuned_width(h, 0, "x_fwd_rk") == binding.hot_tuned_width(h, 0, "x_fwd") > 0
+    finally:
+        binding.hot_destroy(h)
+    h, _ = binding.hot_plan(32, "implicit", "f32", nu=0.01, dt=1e-3)
+    try:
+        assert lib.hot_set_variant(h, names.index("x_fwd_rk"), 0) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)

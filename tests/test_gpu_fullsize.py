@@ -47,12 +47,17 @@ def _small_to_big_index(n):
     return k % N, k
 
 
-def _run(op, x, nsteps=0, nu=NU, dt=1e-3):
+def _run(op, x, nsteps=0, nu=NU, dt=1e-3, tune=False):
+    """tune: autotune the plan first, as bench.py does before it times."""
     torch = _torch()
     h, wsb = binding.hot_plan(N, op, "f32", "two_thirds", nu, dt)
     try:
         y = torch.empty_like(x)
         ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        if tune:
+            binding.hot_tune(h, ws)
+            print("tuned:", {k: binding.hot_tuned_width(h, 0, k) for k in ("x_inv_curl", "y_inv", "y_fwd", "x_fwd",
+                                                                          "x_fwd_rk")}, flush=True)
         binding.hot_run(h, [x], [y], ws, nsteps)
         torch.cuda.synchronize()
         del ws
@@ -92,11 +97,12 @@ def test_taylor_green_rhs_1024_fp32():
     assert _compare_with_small_oracle(y, ref, n) < fp32_tol(N)
 
 
-def test_band_limited_rhs_1024_fp32_matches_oracle_at_128():
-    print("fullsize: R1 rhs", flush=True)
+@pytest.mark.parametrize("tune", [False, True])
+def test_band_limited_rhs_1024_fp32_matches_oracle_at_128(tune):
+    print(f"fullsize: R1 rhs tune={tune}", flush=True)
     ix, iy, iz, vals = inputs.smooth_random_modes(N, seed=0)
     x = _sparse_to_gpu((ix, iy, iz), vals)
-    y = _run("rhs", x)
+    y = _run("rhs", x, tune=tune)
     # the same field on a 128 grid: same wavenumbers, coefficients scaled by (128/1024)^3
     small = inputs.smooth_random(128, seed=0)
     # smooth_random normalises E = 1/8 on each grid, so the two fields are the same
@@ -104,7 +110,8 @@ def test_band_limited_rhs_1024_fp32_matches_oracle_at_128():
     assert _compare_with_small_oracle(y, ref, 128) < fp32_tol(N)
 
 
-def test_beltrami_rk4_1024_fp32_exact_decay():
+@pytest.mark.parametrize("tune", [False, True])
+def test_beltrami_rk4_1024_fp32_exact_decay(tune):
     # Explicit RK4 is stable for the viscous term only while dt nu |k|^2 stays
     # inside its real stability interval (|z| < 2.78); at N = 1024 the largest
     # retained |k|^2 is 3 * 341^2, so nu dt = 5e-6 gives |z| <= 1.75 there.  A
@@ -114,7 +121,7 @@ def test_beltrami_rk4_1024_fp32_exact_decay():
     assert nu * dt * 3 * 341**2 < 2.78
     ix, iy, iz, vals = inputs.beltrami_modes(N, K2, seed=4)
     x = _sparse_to_gpu((ix, iy, iz), vals)
-    y = _run("rk4", x, nsteps=n, nu=nu, dt=dt)
+    y = _run("rk4", x, nsteps=n, nu=nu, dt=dt, tune=tune)
     z = -nu * K2 * dt
     R = 1 + z + z**2 / 2 + z**3 / 6 + z**4 / 24
     torch = _torch()

@@ -195,3 +195,34 @@ def test_radix3_sizes_match_oracle(N, dtype):
     assert rel_l2(got, oracle.rhs(ref_input(uh, dtype), NU)) < tol(dtype, N)
     (got,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1)
     assert rel_l2(got, oracle.rk4(ref_input(uh, dtype), NU, DT, 1)) < tol(dtype, N)
+
+
+# -- the x pass fused with the stage update (x_fwd_rk) -----------------------------
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N,fused", [(16, 1), (32, 0), (64, 1), (24, 1), (128, 0)])
+def test_rk4_with_fused_x_pass_matches_oracle(N, fused, dtype):
+    print(f"rk4 fused={fused} N={N} {dtype}", flush=True)
+    uh = inputs.rough_random(N, 70 + N)
+    (got,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=2, variants={"x_fwd_rk": fused})
+    ref = oracle.rk4(ref_input(uh, dtype), NU, DT, 2)
+    assert rel_l2(got, ref) < tol(dtype, N)
+    M = oracle.retained_mask(N)
+    assert np.all(got[:, ~M] == 0)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_rhs_with_fused_x_pass_matches_oracle(dtype):
+    N = 48
+    uh = inputs.smooth_random(N, 5)
+    (got,) = run("rhs", [uh], dtype, nu=NU, variants={"x_fwd_rk": 1})
+    assert rel_l2(got, oracle.rhs(ref_input(uh, dtype), NU)) < tol(dtype, N)
+
+
+def test_fused_and_separate_x_pass_agree_on_a_batch():
+    fields = [inputs.rough_random(16, 1), inputs.smooth_random(32, 2), inputs.rough_random(24, 4)]
+    a = run("rk4", fields, "f32", nu=NU, dt=DT, nsteps=1, variants={"x_fwd_rk": -1})
+    b = run("rk4", fields, "f32", nu=NU, dt=DT, nsteps=1, variants={"x_fwd_rk": 1})
+    for x, y, f in zip(a, b, fields):
+        assert rel_l2(y, x) < 1e-6
+        assert rel_l2(y, oracle.rk4(round32(f), NU, DT, 1)) < fp32_tol(f.shape[1])
