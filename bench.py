@@ -86,7 +86,7 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, command):
     fs = true_bytes / (fetch[COPY_KERNEL][0] * 1024.0)
     ws = true_bytes / (write[COPY_KERNEL][0] * 1024.0)
     names = {"k_z_cross": "z_cross", "k_x_inv_curl": "x_inv_curl", "k_rk_stage": "rk_stage",
-             "k_gather": "gather", "k_scatter": "scatter", "y_inv": "y_inv"}
+             "k_gather": "gather", "k_scatter": "scatter", "y_inv": "y_inv", "k_x_fwd_rk": "x_fwd_rk"}
     out = {"fetch_scale": fs, "write_scale": ws, "command": command}
     for k, pname in names.items():
         if k in fetch and k in write:
@@ -120,13 +120,20 @@ def _r1_modes(args):
     return inputs.smooth_random_modes(N, seed)
 
 
+GEN_WORKERS = 16  # host processes generating the batch fields (--gen-workers)
+
+
 def batch_modes(sizes, first_seed=1000):
     """R1 modes (seed first_seed + i) of every instance, generated by a
-    process pool; call before the process touches the GPU."""
+    process pool (forked: call before the process touches the GPU), or in
+    this process with one worker."""
     import concurrent.futures
 
-    with concurrent.futures.ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
-        return list(ex.map(_r1_modes, [(int(N), first_seed + i) for i, N in enumerate(sizes)], chunksize=64))
+    jobs = [(int(N), first_seed + i) for i, N in enumerate(sizes)]
+    if GEN_WORKERS <= 1:
+        return [_r1_modes(j) for j in jobs]
+    with concurrent.futures.ProcessPoolExecutor(min(GEN_WORKERS, os.cpu_count() or 1)) as ex:
+        return list(ex.map(_r1_modes, jobs, chunksize=64))
 
 
 def batch_fields(sizes, dtype, first_seed=1000, modes=None):
@@ -337,8 +344,8 @@ def bench_surrogate(a):
     # rows are drawn with probability proportional to s^2: the stopping test
     # measures the increment's error in the field's L2 norm, where a mode's
     # error counts as s * |y - t|
-    wrow = (S.double() ** 2)
-    wrow = wrow / wrow.sum()
+    cdf = torch.cumsum(S.double() ** 2, 0)
+    cdf /= cdf[-1].clone()
     t_data = time.perf_counter() - t0
     rows = X.shape[0]
     # ---- training (FP32 master weights, BF16 MFMA products, Adam)
@@ -365,7 +372,8 @@ def bench_surrogate(a):
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     grad_ms = 0.0
     for step in range(1, a.train_steps + 1):
-        idx = torch.multinomial(wrow, mb, replacement=True, generator=gen)
+        u = torch.rand(mb, dtype=torch.float64, device="cuda", generator=gen)
+        idx = torch.clamp(torch.searchsorted(cdf, u), max=rows - 1)
         torch.index_select(X, 0, idx, out=xb)
         torch.index_select(T, 0, idx, out=tb)
         lr = 1e-3 * (0.5 * (1 + np.cos(np.pi * (step - 1) / a.train_steps)))  # cosine decay
@@ -524,6 +532,7 @@ def main():
                     help="write profiles/counters.json from two rocprofv3 --pmc counter_collection.csv files "
                          "(no GPU needed); use with --calibrate-copy MIB and --pmc-command")
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded with the counters")
+    ap.add_argument("--gen-workers", type=int, default=16, help="batch workloads: field generation processes")
     ap.add_argument("--train-fields", type=int, default=200, help="surrogate: training trajectories")
     ap.add_argument("--train-sizes", default="batch", choices=["batch", "n64"],
                     help="surrogate: training sizes drawn like the batch's, or N = 64 only")
@@ -534,6 +543,8 @@ def main():
                     help="single: one N^3 field (default); batch: many uneven instances, one RK4 step each")
     ap.add_argument("--batch", type=int, default=4096, help="instances of the batch workload")
     a = ap.parse_args()
+    global GEN_WORKERS
+    GEN_WORKERS = a.gen_workers
 
     if a.ingest_counters:
         ingest_counters(a.ingest_counters[0], a.ingest_counters[1], a.calibrate_copy,

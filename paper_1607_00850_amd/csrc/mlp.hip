@@ -45,10 +45,12 @@ using namespace hot;
 namespace {
 
 // Training workspace (floats unless noted): H1, H2, H3, dZa, dZb [rows][256],
-// Y, dY [rows][6], then the loss partial sums (doubles).
+// Y, dY [rows][6], the loss partial sums (doubles), then the split-K pieces
+// of the weight gradients [nsplit][256][256].
+constexpr int kSplitRows = 512;  // rows summed per split-K piece
 struct TrainLayout {
-  size_t h1, h2, h3, za, zb, y, dy, part, bytes;
-  int nparts;
+  size_t h1, h2, h3, za, zb, y, dy, part, split, bytes;
+  int nparts, nsplit;
   explicit TrainLayout(long rows) {
     const size_t big = (size_t)rows * kHid * sizeof(float), small = (size_t)rows * kOut * sizeof(float);
     auto up = [](size_t v) { return (v + 255) / 256 * 256; };
@@ -62,7 +64,10 @@ struct TrainLayout {
     part = dy + up(small);
     long n = ((long)rows * kOut + 255) / 256;
     nparts = (int)(n > 1024 ? 1024 : n);
-    bytes = part + up((size_t)nparts * sizeof(double));
+    split = part + up((size_t)nparts * sizeof(double));
+    nsplit = (int)((rows + kSplitRows - 1) / kSplitRows);
+    if (nsplit > 64) nsplit = 64;
+    bytes = split + up((size_t)nsplit * kHid * kHid * sizeof(float));
   }
 };
 
@@ -72,7 +77,24 @@ hipError_t gemm(hipStream_t s, int M, int N, int K, const float* A, long sam, lo
                 long shm = 0, long shn = 0) {
   const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
   hipLaunchKernelGGL((k_gemm<EPI>), grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, scm, scn, bias, H,
-                     shm, shn);
+                     shm, shn, K, 0L);
+  return hipGetLastError();
+}
+
+// A weight gradient (M, N <= 256, K = rows): K split into nsplit pieces of
+// whole 32-row steps, summed afterwards in a fixed order.
+hipError_t gemm_wgrad(hipStream_t s, int M, int N, int K, const float* A, long sam, long sak, const float* B,
+                      long sbk, long sbn, float* C, long scm, long scn, float* pieces, int nsplit) {
+  const int kchunk = ((K + nsplit - 1) / nsplit + 31) / 32 * 32;
+  const int nz = (K + kchunk - 1) / kchunk;
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)nz);
+  hipLaunchKernelGGL((k_gemm<EPI_NONE>), grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, pieces, (long)N,
+                     1L, (const float*)nullptr, (const float*)nullptr, 0L, 0L, kchunk, (long)M * N);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long MN = (long)M * N;
+  hipLaunchKernelGGL(k_split_sum, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, (const float*)pieces, nz, M,
+                     N, C, scm, scn);
   return hipGetLastError();
 }
 
@@ -114,6 +136,7 @@ int hot_mlp_grad(const float* th, const float* x, const float* t, int32_t rows, 
   float *Za = (float*)(base + L.za), *Zb = (float*)(base + L.zb), *Y = (float*)(base + L.y);
   float* dY = (float*)(base + L.dy);
   double* part = (double*)(base + L.part);
+  float* pieces = (float*)(base + L.split);
   const long R = rows, H = kHid;
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t v) {
@@ -130,20 +153,20 @@ int hot_mlp_grad(const float* th, const float* x, const float* t, int32_t rows, 
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, part, L.nparts, R * kOut, loss);
   ok(hipGetLastError());
   // output layer
-  ok(gemm<EPI_NONE>(s, kOut, kHid, rows, dY, 1, kOut, H3, H, 1, grad + kW4, H, 1));
+  ok(gemm_wgrad(s, kOut, kHid, rows, dY, 1, kOut, H3, H, 1, grad + kW4, H, 1, pieces, L.nsplit));
   hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, s, dY, rows, kOut, grad + kB4);
   ok(hipGetLastError());
   ok(gemm<EPI_DTANH>(s, rows, kHid, kOut, dY, kOut, 1, th + kW4, H, 1, Za, H, 1, nullptr, H3, H, 1));
   // hidden layers 3, 2, 1
-  ok(gemm<EPI_NONE>(s, kHid, kHid, rows, Za, 1, H, H2, H, 1, grad + kW3, H, 1));
+  ok(gemm_wgrad(s, kHid, kHid, rows, Za, 1, H, H2, H, 1, grad + kW3, H, 1, pieces, L.nsplit));
   hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, Za, rows, kHid, grad + kB3);
   ok(hipGetLastError());
   ok(gemm<EPI_DTANH>(s, rows, kHid, kHid, Za, H, 1, th + kW3, H, 1, Zb, H, 1, nullptr, H2, H, 1));
-  ok(gemm<EPI_NONE>(s, kHid, kHid, rows, Zb, 1, H, H1, H, 1, grad + kW2, H, 1));
+  ok(gemm_wgrad(s, kHid, kHid, rows, Zb, 1, H, H1, H, 1, grad + kW2, H, 1, pieces, L.nsplit));
   hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, Zb, rows, kHid, grad + kB2);
   ok(hipGetLastError());
   ok(gemm<EPI_DTANH>(s, rows, kHid, kHid, Zb, H, 1, th + kW2, H, 1, Za, H, 1, nullptr, H1, H, 1));
-  ok(gemm<EPI_NONE>(s, kHid, kIn, rows, Za, 1, H, x, kIn, 1, grad + kW1, kIn, 1));
+  ok(gemm_wgrad(s, kHid, kIn, rows, Za, 1, H, x, kIn, 1, grad + kW1, kIn, 1, pieces, L.nsplit));
   hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, Za, rows, kHid, grad + kB1);
   ok(hipGetLastError());
   return e == hipSuccess ? HOT_OK : HOT_E_HIP;

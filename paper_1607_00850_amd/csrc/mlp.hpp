@@ -68,7 +68,9 @@ __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
 // ---------------------------------------------------------------------------
 // Training GEMM: C(m, n) = epi(sum_k A(m, k) B(k, n)) for FP32 operands with
 // arbitrary strides, rounded to BF16 while staged into LDS.  64 x 64 tile per
-// 256-thread block (2 x 2 waves of 32 x 32), k-steps of 32.
+// 256-thread block (2 x 2 waves of 32 x 32), k-steps of 32.  Split K:
+// blockIdx.z sums k in [z kchunk, (z + 1) kchunk) into C + z csz (EPI_NONE;
+// k_split_sum adds the pieces).
 //   EPI_NONE: C = acc
 //   EPI_BIAS: C = acc + bias[n]
 //   EPI_BIAS_TANH: C = tanh(acc + bias[n])
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
                                               const float* __restrict__ B, long sbk, long sbn,
                                               float* __restrict__ C, long scm, long scn,
                                               const float* __restrict__ bias, const float* __restrict__ H, long shm,
-                                              long shn) {
+                                              long shn, int kchunk, long csz) {
   constexpr int LD = 40;  // 32 + 8: rows 80 bytes apart, conflict-free 16-byte fragment reads
   __shared__ __attribute__((aligned(16))) unsigned short As[64 * LD];
   __shared__ __attribute__((aligned(16))) unsigned short Bs[64 * LD];
@@ -92,13 +94,15 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  C += blockIdx.z * csz;
+  for (int k0 = kb; k0 < ke; k0 += 32) {
     float av[8], bv[8];
     const int m = m0 + sr, n = n0 + sr;
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + sk + i;
-      av[i] = (m < M && k < K) ? A[m * sam + k * sak] : 0.f;
-      bv[i] = (n < N && k < K) ? B[k * sbk + n * sbn] : 0.f;
+      av[i] = (m < M && k < ke) ? A[m * sam + k * sak] : 0.f;
+      bv[i] = (n < N && k < ke) ? B[k * sbk + n * sbn] : 0.f;
     }
     __syncthreads();  // the previous step's fragments have been read
     *(uint4*)&As[sr * LD + sk] = uint4{pack2(av[0], av[1]), pack2(av[2], av[3]), pack2(av[4], av[5]), pack2(av[6], av[7])};
@@ -124,6 +128,18 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
         }
         C[m * scm + n * scn] = v;
       }
+}
+
+// C(m, n) = sum over z < nz of P[z][m][n] (fixed order), P of [nz][M][N].
+__global__ __launch_bounds__(256) void k_split_sum(const float* __restrict__ P, int nz, int M, int N,
+                                                   float* __restrict__ C, long scm, long scn) {
+  const long MN = (long)M * N;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < MN; i += (long)gridDim.x * 256) {
+    float s = 0.f;
+    for (int z = 0; z < nz; ++z) s += P[z * MN + i];
+    const int m = (int)(i / N), n = (int)(i - (long)m * N);
+    C[m * scm + n * scn] = s;
+  }
 }
 
 // Loss and output gradient: R = Y - T, dY = 2 R / (rows * 6); part[block] =

@@ -58,7 +58,7 @@ def test_fused_forward_matches_reference(rows):
     assert _rel(got, ref64) < 5e-2
 
 
-@pytest.mark.parametrize("rows", [64, 300])
+@pytest.mark.parametrize("rows", [64, 300, 1100])  # 1100: the weight gradients split K in 3
 def test_gradient_matches_reference(rows):
     print(f"mlp grad rows={rows}", flush=True)
     torch = _torch()
