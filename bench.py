@@ -481,6 +481,70 @@ def bench_surrogate(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_tg(a):
+    """Taylor-Green vortex at Re = 1600 (Sec. 4), one long RK4 run: the
+    kinetic energy E(t), the dissipation rate eps(t) = nu <|omega|^2> after
+    every step, and the residual of the energy budget dE/dt = -eps of the
+    dealiased Galerkin system (trapezoid rule between steps).  There is no
+    reference solution to compare with, so the run checks itself."""
+    import numpy as np
+    import torch
+
+    from paper_1607_00850_amd import binding, inputs
+
+    N, steps, dtype = a.tg_n, a.tg_steps, a.dtype
+    cdt = torch.complex64 if dtype == "f32" else torch.complex128
+    u = torch.from_numpy(inputs.taylor_green(N)).to(cdt).cuda()
+    plan, wsb = binding.hot_plan(N, "rk4", dtype, "two_thirds", NU, DT)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    diag = torch.empty((steps + 1, 2), dtype=torch.float64, device="cuda")
+    try:
+        binding.hot_tune(plan, ws)
+        binding.hot_diagnostics(plan, [u], ws, diag[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(steps):
+            binding.hot_run(plan, [u], [u], ws, 1)
+            binding.hot_diagnostics(plan, [u], ws, diag[n + 1])
+            if (n + 1) % 2000 == 0:
+                torch.cuda.synchronize()
+                print(f"tg step {n + 1}: E {float(diag[n + 1, 0]):.6f} eps {float(diag[n + 1, 1]):.6g}",
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        binding.hot_destroy(plan)
+    d = diag.cpu().numpy()
+    E, eps = d[:, 0], d[:, 1]
+    t = DT * np.arange(steps + 1)
+    resid = (E[1:] - E[:-1]) / DT + 0.5 * (eps[1:] + eps[:-1])
+    k = int(np.argmax(eps))
+    every = max(1, steps // 40)
+    line = {
+        "metric": "instances/sec",
+        "value": steps / el,
+        "unit": "RK4 steps/s of one field (diagnostics after every step included)",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": el * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "Taylor-Green initial field (Sec. 4), Re = 1600",
+        "config": {"workload": f"taylor_green_re1600_{N}^3_{dtype}", "N": N, "nu": NU, "dt": DT, "t_end": DT * steps},
+        "E0": float(E[0]),
+        "eps0": float(eps[0]),
+        "E_end": float(E[-1]),
+        "eps_peak": {"t": float(t[k]), "value": float(eps[k])},
+        "budget_residual": {"max_abs_over_peak_eps": float(np.max(np.abs(resid)) / eps[k]),
+                            "rms_over_peak_eps": float(np.sqrt(np.mean(resid ** 2)) / eps[k])},
+        "series": [[float(t[i]), float(E[i]), float(eps[i])] for i in range(0, steps + 1, every)],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(N_work, seconds=12.0):
     """Time the CPU oracle (one core) on RK4 steps at N = 128 and scale to
     instances/s of an N_work^3 step by the FFT cost N^3 log2 N."""
@@ -533,13 +597,15 @@ def main():
                          "(no GPU needed); use with --calibrate-copy MIB and --pmc-command")
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded with the counters")
     ap.add_argument("--gen-workers", type=int, default=16, help="batch workloads: field generation processes")
+    ap.add_argument("--tg-n", type=int, default=256, help="tg: points per axis")
+    ap.add_argument("--tg-steps", type=int, default=20000, help="tg: RK4 steps (dt = 1e-3)")
     ap.add_argument("--train-fields", type=int, default=200, help="surrogate: training trajectories")
     ap.add_argument("--train-sizes", default="batch", choices=["batch", "n64"],
                     help="surrogate: training sizes drawn like the batch's, or N = 64 only")
     ap.add_argument("--train-steps", type=int, default=3000, help="surrogate: Adam steps")
     ap.add_argument("--minibatch", type=int, default=4096, help="surrogate: rows per Adam step")
     ap.add_argument("--surrogate-batch", type=int, default=16384, help="surrogate: instances compared")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "surrogate"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "surrogate", "tg"],
                     help="single: one N^3 field (default); batch: many uneven instances, one RK4 step each")
     ap.add_argument("--batch", type=int, default=4096, help="instances of the batch workload")
     a = ap.parse_args()
@@ -566,6 +632,9 @@ def main():
         return
     if a.workload == "surrogate":
         bench_surrogate(a)
+        return
+    if a.workload == "tg":
+        bench_tg(a)
         return
 
     if a.calibrate_copy > 0:

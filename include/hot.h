@@ -239,6 +239,18 @@ int hot_mlp_dataset(int32_t N, int32_t dtype, const void* u, const void* d1, con
  * Errors: HOT_E_INVALID (null plan, op not IMPLICIT, misaligned pointer). */
 int hot_set_surrogate(hot_plan_t p, const void* packed);
 
+/* Diagnostics of every instance's spectral field in[i] (canonical layout, the
+ * plan's element type and N): out[2i] = E = (1/2N^6) sum_k |u_k|^2, the
+ * kinetic energy by Parseval under Eq. ffteq, and out[2i+1] = eps =
+ * nu (1/N^6) sum_k |k|^2 |u_k|^2 = nu <|omega|^2>, the rate at which the
+ * viscous term of Eq. NSfinal removes energy (sums over the full spectrum,
+ * written over the half spectrum).  out: device doubles [batch][2],
+ * written on stream (FP64 sums in a fixed order).  The first
+ * 2 * batch * 128 doubles of the workspace serve as scratch: between
+ * hot_run calls nothing lives there.  Errors: HOT_E_INVALID,
+ * HOT_E_WORKSPACE, HOT_E_HIP. */
+int hot_diagnostics(hot_plan_t p, void* const* in, void* workspace, double* out, void* stream);
+
 /* Release the plan's host state (waits for its pending profiling events).
  * NULL is accepted and ignored. */
 int hot_destroy(hot_plan_t p);

@@ -97,6 +97,8 @@ def _lib():
         lib.hot_tune.restype = ctypes.c_int
         lib.hot_tuned_width.argtypes = [vp, i32, i32]
         lib.hot_tuned_width.restype = ctypes.c_int
+        lib.hot_diagnostics.argtypes = [vp, ctypes.POINTER(vp), vp, vp, vp]
+        lib.hot_diagnostics.restype = ctypes.c_int
         lib.hot_set_variant.argtypes = [vp, i32, i32]
         lib.hot_set_variant.restype = ctypes.c_int
         lib.hot_implicit_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -349,3 +351,13 @@ def hot_mlp_dataset(N, dtype, u, d1, d2, d, nu, dt, x, t=None, s=None, stream=No
     of one field."""
     _check(_lib().hot_mlp_dataset(int(N), DTYPES[dtype], _ptr(u), _ptr(d1), _ptr(d2), _ptr(d), float(nu), float(dt),
                                   _ptr(x), _ptr(t), _ptr(s), _stream(stream)), "hot_mlp_dataset")
+
+
+def hot_diagnostics(plan, ins, workspace, out, stream=None):
+    """Energy and dissipation rate of each instance into the device double
+    tensor out[batch][2] (see include/hot.h)."""
+    n = len(ins)
+    pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
+    rc = _lib().hot_diagnostics(plan, pin, _ptr(workspace), _ptr(out), _stream(stream))
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_diagnostics", _lib().hot_last_hip_error(plan))

@@ -780,6 +780,63 @@ __global__ __launch_bounds__(256) void k_imp_advance(cx<T>* __restrict__ U0, con
 }
 
 // ---------------------------------------------------------------------------
+// Diagnostics of a canonical half-spectrum field [3][N][N][N/2+1]:
+//   E   = sum_half w |u_k|^2 / (2 N^6)         kinetic energy (Parseval under Eq. ffteq)
+//   eps = nu sum_half w |k|^2 |u_k|^2 / N^6    = nu <|omega|^2>, the rate at which
+//                                               the viscous term of Eq. NSfinal removes energy
+// with w = 1 on the kz = 0 and kz = N/2 planes and 2 elsewhere.  Per-block FP64
+// partial sums part[block][2], summed in a fixed order by k_diag_final.
+// One launch per instance.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(const cx<T>* __restrict__ u, int N, double* __restrict__ part) {
+  __shared__ double red[4];
+  const long Nh = N / 2 + 1, plane = (long)N * Nh, comp = (long)N * plane;
+  double se = 0.0, sd = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < comp; e += (long)gridDim.x * 256) {
+    const int px = (int)(e / plane);
+    const long r = e - px * plane;
+    const int py = (int)(r / Nh);
+    const int kz = (int)(r - (long)py * Nh);
+    const int kx = kwave(px, N), ky = kwave(py, N);
+    double a = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const cx<T> v = u[c * comp + e];
+      a += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    const double w = (kz == 0 || 2 * kz == N) ? 1.0 : 2.0;
+    se += w * a;
+    sd += w * (double)(kx * kx + ky * ky + kz * kz) * a;
+  }
+  se = block_sum_256(se, red);
+  sd = block_sum_256(sd, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = se;
+    part[2 * blockIdx.x + 1] = sd;
+  }
+}
+
+// out[0..2) = {E, eps} from one instance's nparts partial sums (one wave).
+template <int Unused = 0>
+__global__ __launch_bounds__(64) void k_diag_final(const double* __restrict__ part, int nparts, int N, double nu,
+                                                   double* __restrict__ out) {
+  double se = 0.0, sd = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 64) {
+    se += part[2 * i];
+    sd += part[2 * i + 1];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    se += __shfl_xor(se, o, 64);
+    sd += __shfl_xor(sd, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    const double n6 = (double)N * N * N * N * N * N;
+    out[0] = se / (2.0 * n6);
+    out[1] = nu * sd / n6;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Canonical <-> compact.  Canonical: [3][N][N][N/2+1].  Compact:
 // [3][M][M][Mzp].  Gather drops the modes outside the retained set
 // (projection onto the Galerkin space); scatter writes zeros there.

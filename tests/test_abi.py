@@ -252,3 +252,20 @@ def test_set_variant_rules_without_the_gpu():
         assert lib.hot_set_variant(h, names.index("x_fwd_rk"), 0) == binding.HOT_E_INVALID
     finally:
         binding.hot_destroy(h)
+
+
+def test_diagnostics_argument_checks_without_the_gpu():
+    lib = binding.library()
+    h, _ = binding.hot_plan(16, "rk4", "f64", nu=0.01, dt=1e-3)
+    try:
+        arr = (ctypes.c_void_p * 1)(256 * 1000)
+        assert lib.hot_diagnostics(h, arr, ctypes.c_void_p(256), None, None) == binding.HOT_E_INVALID
+        assert lib.hot_diagnostics(h, arr, None, ctypes.c_void_p(256), None) == binding.HOT_E_WORKSPACE
+        assert lib.hot_diagnostics(h, arr, ctypes.c_void_p(256 + 8), ctypes.c_void_p(256), None) == \
+            binding.HOT_E_WORKSPACE
+        nul = (ctypes.c_void_p * 1)(None)
+        assert lib.hot_diagnostics(h, nul, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == binding.HOT_E_INVALID
+        assert lib.hot_diagnostics(None, arr, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == \
+            binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
