@@ -101,7 +101,8 @@ struct ZShape {
   static constexpr bool kBlock = Tl > 64;
   static constexpr int LPW = kBlock ? 1 : 64 / Tl;        // lines per wave
   static constexpr int LPB = kBlock ? 256 / Tl : 4 * LPW;  // lines per block
-  static constexpr int SLOTS = LPB + (kBlock ? 0 : 4);     // + one dummy line per wave
+  static constexpr bool kIdle = !kBlock && LPW * Tl < 64;  // lanes without a line
+  static constexpr int SLOTS = LPB + (kIdle ? 4 : 0);      // + one dummy line per wave
   // line slot and lane index of thread tid; live == false for idle lanes
   __device__ __forceinline__ static void place(int tid, int& li, int& j, bool& live) {
     if constexpr (kBlock) {
