@@ -128,3 +128,59 @@ def test_beltrami_rk4_1024_fp32_exact_decay(tune):
     err = torch.linalg.vector_norm((y - x * R**n).reshape(-1).to(torch.complex128))
     den = torch.linalg.vector_norm((x * R**n).reshape(-1).to(torch.complex128))
     assert float(err / den) < fp32_tol(N)
+
+
+def test_band_limited_rhs_1024_fp64_matches_oracle_at_128():
+    # the largest size in FP64 (workspace ~90 GB): FP64 bar of the parity tests
+    print("fullsize: R1 rhs fp64", flush=True)
+    torch = _torch()
+    ix, iy, iz, vals = inputs.smooth_random_modes(N, seed=0)
+    x = torch.zeros((3, N, N, N // 2 + 1), dtype=torch.complex128, device="cuda")
+    idx = [torch.from_numpy(np.asarray(a)).long().cuda() for a in (ix, iy, iz)]
+    x[:, idx[0], idx[1], idx[2]] = torch.from_numpy(np.asarray(vals)).cuda()
+    h, wsb = binding.hot_plan(N, "rhs", "f64", "two_thirds", NU, 1e-3)
+    try:
+        y = torch.empty_like(x)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        binding.hot_run(h, [x], [y], ws, 0)
+        torch.cuda.synchronize()
+        del ws
+    finally:
+        binding.hot_destroy(h)
+    ref = oracle.rhs(inputs.smooth_random(128, seed=0), NU)
+    big_idx, k = _small_to_big_index(128)
+    kz = np.arange(65)
+    keep = np.abs(k) < 64
+    r = ref[:, keep][:, :, keep][:, :, :, kz < 64] * (N / 128) ** 3
+    bi = big_idx[keep]
+    IX, IY, IZ = np.meshgrid(bi, bi, kz[kz < 64], indexing="ij")
+    sel = [torch.from_numpy(a.ravel()).long().cuda() for a in (IX, IY, IZ)]
+    got = y[:, sel[0], sel[1], sel[2]].cpu().numpy().reshape(r.shape)
+    assert np.linalg.norm(got - r) <= 1e-12 * np.linalg.norm(r)
+    # every other coefficient is zero: the norms agree
+    assert float(torch.linalg.vector_norm(y)) == pytest.approx(float(np.linalg.norm(r)), rel=1e-12)
+
+
+def test_implicit_beltrami_1024_fp32_crank_nicolson_factor():
+    # the implicit step at full size: a Beltrami field decays by (1 - a)/(1 + a) per step
+    print("fullsize: Beltrami implicit", flush=True)
+    torch = _torch()
+    K2, nu, dt, n = 10000, 1e-3, 5e-3, 2
+    ix, iy, iz, vals = inputs.beltrami_modes(N, K2, seed=4)
+    x = _sparse_to_gpu((ix, iy, iz), vals)
+    h, wsb = binding.hot_plan(N, "implicit", "f32", "two_thirds", nu, dt, 1e-5, 10)
+    try:
+        y = torch.empty_like(x)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        assert binding.hot_run(h, [x], [y], ws, n) == binding.HOT_OK
+        torch.cuda.synchronize()
+        sweeps, _ = binding.hot_implicit_stats(h, 1)
+        del ws
+    finally:
+        binding.hot_destroy(h)
+    a = 0.5 * dt * nu * K2
+    R = ((1 - a) / (1 + a)) ** n
+    err = torch.linalg.vector_norm((y - x * R).reshape(-1).to(torch.complex128))
+    den = torch.linalg.vector_norm((x * R).reshape(-1).to(torch.complex128))
+    assert float(err / den) < fp32_tol(N)
+    assert sweeps == [2 * n]
