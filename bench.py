@@ -32,6 +32,13 @@ NU = 1.0 / 1600.0  # Re = 1600 (Sec. 4)
 DT = 1e-3          # Sec. 4
 
 
+def unpruned_step_bytes(N, elem):
+    """Bytes of one RK4 step in the unpruned three-pass model: 204 passes of a
+    full half-spectrum component, S(N) = N^2 (N/2 + 1) complex values.  The
+    pruned passes here move less; this model is only a reference point."""
+    return 204.0 * N * N * (N // 2 + 1) * elem
+
+
 def source_hash():
     """Hash of the sources of the right-hand-side and RK4 kernels."""
     h = hashlib.sha256()
@@ -265,6 +272,11 @@ def bench_batch(a):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / t_graph / 1e9,
                           "frac": step_bytes / t_graph / 1e9 / HBM_PEAK_GBS},
+        "step_roofline_unpruned_model": {
+            "model_bytes_per_step": float(sum(unpruned_step_bytes(int(n), 8 if a.dtype == "f32" else 16)
+                                              for n in sizes)),
+            "frac": float(sum(unpruned_step_bytes(int(n), 8 if a.dtype == "f32" else 16) for n in sizes))
+                    / t_graph / 1e9 / HBM_PEAK_GBS},
         "setup_seconds": {"fields": t_gen},
     }
     print(json.dumps(line), flush=True)
@@ -702,6 +714,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (ms_step / 1e3) / 1e9,
                           "frac": step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "step_roofline_unpruned_model": {
+            "model_bytes_per_step": unpruned_step_bytes(N, 8 if dtype == "f32" else 16),
+            "frac": unpruned_step_bytes(N, 8 if dtype == "f32" else 16) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "passes": passes,
         "tuned_columns": widths,
     }
