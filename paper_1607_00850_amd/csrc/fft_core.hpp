@@ -324,11 +324,11 @@ struct LinePlan {
   static constexpr int N = N_;
   static constexpr int R = R_;
   static constexpr int Tl = N_ / R_;
-  // First-stage writes go to positions r1 apart (r1 = first radix); padding
-  // one slot every 2^SH positions of a contiguous line spreads them over the
-  // LDS banks.
+  // First-stage writes go to positions r1 apart (r1 = first radix); the LDS
+  // line view spreads them over the banks (an XOR swizzle for r1 >= 16, one
+  // padding slot every 2^SH positions below).
   static constexpr int SH = ilog2<FirstOf<Rs...>::value>();
-  static constexpr int line_slots = N_ + (N_ >> SH) + 1;
+  static constexpr int line_slots = SH >= 4 ? N_ : N_ + (N_ >> SH) + 1;
   template <typename T>
   static constexpr StageTw<T, N_> twiddles() {
     return make_stage_tw<T, N_, Rs...>();

@@ -77,12 +77,19 @@ struct LdsCols {
 };
 
 // LDS view for one contiguous line owned by a lane group (inside one wave,
-// or whole waves of the block when BLOCK); one padding slot every 2^SH
-// positions.
+// or whole waves of the block when BLOCK).  First-stage writes of
+// neighbouring lanes are 2^SH positions apart: for SH >= 4 bits 1-3 of the
+// position are XOR-ed with the 2^SH-block index, below that one padding slot
+// follows every 2^SH positions.
 template <typename T, int SH, bool BLOCK>
 struct LdsLine {
   cx<T>* base;
-  __device__ __forceinline__ static int sw(int p) { return p + (p >> SH); }
+  __device__ __forceinline__ static int sw(int p) {
+    // first radix >= 16: XOR bits 1-3 with the block index (no padding;
+    // measured 1-3% faster than the padding in z_cross at N = 1024)
+    if constexpr (SH >= 4) return p ^ (((p >> SH) & 7) << 1);
+    else return p + (p >> SH);
+  }
   __device__ __forceinline__ void put(int pos, cx<T> v) { base[sw(pos)] = v; }
   __device__ __forceinline__ cx<T> get(int pos) const { return base[sw(pos)]; }
   __device__ __forceinline__ void sync() {
