@@ -245,10 +245,10 @@ int hot_set_surrogate(hot_plan_t p, const void* packed);
  * nu (1/N^6) sum_k |k|^2 |u_k|^2 = nu <|omega|^2>, the rate at which the
  * viscous term of Eq. NSfinal removes energy (sums over the full spectrum,
  * written over the half spectrum).  out: device doubles [batch][2],
- * written on stream (FP64 sums in a fixed order).  The first
- * 2 * batch * 128 doubles of the workspace serve as scratch: between
- * hot_run calls nothing lives there.  Errors: HOT_E_INVALID,
- * HOT_E_WORKSPACE, HOT_E_HIP. */
+ * written on stream (FP64 sums in a fixed order).  The first 2 KiB of the
+ * workspace serve as scratch (one instance after the other): between
+ * hot_run calls nothing lives there, kept implicit histories included.
+ * Errors: HOT_E_INVALID, HOT_E_WORKSPACE, HOT_E_HIP. */
 int hot_diagnostics(hot_plan_t p, void* const* in, void* workspace, double* out, void* stream);
 
 /* Release the plan's host state (waits for its pending profiling events).

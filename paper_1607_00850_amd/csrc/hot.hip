@@ -1,5 +1,6 @@
 // libhot host side: plan validation, workspace layout, pass schedule and the
-// C ABI of include/hot.h.  All arithmetic runs in the kernels of kernels.hpp.
+// C ABI of include/hot.h.  All arithmetic runs in the kernels of kernels.hpp
+// (and, for the surrogate warm start, mlp.hpp).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -663,25 +664,23 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
 extern "C" int hot_diagnostics(hot_plan_t p, void* const* in, void* workspace, double* out, void* stream) {
   if (!p || !in || !out || ((uintptr_t)out & 7) != 0) return HOT_E_INVALID;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
-  constexpr int kParts = 128;
-  if ((size_t)p->batch * kParts * 2 * sizeof(double) > p->ws_bytes) return HOT_E_WORKSPACE;
+  constexpr int kParts = 128;  // partial sums of one instance: 2 KiB of scratch
+  if ((size_t)kParts * 2 * sizeof(double) > p->ws_bytes) return HOT_E_WORKSPACE;
   for (int i = 0; i < p->batch; ++i)
     if (!in[i] || ((uintptr_t)in[i] % kAlign) != 0) return HOT_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
   double* part = (double*)workspace;
   hipError_t e = hipSuccess;
+  // one instance after the other through the same scratch (stream order)
   for (int i = 0; i < p->batch && e == hipSuccess; ++i) {
-    double* pi = part + 2L * kParts * i;
     if (p->dtype == HOT_F64)
-      hipLaunchKernelGGL(k_diag<double>, dim3(kParts), dim3(256), 0, s, (const cx<double>*)in[i], p->n[i], pi);
+      hipLaunchKernelGGL(k_diag<double>, dim3(kParts), dim3(256), 0, s, (const cx<double>*)in[i], p->n[i], part);
     else
-      hipLaunchKernelGGL(k_diag<float>, dim3(kParts), dim3(256), 0, s, (const cx<float>*)in[i], p->n[i], pi);
+      hipLaunchKernelGGL(k_diag<float>, dim3(kParts), dim3(256), 0, s, (const cx<float>*)in[i], p->n[i], part);
     e = hipGetLastError();
-  }
-  // one final sum per instance (N differs between instances; nu is the plan's)
-  for (int i = 0; i < p->batch && e == hipSuccess; ++i) {
-    hipLaunchKernelGGL(k_diag_final<>, dim3(1), dim3(64), 0, s, (const double*)(part + 2L * kParts * i), kParts,
-                       p->n[i], p->nu, out + 2 * i);
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_diag_final<>, dim3(1), dim3(64), 0, s, (const double*)part, kParts, p->n[i], p->nu,
+                       out + 2 * i);
     e = hipGetLastError();
   }
   if (e != hipSuccess) {

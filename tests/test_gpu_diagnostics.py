@@ -67,3 +67,30 @@ def test_taylor_green_energy_budget():
     # energy decays monotonically; dissipation grows as the vortices stretch
     assert np.all(np.diff(E) < 0)
     assert eps[-1] > eps[0]
+
+
+def test_diagnostics_leave_kept_implicit_history_intact():
+    # a batch whose first size group is small: the diagnostics' scratch must
+    # stay clear of the kept increment histories between calls
+    torch = _torch()
+    fields = [inputs.smooth_random(16, 50)] + [inputs.rough_random(24, 51 + i) for i in range(8)]
+    ns = [f.shape[1] for f in fields]
+
+    def run(with_diag):
+        h, wsb = binding.hot_plan(ns, "implicit", "f64", nu=NU, dt=0.02, tol=1e-10, max_iter=50,
+                                  keep_history=True)
+        try:
+            ws = workspace(wsb)
+            xs = [to_dev(f, "f64") for f in fields]
+            binding.hot_run(h, xs, xs, ws, 2)
+            if with_diag:
+                out = torch.empty((len(fields), 2), dtype=torch.float64, device="cuda")
+                binding.hot_diagnostics(h, xs, ws, out)
+            binding.hot_run(h, xs, xs, ws, 2)
+            torch.cuda.synchronize()
+            return [x.cpu().numpy() for x in xs]
+        finally:
+            binding.hot_destroy(h)
+
+    for a, b in zip(run(False), run(True)):
+        np.testing.assert_array_equal(a, b)
