@@ -44,6 +44,7 @@ extern "C" {
 #define HOT_E_UNSUPPORTED (-2) /* valid request this build does not implement (e.g. an N) */
 #define HOT_E_WORKSPACE (-3)   /* workspace pointer null or misaligned */
 #define HOT_E_HIP (-4)         /* a HIP call failed; hot_last_hip_error() has the code */
+#define HOT_E_NONFINITE (-5)   /* HOT_FLAG_CHECK_FINITE: a result holds a NaN or an infinity */
 #define HOT_E_NOCONVERGE (-6)  /* IMPLICIT: an instance hit max_iter sweeps (its last iterate is kept) */
 
 /* Element type. */
@@ -95,6 +96,11 @@ extern "C" {
  * previous call on the same plan and workspace; the caller passes the state
  * that call returned.  Without it every call starts without history. */
 #define HOT_FLAG_KEEP_HISTORY 1
+/* CHECK_FINITE (RHS, RK4, IMPLICIT): hot_run ends by scanning every
+ * instance's result (its retained modes) for NaN and infinity and returns
+ * HOT_E_NONFINITE if it finds one; this costs one synchronisation, so such a
+ * plan cannot be captured in a graph.  The workspace grows by 256 bytes. */
+#define HOT_FLAG_CHECK_FINITE 2
 
 typedef struct hot_desc {
   int32_t abi_version; /* HOT_ABI_VERSION */
@@ -105,7 +111,7 @@ typedef struct hot_desc {
   int32_t dtype;       /* HOT_F64 or HOT_F32 */
   int32_t dealias;     /* HOT_DEALIAS_* (RHS and RK4) */
   int32_t op;          /* HOT_OP_* */
-  int32_t flags;       /* HOT_FLAG_* (0 or KEEP_HISTORY for IMPLICIT) */
+  int32_t flags;       /* HOT_FLAG_* (KEEP_HISTORY: IMPLICIT only; CHECK_FINITE: RHS, RK4, IMPLICIT) */
   double tol;          /* IMPLICIT: relative stopping tolerance (> 0); ignored otherwise */
   int32_t max_iter;    /* IMPLICIT: sweeps per step at most (>= 1); ignored otherwise */
   int32_t reserved;    /* must be 0 */
@@ -137,7 +143,9 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes);
  * Errors: HOT_E_INVALID (null plan/pointer, nsteps < 0), HOT_E_WORKSPACE,
  * HOT_E_HIP (launch failure; the plan keeps the HIP error code),
  * HOT_E_NOCONVERGE (IMPLICIT only: the whole call ran, some step of some
- * instance stopped at max_iter; hot_implicit_stats says which). */
+ * instance stopped at max_iter; hot_implicit_stats says which),
+ * HOT_E_NONFINITE (HOT_FLAG_CHECK_FINITE: the whole call ran and a result
+ * holds a NaN or an infinity; takes precedence over HOT_E_NOCONVERGE). */
 int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps, void* stream);
 
 /* A captured hot_run: the whole operation (every pass of every instance and
@@ -146,7 +154,8 @@ int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, in
  * stream (NULL); the pointer tables are uploaded first, outside the capture.
  * The graph keeps the pointers it was created with.  Per-pass profiling is
  * not recorded inside graphs.  Errors as hot_run; HOT_E_UNSUPPORTED for
- * IMPLICIT, whose sweep count is decided on the host. */
+ * IMPLICIT, whose sweep count is decided on the host, and for plans with
+ * HOT_FLAG_CHECK_FINITE. */
 typedef struct hot_graph_s* hot_graph_t;
 int hot_graph_create(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
                      void* stream, hot_graph_t* graph);

@@ -18,6 +18,7 @@ HOT_E_INVALID = -1
 HOT_E_UNSUPPORTED = -2
 HOT_E_WORKSPACE = -3
 HOT_E_HIP = -4
+HOT_E_NONFINITE = -5
 HOT_E_NOCONVERGE = -6
 
 HOT_F64, HOT_F32 = 0, 1
@@ -25,6 +26,7 @@ HOT_DEALIAS_TWO_THIRDS, HOT_DEALIAS_NONE = 0, 1
 HOT_OP_R2C, HOT_OP_C2R, HOT_OP_RHS, HOT_OP_RK4, HOT_OP_IMPLICIT = 0, 1, 2, 3, 4
 
 HOT_FLAG_KEEP_HISTORY = 1
+HOT_FLAG_CHECK_FINITE = 2
 
 DTYPES = {"f64": HOT_F64, "f32": HOT_F32}
 DEALIAS = {"two_thirds": HOT_DEALIAS_TWO_THIRDS, "none": HOT_DEALIAS_NONE}
@@ -134,12 +136,13 @@ def library():
 
 
 def hot_plan(n, op, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0, tol=1e-10, max_iter=50,
-             keep_history=False):
+             keep_history=False, check_finite=False):
     """Plan an operation; returns (handle, workspace_bytes).  n: int or list.
-    tol, max_iter, keep_history: the implicit step (ignored otherwise)."""
+    tol, max_iter, keep_history: the implicit step (ignored otherwise);
+    check_finite: hot_run scans its results for NaN and infinity."""
     ns = [int(n)] if isinstance(n, int) else [int(v) for v in n]
     arr = (ctypes.c_int32 * len(ns))(*ns)
-    flags = HOT_FLAG_KEEP_HISTORY if keep_history else 0
+    flags = (HOT_FLAG_KEEP_HISTORY if keep_history else 0) | (HOT_FLAG_CHECK_FINITE if check_finite else 0)
     d = HotDesc(HOT_ABI_VERSION, len(ns), arr, float(nu), float(dt), DTYPES[dtype], DEALIAS[dealias], OPS[op],
                 flags, float(tol), int(max_iter), 0)
     h = ctypes.c_void_p()
@@ -171,14 +174,15 @@ def hot_run(plan, ins, outs, workspace, nsteps=0, stream=None):
     """Enqueue the planned op.  ins/outs: sequences of device tensors (or raw
     pointers), one per instance; workspace: device tensor or pointer;
     stream: a torch.cuda.Stream, a raw hipStream_t, or None for torch's
-    current stream.  Returns HOT_OK, or HOT_E_NOCONVERGE when an implicit
-    step stopped at max_iter (see hot_implicit_stats); raises otherwise."""
+    current stream.  Returns HOT_OK, HOT_E_NOCONVERGE when an implicit
+    step stopped at max_iter (see hot_implicit_stats), or HOT_E_NONFINITE
+    when a plan with check_finite found a NaN or infinity; raises otherwise."""
     stream = _stream(stream)
     n = len(ins)
     pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
     pout = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
     rc = _lib().hot_run(plan, pin, pout, _ptr(workspace), int(nsteps), stream)
-    if rc not in (HOT_OK, HOT_E_NOCONVERGE):
+    if rc not in (HOT_OK, HOT_E_NOCONVERGE, HOT_E_NONFINITE):
         raise HotError(rc, "hot_run", _lib().hot_last_hip_error(plan))
     return rc
 

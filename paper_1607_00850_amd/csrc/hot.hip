@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/hot.h"
+#include "checks.hpp"
 #include "impl.hpp"
 #include "mlp_launch.hpp"
 
@@ -122,6 +123,7 @@ struct hot_plan_s {
   int max_iter;  // implicit step: sweeps per step at most
   std::vector<int> imp_sweeps, imp_nonconv;  // implicit step: last call, per instance
   int flags = 0;
+  size_t o_finite = 0;              // HOT_FLAG_CHECK_FINITE: byte offset of the flag in the workspace
   const void* surrogate = nullptr;  // packed MLP for the implicit warm start
   void* hist_ws = nullptr;          // workspace holding the kept history
   size_t elem;  // bytes per complex element
@@ -158,6 +160,7 @@ const char* hot_error_string(int code) {
     case HOT_E_WORKSPACE: return "workspace missing or misaligned";
     case HOT_E_HIP: return "HIP error";
     case HOT_E_NOCONVERGE: return "implicit step stopped at max_iter sweeps";
+    case HOT_E_NONFINITE: return "result holds a NaN or an infinity";
     default: return "unknown error";
   }
 }
@@ -171,7 +174,9 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
   if (d->op < HOT_OP_R2C || d->op > HOT_OP_IMPLICIT) return HOT_E_INVALID;
   if (d->dealias != HOT_DEALIAS_TWO_THIRDS && d->dealias != HOT_DEALIAS_NONE) return HOT_E_INVALID;
   if (d->reserved != 0) return HOT_E_INVALID;
-  if (d->flags != 0 && !(d->op == HOT_OP_IMPLICIT && d->flags == HOT_FLAG_KEEP_HISTORY)) return HOT_E_INVALID;
+  if (d->flags & ~(HOT_FLAG_KEEP_HISTORY | HOT_FLAG_CHECK_FINITE)) return HOT_E_INVALID;
+  if ((d->flags & HOT_FLAG_KEEP_HISTORY) && d->op != HOT_OP_IMPLICIT) return HOT_E_INVALID;
+  if ((d->flags & HOT_FLAG_CHECK_FINITE) && (d->op == HOT_OP_R2C || d->op == HOT_OP_C2R)) return HOT_E_INVALID;
   if (!(d->nu >= 0.0)) return HOT_E_INVALID;  // also rejects NaN
   if ((d->op == HOT_OP_RK4 || d->op == HOT_OP_IMPLICIT) && !(d->dt > 0.0)) return HOT_E_INVALID;
   if (d->op == HOT_OP_IMPLICIT && (!(d->tol > 0.0) || d->max_iter < 1)) return HOT_E_INVALID;
@@ -257,6 +262,10 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
     off += G.bytes;
   }
   if (!plain) p->ws_bytes = off;
+  if (p->flags & HOT_FLAG_CHECK_FINITE) {
+    p->o_finite = p->ws_bytes;
+    p->ws_bytes += kAlign;
+  }
   *out = p;
   *workspace_bytes = p->ws_bytes;
   return HOT_OK;
@@ -706,14 +715,49 @@ extern "C" int hot_implicit_stats(hot_plan_t p, int32_t* sweeps, int32_t* noncon
   return HOT_OK;
 }
 
+// HOT_FLAG_CHECK_FINITE: scan every instance's compact result (Acc for a
+// plain right-hand side, U0 otherwise) for NaN and infinity.
+static int check_finite(hot_plan_s* p, void* workspace, hipStream_t s) {
+  int* flag = (int*)((char*)workspace + p->o_finite);
+  hipLaunchKernelGGL(k_set_int<>, dim3(1), dim3(1), 0, s, flag, 0);
+  hipError_t e = hipGetLastError();
+  for (const auto& G : p->groups) {
+    if (e != hipSuccess) break;
+    const GroupPtrs q = group_ptrs(G, workspace);
+    const void* X = p->op == HOT_OP_RHS ? q.Acc : q.U0;
+    const dim3 grid(grid_1d(3 * G.C, 256), (unsigned)G.B());
+    if (p->dtype == HOT_F64)
+      hipLaunchKernelGGL(k_nonfinite<double>, grid, dim3(256), 0, s, (const cx<double>*)X, G.C, 3 * G.C, G.g, flag);
+    else
+      hipLaunchKernelGGL(k_nonfinite<float>, grid, dim3(256), 0, s, (const cx<float>*)X, G.C, 3 * G.C, G.g, flag);
+    e = hipGetLastError();
+  }
+  int h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    p->last_hip = (int)e;
+    return HOT_E_HIP;
+  }
+  return h ? HOT_E_NONFINITE : HOT_OK;
+}
+
 extern "C" int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
                        void* stream) {
   int rc = check_run_args(p, in, out, workspace, nsteps);
   if (rc != HOT_OK) return rc;
-  rc = ensure_tables(p, in, out, workspace, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  rc = ensure_tables(p, in, out, workspace, s);
   if (rc != HOT_OK) return rc;
-  if (p->op == HOT_OP_IMPLICIT) return run_implicit(p, in, out, workspace, nsteps, (hipStream_t)stream);
-  return enqueue(p, in, out, workspace, nsteps, (hipStream_t)stream, true);
+  if (p->op == HOT_OP_IMPLICIT)
+    rc = run_implicit(p, in, out, workspace, nsteps, s);
+  else
+    rc = enqueue(p, in, out, workspace, nsteps, s, true);
+  if ((p->flags & HOT_FLAG_CHECK_FINITE) && (rc == HOT_OK || rc == HOT_E_NOCONVERGE)) {
+    const int fc = check_finite(p, workspace, s);
+    if (fc != HOT_OK) return fc;
+  }
+  return rc;
 }
 
 extern "C" int hot_graph_create(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
@@ -722,7 +766,7 @@ extern "C" int hot_graph_create(hot_plan_t p, void* const* in, void* const* out,
   if (!graph || !stream) return HOT_E_INVALID;  // the legacy default stream cannot be captured
   int rc = check_run_args(p, in, out, workspace, nsteps);
   if (rc != HOT_OK) return rc;
-  if (p->op == HOT_OP_IMPLICIT) return HOT_E_UNSUPPORTED;
+  if (p->op == HOT_OP_IMPLICIT || (p->flags & HOT_FLAG_CHECK_FINITE)) return HOT_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   rc = ensure_tables(p, in, out, workspace, s);
   if (rc != HOT_OK) return rc;

@@ -72,7 +72,7 @@ def test_plan_rejects_bad_descriptor_fields():
     good = dict(abi_version=2, batch=1, n=n, nu=0.0, dt=1e-3, dtype=0, dealias=0, op=3, flags=0, tol=1e-6,
                 max_iter=10, reserved=0)
     for field, bad in [("abi_version", 1), ("batch", 0), ("dtype", 7), ("dealias", 5), ("op", 9), ("flags", 1),
-                       ("reserved", 1)]:
+                       ("flags", 4), ("reserved", 1)]:
         kw = dict(good)
         kw[field] = bad
         d = binding.HotDesc(**kw)
@@ -202,6 +202,31 @@ def test_implicit_stats_and_graph_rules_without_the_gpu():
     finally:
         binding.hot_destroy(h)
     assert lib.hot_error_string(binding.HOT_E_NOCONVERGE) != lib.hot_error_string(-99)
+
+
+def test_check_finite_flag_rules_without_the_gpu():
+    lib = binding.library()
+    # allowed on the three time-stepping/right-hand-side ops; costs one 256-byte slot
+    for op in ("rhs", "rk4", "implicit"):
+        _, w0 = binding.hot_plan([16, 24], op, "f32", nu=0.01, dt=1e-3)
+        h, w1 = binding.hot_plan([16, 24], op, "f32", nu=0.01, dt=1e-3, check_finite=True)
+        binding.hot_destroy(h)
+        assert w1 == w0 + 256
+    h, _ = binding.hot_plan(16, "implicit", "f64", nu=0.01, dt=1e-3, keep_history=True, check_finite=True)
+    binding.hot_destroy(h)
+    _expect(binding.HOT_E_INVALID, op="r2c", check_finite=True)
+    _expect(binding.HOT_E_INVALID, op="c2r", check_finite=True)
+    # the check synchronises on the host: no graph capture
+    h, _ = binding.hot_plan(16, "rk4", "f64", nu=0.01, dt=1e-3, check_finite=True)
+    try:
+        arr = (ctypes.c_void_p * 1)(256 * 1000)
+        g = ctypes.c_void_p()
+        rc = lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, ctypes.c_void_p(256), ctypes.byref(g))
+        assert rc == binding.HOT_E_UNSUPPORTED and not g.value
+    finally:
+        binding.hot_destroy(h)
+    msg = lib.hot_error_string(binding.HOT_E_NONFINITE)
+    assert msg and msg != lib.hot_error_string(-99)
 
 
 def test_mlp_sizes_and_surrogate_rules_without_the_gpu():

@@ -1,0 +1,85 @@
+"""The plan flag that scans results for NaN and infinity, through the C ABI.
+
+* A finite run with the flag returns HOT_OK and the same bits as the plan
+  without it (the scan only reads).
+* A NaN or infinity in a retained input mode spreads through the transforms
+  and is reported as HOT_E_NONFINITE, for every op that takes the flag and
+  for every instance of a batch.
+* A NaN in a mode outside the retained set is never read (the 2/3 rule drops
+  it), so the result stays finite.
+* The implicit step with a NaN input cannot converge; the non-finite report
+  takes precedence over the max_iter stop.
+"""
+import numpy as np
+import pytest
+
+from paper_1607_00850_amd import binding, inputs
+from hotrun import empty_spectral, to_dev, workspace
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(op, arrays, dtype, check, **kw):
+    import torch
+    ns = [a.shape[1] for a in arrays]
+    h, wsb = binding.hot_plan(ns, op, dtype, "two_thirds", 0.01, 1e-3, check_finite=check, **kw)
+    try:
+        ins = [to_dev(a, dtype) for a in arrays]
+        outs = [empty_spectral(N, dtype) for N in ns]
+        ws = workspace(wsb)
+        rc = binding.hot_run(h, ins, outs, ws, 0 if op == "rhs" else 2)
+        torch.cuda.synchronize()
+        return rc, [o.cpu().numpy() for o in outs]
+    finally:
+        binding.hot_destroy(h)
+
+
+def _field(N, seed):
+    return inputs.rough_random(N, seed)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("op", ["rhs", "rk4", "implicit"])
+def test_finite_run_is_ok_and_unchanged(op, dtype):
+    arrays = [_field(16, 1), _field(24, 2)]
+    kw = dict(tol=1e-6, max_iter=30) if op == "implicit" else {}
+    rc0, ref = _run(op, arrays, dtype, False, **kw)
+    rc1, got = _run(op, arrays, dtype, True, **kw)
+    assert rc0 == rc1 == binding.HOT_OK
+    for a, b in zip(got, ref):
+        assert np.isfinite(a).all()
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("op", ["rhs", "rk4"])
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+@pytest.mark.parametrize("which", [0, 1])
+def test_nonfinite_retained_mode_is_reported(op, dtype, bad, which):
+    arrays = [_field(16, 3), _field(24, 4)]
+    arrays[which] = arrays[which].copy()
+    arrays[which][1, 2, 1, 3] = complex(bad, 0.0)   # |k| well inside the 2/3 set
+    rc, _ = _run(op, arrays, dtype, True)
+    assert rc == binding.HOT_E_NONFINITE
+    rc, _ = _run(op, arrays, dtype, False)
+    assert rc == binding.HOT_OK
+
+
+def test_nan_in_a_truncated_mode_is_not_read():
+    N = 24
+    u = _field(N, 5).copy()
+    u[0, N // 2, 0, 0] = complex(np.nan, np.nan)   # kx = -N/2: outside 3|k| < N
+    u[2, 0, 0, N // 2] = complex(np.inf, 0.0)      # kz = N/2
+    for op in ("rhs", "rk4"):
+        rc, out = _run(op, [u], "f64", True)
+        assert rc == binding.HOT_OK
+        assert np.isfinite(out[0]).all()
+
+
+def test_implicit_nan_reports_nonfinite_before_noconverge():
+    u = _field(16, 6).copy()
+    u[0, 1, 1, 1] = complex(np.nan, 0.0)
+    rc, _ = _run("implicit", [u], "f64", False, tol=1e-8, max_iter=3)
+    assert rc == binding.HOT_E_NOCONVERGE
+    rc, _ = _run("implicit", [u], "f64", True, tol=1e-8, max_iter=3)
+    assert rc == binding.HOT_E_NONFINITE
