@@ -14,7 +14,8 @@ Extra fields:
                 traffic from the committed rocprofv3 counter summary when its
                 source hash matches the kernels built now, else null.
   cpu_baseline  the CPU oracle timed on a bounded sample (RK4 steps at a
-                smaller N on one core), scaled to this workload's unit.
+                smaller N on one core, then on every allowed core at once,
+                up to 16), scaled to this workload's unit.
 """
 import argparse
 import glob
@@ -557,19 +558,17 @@ def bench_tg(a):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(N_work, seconds=12.0):
-    """Time the CPU oracle (one core) on RK4 steps at N = 128 and scale to
-    instances/s of an N_work^3 step by the FFT cost N^3 log2 N."""
-    import numpy as np
-
+def _oracle_rk4_rate(seconds, core=None, n=128):
+    """RK4 steps of the FP64 oracle at N = n on one core for about `seconds`:
+    (steps, elapsed s).  Pins the calling process to `core` (default: its
+    lowest allowed core)."""
     import oracle
     from paper_1607_00850_amd import inputs
 
     try:
-        os.sched_setaffinity(0, {min(os.sched_getaffinity(0))})
+        os.sched_setaffinity(0, {min(os.sched_getaffinity(0)) if core is None else core})
     except (AttributeError, OSError):
         pass
-    n = 128
     uh = inputs.smooth_random(n, 0)
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -577,18 +576,48 @@ def cpu_baseline(N_work, seconds=12.0):
         steps += 1
         if time.perf_counter() - t0 > seconds:
             break
-    el = time.perf_counter() - t0
+    return steps, time.perf_counter() - t0
+
+
+def cpu_baseline(N_work, seconds=12.0, max_procs=16):
+    """Time the CPU oracle on RK4 steps at N = 128 and scale to instances/s of
+    an N_work^3 step by the FFT cost N^3 log2 N: once on one pinned core (the
+    reported value), then as one pinned single-threaded process per allowed
+    core (at most max_procs), all at once (all_cores).  Runs before the GPU is
+    touched: the worker processes are forked."""
+    import concurrent.futures
+
+    import numpy as np
+
+    n = 128
+    scale = np.log2(N_work) / np.log2(n)
+    allowed = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    steps, el = _oracle_rk4_rate(seconds, n=n)
+    if allowed:
+        os.sched_setaffinity(0, set(allowed))
     pps = n**3 * steps / el
-    scale = (np.log2(N_work) / np.log2(n))
-    inst = pps / scale / float(N_work) ** 3
-    return {
-        "value": inst,
+    out = {
+        "value": pps / scale / float(N_work) ** 3,
         "unit": "instances/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"{steps} RK4 steps of the FP64 oracle at N={n} (R1 seed 0) in {el:.1f} s on 1 core = "
                   f"{pps:.3g} point-steps/s; scaled to N={N_work} by log2(N) ({scale:.3f}x per point)",
     }
+    cores = allowed[:max_procs]
+    if len(cores) > 1:
+        with concurrent.futures.ProcessPoolExecutor(len(cores)) as ex:
+            runs = list(ex.map(_oracle_rk4_rate, [seconds] * len(cores), cores))
+        agg = sum(n**3 * st / t for st, t in runs)
+        out["all_cores"] = {
+            "value": agg / scale / float(N_work) ** 3,
+            "unit": "instances/s",
+            "cores": len(cores),
+            "sample": f"{len(cores)} pinned single-threaded oracle processes at once, each RK4 steps at N={n} for "
+                      f"about {seconds:.0f} s ({sum(st for st, _ in runs)} steps in all) = {agg:.3g} point-steps/s; "
+                      f"scaled as above",
+        }
+    return out
 
 
 def main():
@@ -634,6 +663,11 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}, WORLD_SIZE {world}); "
               "the multi-GPU slab decomposition is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
+
+    # the CPU oracle first: its worker processes are forked before the GPU is touched
+    cpu = None
+    if a.workload == "single" and not a.no_cpu_baseline:
+        cpu = cpu_baseline(a.n, a.cpu_seconds)
 
     import torch
 
@@ -720,8 +754,8 @@ def main():
         "passes": passes,
         "tuned_columns": widths,
     }
-    if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(N, a.cpu_seconds)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
