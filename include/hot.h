@@ -260,6 +260,71 @@ int hot_set_surrogate(hot_plan_t p, const void* packed);
  * Errors: HOT_E_INVALID, HOT_E_WORKSPACE, HOT_E_HIP. */
 int hot_diagnostics(hot_plan_t p, void* const* in, void* workspace, double* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * One share of a slab-decomposed field (Sec. 3, "Mesh decomposition" and
+ * "Three dimensional Fourier transforms with MPI").  nranks shares split one
+ * N^3 field: in physical space share r holds the x planes
+ * [r*nx, (r+1)*nx), nx = N/nranks; in wavenumber space it holds a slab of
+ * kz, the second of the two alignments the paper names for the last
+ * transform (the paper's own code distributes ky).  So the x and y transforms
+ * are local and one all-to-all per direction sits next to the z transform:
+ * six components go from the wavenumber slabs to the physical slabs after
+ * the inverse y pass, three come back after the forward z pass.  The library
+ * runs the local passes; the caller moves the blocks between the shares
+ * (RCCL all-to-all, one per component; or device copies when the shares
+ * share a device).  The retained kz [0, Mz) are split in chunks of
+ * ceil(Mz/nranks); share r holds kz0 = r*chunk onwards.
+ * ------------------------------------------------------------------------ */
+
+/* Where the exchanged blocks sit (byte offsets into the share's workspace).
+ * Both buffers are [6 components][nranks blocks][nx][N][pitch] elements;
+ * block q of a component is block_bytes long, components are comp_bytes
+ * apart.  Forward exchange (after HOT_SLAB_INVERSE), for c = 0..5: send
+ * block q of component c of the send buffer to share q, into block `rank` of
+ * component c of its receive buffer.  Backward exchange (after
+ * HOT_SLAB_CROSS), for c = 0..2: send block q of component c of the receive
+ * buffer to share q, into block `rank` of component c of its send buffer. */
+typedef struct hot_slab_layout {
+  int32_t nranks, rank;
+  int32_t nx;     /* x planes of each physical slab: N / nranks */
+  int32_t kz0;    /* first kz of this share */
+  int32_t nkz;    /* kz extent of the share's canonical in/out arrays: chunk,
+                     or for the last share N/2+1 - kz0 (the truncated kz too) */
+  int32_t mz;     /* retained kz of this share: kz0 .. kz0 + mz - 1 */
+  int32_t chunk;  /* retained kz per share (the last share may hold fewer) */
+  int32_t pitch;  /* z pitch of the exchanged blocks (>= chunk) */
+  size_t send_offset, recv_offset, comp_bytes, block_bytes;
+} hot_slab_layout;
+
+/* Plan share `rank` of `nranks` of one field.  d as for hot_plan with
+ * batch = 1, op HOT_OP_RHS or HOT_OP_RK4, flags = 0.  N must be a multiple
+ * of nranks and every share must hold at least one retained kz
+ * ((nranks - 1) * chunk < Mz), else HOT_E_UNSUPPORTED.  The workspace holds
+ * the share's compact state and both exchange buffers.  hot_run, hot_tune,
+ * hot_graph_create and hot_diagnostics return HOT_E_UNSUPPORTED on a plan
+ * with nranks > 1; hot_set_variant, profiling and hot_pass_bytes work.
+ * Host only. */
+int hot_plan_slab(const hot_desc* d, int32_t nranks, int32_t rank, hot_plan_t* out, size_t* workspace_bytes);
+int hot_slab_layout_of(hot_plan_t p, hot_slab_layout* out);
+
+#define HOT_SLAB_GATHER 0  /* in (canonical share [3][N][N][nkz]) -> state   */
+#define HOT_SLAB_INVERSE 1 /* x and y inverse passes -> send buffer           */
+#define HOT_SLAB_CROSS 2   /* z passes and u x omega, in the receive buffer   */
+#define HOT_SLAB_FORWARD 3 /* y and x forward passes, the stage update        */
+#define HOT_SLAB_SCATTER 4 /* state (RK4) or right-hand side (RHS) -> out     */
+
+/* Enqueue one phase of the share on the stream.  One RK4 step is, for
+ * stage = 0..3: INVERSE, forward exchange, CROSS, backward exchange,
+ * FORWARD; a right-hand side is the same with stage = 4.  GATHER before the
+ * first step, SCATTER after the last (in and out are used by these two only;
+ * out = canonical share [3][N][N][nkz], every element written, zero outside
+ * the retained set).  The exchanges are the caller's; every share must have
+ * finished a phase before any share's exchange reads its buffer.
+ * Errors: HOT_E_INVALID (phase, stage or pointers; an RK4 plan takes stages
+ * 0..3, an RHS plan stage 4), HOT_E_WORKSPACE, HOT_E_HIP. */
+int hot_slab_run(hot_plan_t p, int32_t phase, int32_t stage, const void* in, void* out, void* workspace,
+                 void* stream);
+
 /* Release the plan's host state (waits for its pending profiling events).
  * NULL is accepted and ignored. */
 int hot_destroy(hot_plan_t p);

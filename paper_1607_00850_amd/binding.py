@@ -27,6 +27,7 @@ HOT_OP_R2C, HOT_OP_C2R, HOT_OP_RHS, HOT_OP_RK4, HOT_OP_IMPLICIT = 0, 1, 2, 3, 4
 
 HOT_FLAG_KEEP_HISTORY = 1
 HOT_FLAG_CHECK_FINITE = 2
+HOT_SLAB_GATHER, HOT_SLAB_INVERSE, HOT_SLAB_CROSS, HOT_SLAB_FORWARD, HOT_SLAB_SCATTER = 0, 1, 2, 3, 4
 
 DTYPES = {"f64": HOT_F64, "f32": HOT_F32}
 DEALIAS = {"two_thirds": HOT_DEALIAS_TWO_THIRDS, "none": HOT_DEALIAS_NONE}
@@ -47,6 +48,23 @@ class HotDesc(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("max_iter", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+    ]
+
+
+class HotSlabLayout(ctypes.Structure):
+    _fields_ = [
+        ("nranks", ctypes.c_int32),
+        ("rank", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("kz0", ctypes.c_int32),
+        ("nkz", ctypes.c_int32),
+        ("mz", ctypes.c_int32),
+        ("chunk", ctypes.c_int32),
+        ("pitch", ctypes.c_int32),
+        ("send_offset", ctypes.c_size_t),
+        ("recv_offset", ctypes.c_size_t),
+        ("comp_bytes", ctypes.c_size_t),
+        ("block_bytes", ctypes.c_size_t),
     ]
 
 
@@ -126,6 +144,12 @@ def _lib():
         lib.hot_mlp_dataset_rows.restype = ctypes.c_int64
         lib.hot_mlp_dataset.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]
         lib.hot_mlp_dataset.restype = ctypes.c_int
+        lib.hot_plan_slab.argtypes = [ctypes.POINTER(HotDesc), i32, i32, ctypes.POINTER(vp), ctypes.POINTER(sz)]
+        lib.hot_plan_slab.restype = ctypes.c_int
+        lib.hot_slab_layout_of.argtypes = [vp, ctypes.POINTER(HotSlabLayout)]
+        lib.hot_slab_layout_of.restype = ctypes.c_int
+        lib.hot_slab_run.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+        lib.hot_slab_run.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -365,3 +389,31 @@ def hot_diagnostics(plan, ins, workspace, out, stream=None):
     rc = _lib().hot_diagnostics(plan, pin, _ptr(workspace), _ptr(out), _stream(stream))
     if rc != HOT_OK:
         raise HotError(rc, "hot_diagnostics", _lib().hot_last_hip_error(plan))
+
+
+def hot_plan_slab(n, op, nranks, rank, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0):
+    """Plan share `rank` of `nranks` of one N^3 field (op "rhs" or "rk4");
+    returns (handle, workspace_bytes)."""
+    arr = (ctypes.c_int32 * 1)(int(n))
+    d = HotDesc(HOT_ABI_VERSION, 1, arr, float(nu), float(dt), DTYPES[dtype], DEALIAS[dealias], OPS[op], 0, 1e-10, 50,
+                0)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    rc = _lib().hot_plan_slab(ctypes.byref(d), int(nranks), int(rank), ctypes.byref(h), ctypes.byref(ws))
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_plan_slab")
+    return h, ws.value
+
+
+def hot_slab_layout_of(plan):
+    """The share's HotSlabLayout (geometry and exchange buffer offsets)."""
+    lay = HotSlabLayout()
+    _check(_lib().hot_slab_layout_of(plan, ctypes.byref(lay)), "hot_slab_layout_of")
+    return lay
+
+
+def hot_slab_run(plan, phase, workspace, stage=0, inp=None, out=None, stream=None):
+    """Enqueue one phase (HOT_SLAB_*) of a share; see include/hot.h."""
+    rc = _lib().hot_slab_run(plan, int(phase), int(stage), _ptr(inp), _ptr(out), _ptr(workspace), _stream(stream))
+    if rc != HOT_OK:
+        raise HotError(rc, "hot_slab_run", _lib().hot_last_hip_error(plan))

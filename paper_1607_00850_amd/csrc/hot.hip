@@ -81,6 +81,8 @@ static Geo make_geo(int N, int mode, int elem) {
   g.M = g.lo + g.hi;
   const int seg = 128 / elem;
   g.Mzp = (mode != 2 && g.Mz >= 4 * seg) ? (g.Mz + seg - 1) / seg * seg : g.Mz;
+  g.kz0 = 0;
+  g.czp = N / 2 + 1;
   return g;
 }
 
@@ -104,6 +106,7 @@ struct Group {
   size_t off = 0;                   // byte offset of the group's region
   size_t oU0 = 0, oU1 = 0, oAcc = 0, oNh = 0, oA1 = 0, oA2 = 0, oTab = 0;
   size_t oH[2] = {0, 0}, oAct = 0, oPart = 0;  // implicit step only
+  size_t oZ = 0;                              // z-slab share: receive buffer of the all-to-all
   int nparts = 0;                             // blocks of the implicit update
   int rot = 0, hist = 0;                      // implicit step: buffer rotation, history depth
   int fused = -1;  // RK4/RHS: x_fwd_rk variant fusing the x pass with the stage update, -1 = separate passes
@@ -123,6 +126,11 @@ struct hot_plan_s {
   int max_iter;  // implicit step: sweeps per step at most
   std::vector<int> imp_sweeps, imp_nonconv;  // implicit step: last call, per instance
   int flags = 0;
+  // z-slab share (hot_plan_slab): nranks > 1 splits kz over the shares in
+  // chunks of `chunk` retained values and x over them in nx planes each
+  bool slab = false;
+  int nranks = 1, rank = 0, chunk = 0, nx = 0;
+  Geo gz{};  // geometry of the exchanged z lines (all retained kz, pitch of the blocks)
   size_t o_finite = 0;              // HOT_FLAG_CHECK_FINITE: byte offset of the flag in the workspace
   const void* surrogate = nullptr;  // packed MLP for the implicit warm start
   void* hist_ws = nullptr;          // workspace holding the kept history
@@ -163,6 +171,59 @@ const char* hot_error_string(int code) {
     case HOT_E_NONFINITE: return "result holds a NaN or an infinity";
     default: return "unknown error";
   }
+}
+
+// Workspace layout of every group (offsets and sizes from the groups'
+// geometry); sets p->ws_bytes.
+static int layout_groups(hot_plan_s* p, int op) {
+  const bool plain = op == HOT_OP_R2C || op == HOT_OP_C2R;
+  p->ws_bytes = 0;
+  size_t off = 0;
+  for (auto& G : p->groups) {
+    if (G.B() > 65535) return HOT_E_UNSUPPORTED;  // one grid dimension per batch
+    const long N = G.N;
+    G.C = (long)G.g.M * G.g.M * G.g.Mzp;
+    G.D1 = N * G.g.M * G.g.Mzp;
+    G.D2 = N * N * G.g.Mzp;
+    G.lC = (double)G.g.M * G.g.M * G.g.Mz;
+    G.lD1 = (double)N * G.g.M * G.g.Mz;
+    G.lD2 = (double)N * N * G.g.Mz;
+    const size_t e = p->elem, B = (size_t)G.B();
+    if (plain) {
+      G.bytes = 2 * align_up(3 * (size_t)G.D2 * e);  // shared by all instances, one at a time
+      if (G.bytes > p->ws_bytes) p->ws_bytes = G.bytes;
+      continue;
+    }
+    const size_t sC = align_up(B * 3 * (size_t)G.C * e);
+    G.off = off;
+    G.oU0 = 0;
+    G.oU1 = sC;
+    G.oAcc = 2 * sC;
+    G.oNh = 3 * sC;
+    G.oA1 = 4 * sC;
+    G.oA2 = G.oA1 + align_up(B * 6 * (size_t)G.D1 * e);
+    G.oTab = G.oA2 + align_up(B * 6 * (size_t)G.D2 * e);
+    G.bytes = G.oTab + (B > 1 ? align_up(2 * B * sizeof(void*)) : 0);
+    if (p->slab) {
+      G.oZ = G.bytes;
+      G.bytes += align_up(B * 6 * (size_t)G.D2 * e);
+    }
+    if (op == HOT_OP_IMPLICIT) {
+      G.nparts = (int)grid_1d(G.C, 256);
+      G.oH[0] = G.bytes;
+      G.oH[1] = G.oH[0] + sC;
+      G.oAct = G.oH[1] + sC;
+      G.oPart = G.oAct + align_up(B * sizeof(int));
+      G.bytes = G.oPart + align_up(B * (size_t)G.nparts * 2 * sizeof(double));
+    }
+    off += G.bytes;
+  }
+  if (!plain) p->ws_bytes = off;
+  if (p->flags & HOT_FLAG_CHECK_FINITE) {
+    p->o_finite = p->ws_bytes;
+    p->ws_bytes += kAlign;
+  }
+  return HOT_OK;
 }
 
 int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
@@ -222,49 +283,9 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
     }
     gp->members.push_back(i);
   }
-  size_t off = 0;
-  for (auto& G : p->groups) {
-    if (G.B() > 65535) {  // one grid dimension per batch
-      delete p;
-      return HOT_E_UNSUPPORTED;
-    }
-    const long N = G.N;
-    G.C = (long)G.g.M * G.g.M * G.g.Mzp;
-    G.D1 = N * G.g.M * G.g.Mzp;
-    G.D2 = N * N * G.g.Mzp;
-    G.lC = (double)G.g.M * G.g.M * G.g.Mz;
-    G.lD1 = (double)N * G.g.M * G.g.Mz;
-    G.lD2 = (double)N * N * G.g.Mz;
-    const size_t e = p->elem, B = (size_t)G.B();
-    if (plain) {
-      G.bytes = 2 * align_up(3 * (size_t)G.D2 * e);  // shared by all instances, one at a time
-      if (G.bytes > p->ws_bytes) p->ws_bytes = G.bytes;
-      continue;
-    }
-    const size_t sC = align_up(B * 3 * (size_t)G.C * e);
-    G.off = off;
-    G.oU0 = 0;
-    G.oU1 = sC;
-    G.oAcc = 2 * sC;
-    G.oNh = 3 * sC;
-    G.oA1 = 4 * sC;
-    G.oA2 = G.oA1 + align_up(B * 6 * (size_t)G.D1 * e);
-    G.oTab = G.oA2 + align_up(B * 6 * (size_t)G.D2 * e);
-    G.bytes = G.oTab + (B > 1 ? align_up(2 * B * sizeof(void*)) : 0);
-    if (d->op == HOT_OP_IMPLICIT) {
-      G.nparts = (int)grid_1d(G.C, 256);
-      G.oH[0] = G.bytes;
-      G.oH[1] = G.oH[0] + sC;
-      G.oAct = G.oH[1] + sC;
-      G.oPart = G.oAct + align_up(B * sizeof(int));
-      G.bytes = G.oPart + align_up(B * (size_t)G.nparts * 2 * sizeof(double));
-    }
-    off += G.bytes;
-  }
-  if (!plain) p->ws_bytes = off;
-  if (p->flags & HOT_FLAG_CHECK_FINITE) {
-    p->o_finite = p->ws_bytes;
-    p->ws_bytes += kAlign;
+  if (layout_groups(p, d->op) != HOT_OK) {
+    delete p;
+    return HOT_E_UNSUPPORTED;
   }
   *out = p;
   *workspace_bytes = p->ws_bytes;
@@ -327,14 +348,15 @@ int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) 
     if (G.N == p->n[instance]) Gp = &G;
   const Group& I = *Gp;
   const double e = (double)p->elem, C = I.lC, D1 = I.lD1, D2 = I.lD2;
-  const double N = I.g.N, canon = 3.0 * N * N * (N / 2 + 1);
+  const double N = I.g.N, canon = 3.0 * N * N * I.g.czp;
   double b = 0;
   const bool plain = p->op == HOT_OP_R2C || p->op == HOT_OP_C2R;
   switch (pass) {
     case PASS_GATHER: b = plain ? 0 : 6 * C; break;  // read the 3C retained values, write 3C
     case PASS_X_INV_CURL: b = plain ? 0 : 3 * C + 6 * D1; break;
     case PASS_Y_INV: b = plain ? (p->op == HOT_OP_C2R ? 6 * D2 : 0) : 6 * D1 + 6 * D2; break;
-    case PASS_Z_CROSS: b = plain ? 0 : 6 * D2 + 3 * D2; break;
+    // a slab share transforms nx x-planes of lines with every retained kz
+    case PASS_Z_CROSS: b = plain ? 0 : (p->slab ? 9.0 * p->nx * N * p->gz.Mz : 6 * D2 + 3 * D2); break;
     case PASS_Y_FWD: b = plain ? (p->op == HOT_OP_R2C ? 6 * D2 : 0) : 3 * D2 + 3 * D1; break;
     case PASS_X_FWD: b = plain ? (p->op == HOT_OP_R2C ? 6 * D2 : 0) : 3 * D1 + 3 * C; break;
     // RK4 stages move 12C, 18C, 18C, 12C (mean 15C); the plain RHS 9C
@@ -402,7 +424,7 @@ struct Runner {
 };
 
 struct GroupPtrs {
-  char *U0, *U1, *Acc, *Nh, *A1, *A2;
+  char *U0, *U1, *Acc, *Nh, *A1, *A2, *Z;
   char* H[2];  // implicit step: increment histories
   int* act;
   double* part;
@@ -419,6 +441,7 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
   q.Nh = base + G.oNh;
   q.A1 = base + G.oA1;
   q.A2 = base + G.oA2;
+  q.Z = base + G.oZ;
   q.H[0] = base + G.oH[0];
   q.H[1] = base + G.oH[1];
   q.act = (int*)(base + G.oAct);
@@ -428,10 +451,9 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
   return q;
 }
 
-// One evaluation of the right-hand side for every instance of a group, from
-// compact state `src` into Nh.
-void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, const int* act = nullptr,
-                bool x_fwd = true) {
+// The inverse half of a right-hand side for every instance of a group: the x
+// pass (curl fused) from compact state `src`, then the y pass, into A2.
+void inverse_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, const int* act) {
   const Geo& g = G.g;
   const long N = g.N, M = g.M, P = g.Mzp;
   const Ops& o = G.ops;
@@ -445,7 +467,16 @@ void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, 
     return o.strided(r.s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1,
                      G.D2, 6, isA1, isA2, nb, g, act);
   });
-  r.pass(PASS_Z_CROSS, [&] { return o.z_cross(r.s, q.A2, G.D2, isA2, N * N, nb, g, act); });
+}
+
+// The forward half after the z pass: the y pass from A2, then (x_fwd) the x
+// pass into Nh.
+void forward_passes(Runner& r, const Group& G, const GroupPtrs& q, const int* act, bool x_fwd) {
+  const Geo& g = G.g;
+  const long N = g.N, M = g.M, P = g.Mzp;
+  const Ops& o = G.ops;
+  const int nb = G.B();
+  const long isU = 3 * G.C, isA1 = 6 * G.D1, isA2 = 6 * G.D2;
   // y forward: 3 components, y (all N) -> ky (compact)
   r.pass(PASS_Y_FWD, [&] {
     return o.strided(r.s, G.variant[PASS_Y_FWD], -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2,
@@ -460,19 +491,33 @@ void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, 
   });
 }
 
-// One right-hand side plus stage update (mode 0..3 RK4 stage, 4 plain
+// One evaluation of the right-hand side for every instance of a group, from
+// compact state `src` into Nh.
+void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, const int* act = nullptr,
+                bool x_fwd = true) {
+  inverse_passes(r, G, q, src, act);
+  r.pass(PASS_Z_CROSS, [&] { return G.ops.z_cross(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act); });
+  forward_passes(r, G, q, act, x_fwd);
+}
+
+// The stage update after the forward y pass (mode 0..3 RK4 stage, 4 plain
 // right-hand side into Acc): the x pass and the update fused or separate.
-void stage_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, int mode, double nu, double dt) {
+void stage_update(Runner& r, const Group& G, const GroupPtrs& q, int mode, double nu, double dt) {
   const Ops& o = G.ops;
   const long isU = 3 * G.C;
   const int nb = G.B();
-  rhs_passes(r, G, q, src, nullptr, G.fused < 0);
   if (G.fused < 0)
     r.pass(PASS_RK_STAGE, [&] { return o.rk_stage(r.s, q.Nh, q.U0, q.U1, q.Acc, G.C, isU, nb, G.g, mode, nu, dt); });
   else
     r.pass(PASS_X_FWD_RK, [&] {
       return o.x_fwd_rk(r.s, G.fused, q.A1, G.D1, 6 * G.D1, q.U0, q.U1, q.Acc, G.C, isU, nb, G.g, mode, nu, dt);
     });
+}
+
+// One right-hand side plus stage update.
+void stage_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, int mode, double nu, double dt) {
+  rhs_passes(r, G, q, src, nullptr, G.fused < 0);
+  stage_update(r, G, q, mode, nu, dt);
 }
 
 // Upload the members' input/output pointer tables of every batched group
@@ -672,6 +717,7 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
 
 extern "C" int hot_diagnostics(hot_plan_t p, void* const* in, void* workspace, double* out, void* stream) {
   if (!p || !in || !out || ((uintptr_t)out & 7) != 0) return HOT_E_INVALID;
+  if (p->nranks > 1) return HOT_E_UNSUPPORTED;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
   constexpr int kParts = 128;  // partial sums of one instance: 2 KiB of scratch
   if ((size_t)kParts * 2 * sizeof(double) > p->ws_bytes) return HOT_E_WORKSPACE;
@@ -746,6 +792,7 @@ extern "C" int hot_run(hot_plan_t p, void* const* in, void* const* out, void* wo
                        void* stream) {
   int rc = check_run_args(p, in, out, workspace, nsteps);
   if (rc != HOT_OK) return rc;
+  if (p->nranks > 1) return HOT_E_UNSUPPORTED;  // a share runs by phases (hot_slab_run)
   hipStream_t s = (hipStream_t)stream;
   rc = ensure_tables(p, in, out, workspace, s);
   if (rc != HOT_OK) return rc;
@@ -766,7 +813,7 @@ extern "C" int hot_graph_create(hot_plan_t p, void* const* in, void* const* out,
   if (!graph || !stream) return HOT_E_INVALID;  // the legacy default stream cannot be captured
   int rc = check_run_args(p, in, out, workspace, nsteps);
   if (rc != HOT_OK) return rc;
-  if (p->op == HOT_OP_IMPLICIT || (p->flags & HOT_FLAG_CHECK_FINITE)) return HOT_E_UNSUPPORTED;
+  if (p->op == HOT_OP_IMPLICIT || (p->flags & HOT_FLAG_CHECK_FINITE) || p->nranks > 1) return HOT_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   rc = ensure_tables(p, in, out, workspace, s);
   if (rc != HOT_OK) return rc;
@@ -814,6 +861,7 @@ extern "C" int hot_graph_destroy(hot_graph_t graph) {
 extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t reps) {
   if (!p || reps < 1) return HOT_E_INVALID;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
+  if (p->nranks > 1) return HOT_E_UNSUPPORTED;
   if (p->op != HOT_OP_RHS && p->op != HOT_OP_RK4 && p->op != HOT_OP_IMPLICIT) return HOT_OK;  // nothing to tune
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t a = nullptr, b = nullptr;
@@ -942,4 +990,107 @@ extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
       return G.ops.strided_width[G.variant[pass]];
     }
   return HOT_E_INVALID;
+}
+
+// ---------------------------------------------------------------------------
+// z-slab shares
+// ---------------------------------------------------------------------------
+extern "C" int hot_plan_slab(const hot_desc* d, int32_t nranks, int32_t rank, hot_plan_t* out,
+                             size_t* workspace_bytes) {
+  if (out) *out = nullptr;
+  if (!d || !out || !workspace_bytes) return HOT_E_INVALID;
+  if (nranks < 1 || rank < 0 || rank >= nranks) return HOT_E_INVALID;
+  if (d->batch != 1 || !d->n || (d->op != HOT_OP_RHS && d->op != HOT_OP_RK4) || d->flags != 0)
+    return HOT_E_INVALID;
+  hot_plan_t p = nullptr;
+  size_t wsb = 0;
+  int rc = hot_plan(d, &p, &wsb);
+  if (rc != HOT_OK) return rc;
+  const int N = d->n[0];
+  Group& G = p->groups[0];
+  const Geo full = G.g;
+  const int chunk = (full.Mz + nranks - 1) / nranks;
+  if (N % nranks != 0 || (long)(nranks - 1) * chunk >= full.Mz) {
+    hot_destroy(p);
+    return HOT_E_UNSUPPORTED;
+  }
+  // blocks keep 128-byte rows once they are long enough for it to be cheap
+  const int seg = 128 / (int)p->elem;
+  const int pitch = chunk >= 4 * seg ? (chunk + seg - 1) / seg * seg : chunk;
+  const int kz0 = rank * chunk;
+  G.g.kz0 = kz0;
+  G.g.Mz = full.Mz - kz0 < chunk ? full.Mz - kz0 : chunk;
+  G.g.Mzp = pitch;
+  G.g.czp = rank == nranks - 1 ? N / 2 + 1 - kz0 : chunk;
+  p->slab = true;
+  p->nranks = nranks;
+  p->rank = rank;
+  p->chunk = chunk;
+  p->nx = N / nranks;
+  p->gz = full;  // z lines: every retained kz, at the pitch of the blocks
+  p->gz.Mzp = pitch;
+  rc = layout_groups(p, p->op);
+  if (rc != HOT_OK) {
+    hot_destroy(p);
+    return rc;
+  }
+  *out = p;
+  *workspace_bytes = p->ws_bytes;
+  return HOT_OK;
+}
+
+extern "C" int hot_slab_layout_of(hot_plan_t p, hot_slab_layout* out) {
+  if (!p || !out || !p->slab) return HOT_E_INVALID;
+  const Group& G = p->groups[0];
+  out->nranks = p->nranks;
+  out->rank = p->rank;
+  out->nx = p->nx;
+  out->kz0 = G.g.kz0;
+  out->nkz = G.g.czp;
+  out->mz = G.g.Mz;
+  out->chunk = p->chunk;
+  out->pitch = G.g.Mzp;
+  out->send_offset = G.off + G.oA2;
+  out->recv_offset = G.off + G.oZ;
+  out->comp_bytes = (size_t)G.D2 * p->elem;
+  out->block_bytes = (size_t)p->nx * G.N * G.g.Mzp * p->elem;
+  return HOT_OK;
+}
+
+extern "C" int hot_slab_run(hot_plan_t p, int32_t phase, int32_t stage, const void* in, void* out, void* workspace,
+                            void* stream) {
+  if (!p || !p->slab) return HOT_E_INVALID;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
+  const bool staged = phase == HOT_SLAB_INVERSE || phase == HOT_SLAB_FORWARD;
+  if (phase < HOT_SLAB_GATHER || phase > HOT_SLAB_SCATTER) return HOT_E_INVALID;
+  if (staged && (p->op == HOT_OP_RK4 ? (stage < 0 || stage > 3) : stage != 4)) return HOT_E_INVALID;
+  if (phase == HOT_SLAB_GATHER && (!in || ((uintptr_t)in % kAlign) != 0)) return HOT_E_INVALID;
+  if (phase == HOT_SLAB_SCATTER && (!out || ((uintptr_t)out % kAlign) != 0)) return HOT_E_INVALID;
+  Runner r{p, (hipStream_t)stream, true};
+  const Group& G = p->groups[0];
+  const GroupPtrs q = group_ptrs(G, workspace);
+  const Ops& o = G.ops;
+  const long isU = 3 * G.C;
+  switch (phase) {
+    case HOT_SLAB_GATHER:
+      r.pass(PASS_GATHER, [&] { return o.gather(r.s, in, nullptr, q.U0, G.C, isU, 1, G.g); });
+      break;
+    case HOT_SLAB_INVERSE:
+      inverse_passes(r, G, q, (stage == 0 || stage == 4) ? q.U0 : q.U1, nullptr);
+      break;
+    case HOT_SLAB_CROSS: {
+      const long lines = (long)p->nx * G.N, blk = lines * G.g.Mzp;
+      r.pass(PASS_Z_CROSS, [&] { return o.z_cross_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk); });
+      break;
+    }
+    case HOT_SLAB_FORWARD:
+      forward_passes(r, G, q, nullptr, G.fused < 0);
+      stage_update(r, G, q, stage, p->nu, p->dt);
+      break;
+    default:
+      r.pass(PASS_SCATTER, [&] {
+        return o.scatter(r.s, p->op == HOT_OP_RK4 ? q.U0 : q.Acc, out, nullptr, G.C, isU, 1, G.g);
+      });
+  }
+  return r.rc;
 }

@@ -23,6 +23,7 @@ template <> struct LP<128> { using P = LinePlan<128, 16, 16, 8>; };
 template <> struct LP<256> { using P = LinePlan<256, 16, 16, 16>; };
 template <> struct LP<512> { using P = LinePlan<512, 16, 16, 16, 2>; };
 template <> struct LP<1024> { using P = LinePlan<1024, 16, 16, 16, 4>; };
+template <> struct LP<2048> { using P = LinePlan<2048, 16, 16, 16, 8>; };
 // 2^a 3^b lengths of the batched workloads
 template <> struct LP<18> { using P = LinePlan<18, 6, 6, 3>; };
 template <> struct LP<24> { using P = LinePlan<24, 12, 4, 6>; };
@@ -61,6 +62,9 @@ struct Ops {
   hipError_t (*x_inv_curl)(hipStream_t, int variant, const void* U, long csU, long isU, void* A, long csA, long isA,
                            int nb, const Geo&, const int* act);
   hipError_t (*z_cross)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&, const int* act);
+  // z_cross on lines that arrive in chunks of `chunk` coefficients, blocks blk
+  // elements apart (the receive buffer of a z-slab all-to-all)
+  hipError_t (*z_cross_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk);
   hipError_t (*z_c2r)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
   hipError_t (*z_r2c)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
   hipError_t (*rk_stage)(hipStream_t, const void* Nh, void* U0, void* U1, void* Acc, long C, long is, int nb,
@@ -166,8 +170,9 @@ struct Impl {
   }
   using PZ = typename LPz<N>::P;
   static constexpr int lines_per_block() { return ZShape<PZ>::LPB; }
-  static hipError_t z_cross(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
-                            const int* act) {
+  template <class ZA>
+  static hipError_t z_cross_za(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
+                               const int* act, ZA za) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const double n3 = double(N) * N * N;
     const T scale = T(1.0 / (n3 * n3));
@@ -175,14 +180,23 @@ struct Impl {
     // coefficients per lane: the 2/3-rule count, or the all-but-Nyquist one
     constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
     if (g.Mz <= KL23 * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale,
-                         act);
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale,
+                         act, za);
     else if (g.Mz <= KLall * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale,
-                         act);
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g,
+                         scale, act, za);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
+  }
+  static hipError_t z_cross(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
+                            const int* act) {
+    return z_cross_za(s, A, csA, isA, nlines, nb, g, act, ZContig{});
+  }
+  static hipError_t z_cross_blocked(hipStream_t s, void* A, long csA, long nlines, const Geo& g, int chunk,
+                                    long blk) {
+    if (chunk < 1) return hipErrorInvalidValue;
+    return z_cross_za(s, A, csA, 0, nlines, 1, g, nullptr, ZBlocked{chunk, 1.0f / (float)chunk, blk});
   }
   static hipError_t z_c2r(hipStream_t s, const void* in, void* out, long nlines, const Geo& g) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
@@ -227,7 +241,7 @@ struct Impl {
   }
   static hipError_t scatter(hipStream_t s, const void* in, void* out0, void* const* out_tab, long C, long is, int nb,
                             const Geo& g) {
-    const long total = 3L * g.N * g.N * (g.N / 2 + 1);
+    const long total = 3L * g.N * g.N * g.czp;
     hipLaunchKernelGGL((k_scatter<T>), dim3(grid_1d(total, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in,
                        (cx<T>*)out0, (cx<T>* const*)out_tab, C, is, g);
     return hipGetLastError();
@@ -250,12 +264,13 @@ struct Impl {
     return hipGetLastError();
   }
   static Ops ops() {
-    return Ops{&strided,  &x_inv_curl,  &z_cross,    &z_c2r,       &z_r2c, &rk_stage, &x_fwd_rk,
-               &gather,   &scatter,     &imp_predict, &imp_update, &imp_advance, 3,      {WV0, W, WV2}};
+    return Ops{&strided, &x_inv_curl,  &z_cross,    &z_cross_blocked, &z_c2r,       &z_r2c, &rk_stage,
+               &x_fwd_rk, &gather,    &scatter,    &imp_predict,     &imp_update,  &imp_advance, 3,
+               {WV0, W, WV2}};
   }
 };
 
-#define HOT_SIZES(X) X(8) X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(128) X(256) X(512) X(1024)
+#define HOT_SIZES(X) X(8) X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(128) X(256) X(512) X(1024) X(2048)
 
 #define HOT_DECLARE_OPS(n)  \
   Ops make_ops_f32_##n();   \

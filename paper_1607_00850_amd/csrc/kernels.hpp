@@ -28,6 +28,8 @@ struct Geo {
   int lo, hi, M;  // x and y axes
   int Mz;         // retained z (half-axis) modes
   int Mzp;        // z pitch of compact arrays (>= Mz)
+  int kz0;        // kz of local column 0: 0, or the first kz of a z-slab share
+  int czp;        // z extent of the canonical in/out arrays: N/2+1, or a slab share's
 };
 
 __device__ __forceinline__ bool kept(int p, const Geo& g) { return p < g.lo || p >= g.N - g.hi; }
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
   const int kz = (int)(q - (long)iy * g.Mzp);
   const bool valid = q < Q && kz < g.Mz;
   const T ky = T(kwave(cpos(valid ? iy : 0, g), N));
-  const T kzf = T(kz);
+  const T kzf = T(kz + g.kz0);
   const long qq = valid ? q : 0;
   U += blockIdx.y * isU;  // instance of a batch
   A += blockIdx.y * isA;
@@ -346,12 +348,33 @@ __device__ __forceinline__ void read_completed(const L& lds, cx<T>* v, int j, in
   });
 }
 
+// Where coefficient k of a z line sits, relative to the line's first slot.
+// ZContig: the line is one row, k at offset k.  ZBlocked: the line arrives in
+// chunks of `chunk` coefficients, chunk c in the block written by z-slab
+// share c (blocks `blk` elements apart, the line at the same offset in each),
+// as an all-to-all between slab shares delivers it.
+struct ZContig {
+  __device__ __forceinline__ long operator()(int k) const { return k; }
+};
+struct ZBlocked {
+  int chunk;
+  float inv;  // 1 / chunk
+  long blk;
+  __device__ __forceinline__ long operator()(int k) const {
+    // exact: k + 1/2 stays at least 1/(2 chunk) away from every multiple of
+    // chunk, far beyond the float rounding of the product for k < 2^16
+    const int c = (int)((float(k) + 0.5f) * inv);
+    return (long)c * blk + (k - c * chunk);
+  }
+};
+
 // Coalesced load of a compact z line: lane j takes k = j + t*Tl (k < Mz).
-template <typename T, class Plan, int KL>
-__device__ __forceinline__ void load_line(cx<T> (&la)[KL], const cx<T>* __restrict__ a, int j, int Mz, bool valid) {
+template <typename T, class Plan, int KL, class ZA = ZContig>
+__device__ __forceinline__ void load_line(cx<T> (&la)[KL], const cx<T>* __restrict__ a, int j, int Mz, bool valid,
+                                          ZA za = ZA{}) {
   static_for<0, KL>([&](auto t) {
     const int k = j + t * Plan::Tl;
-    la[t] = (valid && k < Mz) ? a[k] : cx<T>{T(0), T(0)};
+    la[t] = (valid && k < Mz) ? a[za(k)] : cx<T>{T(0), T(0)};
   });
 }
 
@@ -361,11 +384,13 @@ __device__ __forceinline__ void load_line(cx<T> (&la)[KL], const cx<T>* __restri
 // Sec. 3.4) scaled by 1/N^6 (the 1/N^3 of Eq. ffteq for each factor), and the
 // forward real transform of c (c0 + i c1 in one FFT, c2 in another).
 // In place: reads components 0..5 of the line, writes 0..2.  The loads of the
-// next component pair are issued before the current pair's FFT.
+// next component pair are issued before the current pair's FFT.  ZA places
+// the coefficients of a line (ZContig: one row; ZBlocked: the chunks of a
+// z-slab all-to-all).
 // ---------------------------------------------------------------------------
-template <typename T, class Plan, int KL>
+template <typename T, class Plan, int KL, class ZA>
 __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA, long isA, long nlines, Geo g,
-                                                 T scale, const int* __restrict__ act) {
+                                                 T scale, const int* __restrict__ act, ZA za) {
   if (act && !act[blockIdx.y]) return;  // instance no longer iterating
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
@@ -386,8 +411,8 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   A += blockIdx.y * isA;  // instance of a batch
 
   cx<T> la[KL], lb[KL];
-  load_line<T, Plan, KL>(la, A + base, j, Mz, valid);
-  load_line<T, Plan, KL>(lb, A + csA + base, j, Mz, valid);
+  load_line<T, Plan, KL>(la, A + base, j, Mz, valid, za);
+  load_line<T, Plan, KL>(lb, A + csA + base, j, Mz, valid, za);
   // twiddles to LDS while the line loads are in flight (an LDS-only barrier
   // leaves them in flight)
   twst.put(tws, threadIdx.x);
@@ -399,8 +424,8 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
     read_completed<T, Plan>(lds, ph[pr], j, Mz);
     lds.sync();
     if constexpr (pr < 2) {
-      load_line<T, Plan, KL>(la, A + (2 * pr + 2) * csA + base, j, Mz, valid);
-      load_line<T, Plan, KL>(lb, A + (2 * pr + 3) * csA + base, j, Mz, valid);
+      load_line<T, Plan, KL>(la, A + (2 * pr + 2) * csA + base, j, Mz, valid, za);
+      load_line<T, Plan, KL>(lb, A + (2 * pr + 3) * csA + base, j, Mz, valid, za);
     }
     Plan::template fft<T, +1>(ph[pr], j, lds, tw);
   });
@@ -427,9 +452,10 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
       if (k < Mz) {
         const cx<T> zk = lds.get(k);
         const cx<T> zm = lds.get((N - k) % N);
-        store_stream(o0 + k, cx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)});
-        store_stream(o1 + k, cx<T>{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)});
-        store_stream(o2 + k, z2[s]);
+        const long ok = za(k);
+        store_stream(o0 + ok, cx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)});
+        store_stream(o1 + ok, cx<T>{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)});
+        store_stream(o2 + ok, z2[s]);
       }
     });
   }
@@ -576,8 +602,8 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
     const int iy = (int)(r / g.Mzp);
     const int kz = (int)(r - (long)iy * g.Mzp);
     if (kz >= g.Mz) continue;  // row padding
-    rk_update(e, Nh[e], Nh[C + e], Nh[2 * C + e], kwave(cpos(ix, g), g.N), kwave(cpos(iy, g), g.N), kz, U0, U1, Acc,
-              C, mode, nu, dt);
+    rk_update(e, Nh[e], Nh[C + e], Nh[2 * C + e], kwave(cpos(ix, g), g.N), kwave(cpos(iy, g), g.N), kz + g.kz0, U0,
+              U1, Acc, C, mode, nu, dt);
   }
 }
 
@@ -630,8 +656,8 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restric
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
     if (kept(p, g))
-      rk_update((long)crow(p, g) * Q + q, v[0][s], v[1][s], v[2][s], kwave(p, N), kyi, kz, U0, U1, Acc, C, mode,
-                nu, dt);
+      rk_update((long)crow(p, g) * Q + q, v[0][s], v[1][s], v[2][s], kwave(p, N), kyi, kz + g.kz0, U0, U1, Acc, C,
+                mode, nu, dt);
   });
 }
 
@@ -661,6 +687,7 @@ __device__ __forceinline__ bool mode_of(long e, const Geo& g, ModeK& m) {
   const int iy = (int)(r / g.Mzp);
   m.kz = (int)(r - (long)iy * g.Mzp);
   if (m.kz >= g.Mz) return false;
+  m.kz += g.kz0;
   m.kx = kwave(cpos(ix, g), g.N);
   m.ky = kwave(cpos(iy, g), g.N);
   return true;
@@ -858,7 +885,7 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in0, c
   const cx<T>* __restrict__ in = in_tab ? in_tab[blockIdx.y] : in0;
   out += blockIdx.y * is;
   const long stride = (long)gridDim.x * blockDim.x;
-  const long Nh = g.N / 2 + 1;
+  const long Nh = g.czp;  // canonical z extent; its kz 0 is local column 0
   const long MMz = (long)g.M * g.Mzp;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < 3 * C; e += stride) {
     const int c = (int)(e / C);
@@ -879,7 +906,7 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, c
   cx<T>* __restrict__ out = out_tab ? out_tab[blockIdx.y] : out0;
   in += blockIdx.y * is;
   const long stride = (long)gridDim.x * blockDim.x;
-  const long Nh = g.N / 2 + 1;
+  const long Nh = g.czp;
   const long plane = (long)g.N * Nh;
   const long total = 3L * g.N * plane;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {

@@ -60,7 +60,7 @@ def test_plan_rejects_bad_arguments():
     _expect(binding.HOT_E_INVALID, nu=float("nan"))
     _expect(binding.HOT_E_INVALID, dt=0.0)
     _expect(binding.HOT_E_INVALID, dt=-1e-3)
-    _expect(binding.HOT_E_UNSUPPORTED, n=2048)   # even, but no kernels for it
+    _expect(binding.HOT_E_UNSUPPORTED, n=4096)   # even, but no kernels for it
     _expect(binding.HOT_E_UNSUPPORTED, n=[64, 100])
 
 
@@ -292,5 +292,93 @@ def test_diagnostics_argument_checks_without_the_gpu():
         assert lib.hot_diagnostics(h, nul, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == binding.HOT_E_INVALID
         assert lib.hot_diagnostics(None, arr, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == \
             binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+
+
+def _slab_expect(code, **kw):
+    args = dict(n=64, op="rk4", nranks=4, rank=0, dtype="f64", nu=0.01, dt=1e-3)
+    args.update(kw)
+    with pytest.raises(binding.HotError) as e:
+        binding.hot_plan_slab(**args)
+    assert e.value.code == code
+
+
+def test_slab_share_geometry_and_workspace():
+    # N = 64, 2/3 rule: Mz = 22 retained kz in chunks of 6 over 4 shares
+    N, R, e = 64, 4, 16
+    lays, wss = [], []
+    for r in range(R):
+        h, ws = binding.hot_plan_slab(N, "rk4", R, r, "f64", nu=0.01, dt=1e-3)
+        lays.append(binding.hot_slab_layout_of(h))
+        wss.append(ws)
+        binding.hot_destroy(h)
+    assert [(l.kz0, l.mz, l.nkz) for l in lays] == [(0, 6, 6), (6, 6, 6), (12, 6, 6), (18, 4, 33 - 18)]
+    for r, l in enumerate(lays):
+        assert (l.nranks, l.rank, l.nx, l.chunk, l.pitch) == (R, r, N // R, 6, 6)
+        assert l.block_bytes == (N // R) * N * 6 * e and l.comp_bytes == R * l.block_bytes
+        assert l.send_offset % 256 == 0 and l.recv_offset % 256 == 0
+        assert l.recv_offset >= l.send_offset + 6 * l.comp_bytes
+    # compact state of a share: M x M x pitch per component
+    K = (N - 1) // 3
+    M, C = 2 * K + 1, (2 * K + 1) ** 2 * 6
+    D1, D2 = N * M * 6, N * N * 6
+    assert wss[0] == 4 * _align(3 * C * e) + _align(6 * D1 * e) + 2 * _align(6 * D2 * e)
+    # 128-byte pitch once chunks are long enough: N = 1024 FP32 over 4 shares
+    h, _ = binding.hot_plan_slab(1024, "rk4", 4, 3, "f32", nu=0.01, dt=1e-3)
+    l = binding.hot_slab_layout_of(h)
+    binding.hot_destroy(h)
+    assert (l.chunk, l.pitch, l.kz0, l.mz, l.nkz) == (86, 96, 258, 342 - 258, 513 - 258)
+
+
+def test_slab_pass_bytes():
+    h, _ = binding.hot_plan_slab(64, "rk4", 4, 1, "f32", nu=0.01, dt=1e-3)
+    try:
+        assert binding.hot_pass_bytes(h, 0, "z_cross") == 9 * 16 * 64 * 22 * 8
+        assert binding.hot_pass_bytes(h, 0, "scatter") == (3 * 43 * 43 * 6 + 3 * 64 * 64 * 6) * 8
+    finally:
+        binding.hot_destroy(h)
+
+
+def test_slab_plan_and_run_rules_without_the_gpu():
+    lib = binding.library()
+    _slab_expect(binding.HOT_E_UNSUPPORTED, nranks=5)     # 64 % 5 != 0
+    _slab_expect(binding.HOT_E_UNSUPPORTED, nranks=32)    # chunk 1: shares beyond kz 21 hold nothing
+    _slab_expect(binding.HOT_E_INVALID, rank=4)
+    _slab_expect(binding.HOT_E_INVALID, rank=-1)
+    _slab_expect(binding.HOT_E_INVALID, nranks=0)
+    _slab_expect(binding.HOT_E_INVALID, op="implicit")
+    _slab_expect(binding.HOT_E_INVALID, op="r2c")
+    h, _ = binding.hot_plan_slab(64, "rk4", 2, 0, "f64", nu=0.01, dt=1e-3)
+    try:
+        arr = (ctypes.c_void_p * 1)(256 * 1000)
+        ws = ctypes.c_void_p(256 * 9)
+        assert lib.hot_run(h, arr, arr, ws, 1, None) == binding.HOT_E_UNSUPPORTED
+        assert lib.hot_tune(h, ws, None, 1) == binding.HOT_E_UNSUPPORTED
+        g = ctypes.c_void_p()
+        assert lib.hot_graph_create(h, arr, arr, ws, 1, ctypes.c_void_p(256), ctypes.byref(g)) == \
+            binding.HOT_E_UNSUPPORTED
+        assert lib.hot_diagnostics(h, arr, ws, ctypes.c_void_p(256), None) == binding.HOT_E_UNSUPPORTED
+        run = lib.hot_slab_run
+        assert run(h, 7, 0, None, None, ws, None) == binding.HOT_E_INVALID
+        assert run(h, binding.HOT_SLAB_INVERSE, 4, None, None, ws, None) == binding.HOT_E_INVALID
+        assert run(h, binding.HOT_SLAB_FORWARD, -1, None, None, ws, None) == binding.HOT_E_INVALID
+        assert run(h, binding.HOT_SLAB_GATHER, 0, None, None, ws, None) == binding.HOT_E_INVALID
+        assert run(h, binding.HOT_SLAB_SCATTER, 0, None, ctypes.c_void_p(257), ws, None) == binding.HOT_E_INVALID
+        assert run(h, binding.HOT_SLAB_CROSS, 0, None, None, ctypes.c_void_p(257), None) == binding.HOT_E_WORKSPACE
+    finally:
+        binding.hot_destroy(h)
+    h, _ = binding.hot_plan_slab(64, "rhs", 2, 1, "f64", nu=0.01)
+    try:
+        assert lib.hot_slab_run(h, binding.HOT_SLAB_INVERSE, 0, None, None, ctypes.c_void_p(256), None) == \
+            binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    # a plain plan has no slab layout
+    h, _ = binding.hot_plan(32, "rk4", "f64", nu=0.01, dt=1e-3)
+    try:
+        lay = binding.HotSlabLayout()
+        assert lib.hot_slab_layout_of(h, ctypes.byref(lay)) == binding.HOT_E_INVALID
+        assert lib.hot_slab_run(h, 0, 0, None, None, ctypes.c_void_p(256), None) == binding.HOT_E_INVALID
     finally:
         binding.hot_destroy(h)
