@@ -579,6 +579,100 @@ def _oracle_rk4_rate(seconds, core=None, n=128):
     return steps, time.perf_counter() - t0
 
 
+def bench_slab(a):
+    """One share of a z-slab decomposed field at its real shape: share
+    `rank` of `ranks` of an N^3 field (2048^3 over 8 shares by default, the
+    paper's largest mesh, which one MI355X cannot hold whole).  Times RK4
+    steps of the share's local passes (per stage: inverse x and y passes,
+    z passes with u x omega, forward y and x passes with the stage update).
+    The two all-to-alls per stage belong to the multi-GPU collective and are
+    not run: on one GPU there is no peer to exchange with, so the z pass
+    transforms whatever its receive buffer holds (the timing of every pass
+    is independent of the values).  The exchanged bytes are reported."""
+    import torch
+
+    from paper_1607_00850_amd import binding, inputs
+
+    N, R, rank, dtype = a.n, a.ranks, a.rank, a.dtype
+    cdt = torch.complex64 if dtype == "f32" else torch.complex128
+    plan, wsb = binding.hot_plan_slab(N, "rk4", R, rank, dtype, "two_thirds", NU, DT)
+    try:
+        lay = binding.hot_slab_layout_of(plan)
+        ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
+        # R1 (seed 0), the part of it in this share's kz slab
+        ix, iy, iz, vals = inputs.smooth_random_modes(N, 0)
+        keep = (iz >= lay.kz0) & (iz < lay.kz0 + lay.nkz)
+        x = torch.zeros((3, N, N, lay.nkz), dtype=cdt, device="cuda")
+        idx = [torch.from_numpy(v[keep]).long().cuda() for v in (ix, iy, iz - lay.kz0)]
+        x[:, idx[0], idx[1], idx[2]] = torch.from_numpy(vals[:, keep]).to(cdt).cuda()
+        y = torch.empty_like(x)
+        stream = torch.cuda.current_stream()
+        widths = {}
+        if not a.no_tune:
+            binding.hot_tune(plan, ws, stream)
+            widths = {k: binding.hot_tuned_width(plan, 0, k) for k in ("x_inv_curl", "y_inv", "y_fwd", "x_fwd",
+                                                                       "x_fwd_rk")}
+
+        def steps(k):
+            for _ in range(k):
+                for st in range(4):
+                    for ph in (binding.HOT_SLAB_INVERSE, binding.HOT_SLAB_CROSS, binding.HOT_SLAB_FORWARD):
+                        binding.hot_slab_run(plan, ph, ws, stage=st, stream=stream)
+
+        binding.hot_slab_run(plan, binding.HOT_SLAB_GATHER, ws, inp=x, stream=stream)
+        steps(a.warmup)
+        torch.cuda.synchronize()
+        binding.hot_profile_enable(plan, True)
+        t0 = time.perf_counter()
+        steps(a.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = binding.hot_profile_read(plan)
+        binding.hot_profile_enable(plan, False)
+        binding.hot_slab_run(plan, binding.HOT_SLAB_SCATTER, ws, out=y, stream=stream)
+        torch.cuda.synchronize()
+        pass_bytes = {k: binding.hot_pass_bytes(plan, 0, k) for k in prof}
+    finally:
+        binding.hot_destroy(plan)
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    dom = max(prof, key=lambda k: prof[k][0])
+    tot_ms, launches = prof[dom]
+    achieved = pass_bytes[dom] / (tot_ms / launches / 1e3) / 1e9
+    passes = {k: {"ms_per_launch": prof[k][0] / prof[k][1], "launches": prof[k][1],
+                  "GBps": pass_bytes[k] / (prof[k][0] / prof[k][1] / 1e3) / 1e9,
+                  "model_bytes_per_launch": pass_bytes[k]} for k in sorted(prof)}
+    step_bytes = sum(pass_bytes[k] * prof[k][1] for k in prof) / a.steps
+    # per stage: six components out and three back, one block per peer each
+    exch = 4 * (6 + 3) * (R - 1) * lay.block_bytes
+    line = {
+        "metric": "instances/sec",
+        "value": 1e3 / ms_step,
+        "unit": "RK4 steps/s of one share's local passes",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (R1 seed 0: the part in this share's kz slab)",
+        "config": {"workload": f"rk4_step_share_{rank}_of_{R}_{N}^3_{dtype}", "N": N, "shares": R, "share": rank,
+                   "x_planes": lay.nx, "kz0": lay.kz0, "retained_kz": lay.mz, "z_pitch": lay.pitch,
+                   "nu": NU, "dt": DT, "exchange": "not run (one GPU)"},
+        "elements_per_sec": float(N) ** 3 / R * 1e3 / ms_step,
+        "exchange_bytes_per_step": {"sent": exch, "received": exch},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (ms_step / 1e3) / 1e9,
+                          "frac": step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "passes": passes,
+        "tuned_columns": widths,
+        "workspace_GB": wsb / 1e9,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(N_work, seconds=12.0, max_procs=16):
     """Time the CPU oracle on RK4 steps at N = 128 and scale to instances/s of
     an N_work^3 step by the FFT cost N^3 log2 N: once on one pinned core (the
@@ -646,8 +740,11 @@ def main():
     ap.add_argument("--train-steps", type=int, default=3000, help="surrogate: Adam steps")
     ap.add_argument("--minibatch", type=int, default=4096, help="surrogate: rows per Adam step")
     ap.add_argument("--surrogate-batch", type=int, default=16384, help="surrogate: instances compared")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "surrogate", "tg"],
-                    help="single: one N^3 field (default); batch: many uneven instances, one RK4 step each")
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "surrogate", "tg", "slab"],
+                    help="single: one N^3 field (default); batch: many uneven instances, one RK4 step each; "
+                         "slab: one share of a z-slab decomposed field (use with --n 2048)")
+    ap.add_argument("--ranks", type=int, default=8, help="slab: shares of the field")
+    ap.add_argument("--rank", type=int, default=0, help="slab: the share timed")
     ap.add_argument("--batch", type=int, default=4096, help="instances of the batch workload")
     a = ap.parse_args()
     global GEN_WORKERS
@@ -681,6 +778,9 @@ def main():
         return
     if a.workload == "tg":
         bench_tg(a)
+        return
+    if a.workload == "slab":
+        bench_slab(a)
         return
 
     if a.calibrate_copy > 0:

@@ -300,10 +300,11 @@ typedef struct hot_slab_layout {
  * batch = 1, op HOT_OP_RHS or HOT_OP_RK4, flags = 0.  N must be a multiple
  * of nranks and every share must hold at least one retained kz
  * ((nranks - 1) * chunk < Mz), else HOT_E_UNSUPPORTED.  The workspace holds
- * the share's compact state and both exchange buffers.  hot_run, hot_tune,
+ * the share's compact state and both exchange buffers.  hot_run,
  * hot_graph_create and hot_diagnostics return HOT_E_UNSUPPORTED on a plan
- * with nranks > 1; hot_set_variant, profiling and hot_pass_bytes work.
- * Host only. */
+ * with nranks > 1; hot_tune (it times the local passes only, on the
+ * workspace: tune before HOT_SLAB_GATHER), hot_set_variant, profiling and
+ * hot_pass_bytes work.  Host only. */
 int hot_plan_slab(const hot_desc* d, int32_t nranks, int32_t rank, hot_plan_t* out, size_t* workspace_bytes);
 int hot_slab_layout_of(hot_plan_t p, hot_slab_layout* out);
 

@@ -861,7 +861,6 @@ extern "C" int hot_graph_destroy(hot_graph_t graph) {
 extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t reps) {
   if (!p || reps < 1) return HOT_E_INVALID;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
-  if (p->nranks > 1) return HOT_E_UNSUPPORTED;
   if (p->op != HOT_OP_RHS && p->op != HOT_OP_RK4 && p->op != HOT_OP_IMPLICIT) return HOT_OK;  // nothing to tune
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t a = nullptr, b = nullptr;

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
     if (OUT_C) {
       if (valid && kept(p, g)) store_out<false>(out + ob + (long)crow(p, g) * ld_out, v[s]);
     } else {
-      if (valid) store_out<true>(out + ob + (long)p * ld_out, v[s]);
+      if (valid) store_out<PAIR == 1>(out + ob + (long)p * ld_out, v[s]);
     }
   });
 }
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
   Plan::template fft<T, +1>(v, j, lds, TwTab<T>{tws});
   if (valid) {
     cx<T>* dst = A + o * csA + q;
-    static_for<0, R>([&](auto s) { store_stream(dst + (long)(j + s * Tl) * Q, v[s]); });
+    static_for<0, R>([&](auto s) { store_out<PAIR == 1>(dst + (long)(j + s * Tl) * Q, v[s]); });
   }
 }
 

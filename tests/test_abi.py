@@ -354,7 +354,6 @@ def test_slab_plan_and_run_rules_without_the_gpu():
         arr = (ctypes.c_void_p * 1)(256 * 1000)
         ws = ctypes.c_void_p(256 * 9)
         assert lib.hot_run(h, arr, arr, ws, 1, None) == binding.HOT_E_UNSUPPORTED
-        assert lib.hot_tune(h, ws, None, 1) == binding.HOT_E_UNSUPPORTED
         g = ctypes.c_void_p()
         assert lib.hot_graph_create(h, arr, arr, ws, 1, ctypes.c_void_p(256), ctypes.byref(g)) == \
             binding.HOT_E_UNSUPPORTED
