@@ -216,6 +216,8 @@ def bench_batch(a):
         for k in prof:
             pass_bytes[k] = sum(binding.hot_pass_bytes(plan, i, k) for i in range(len(sizes)))
         widths = {int(N): binding.hot_tuned_width(plan, int(np.argmax(sizes == N)), "y_inv") for N in set(sizes)}
+        yz_sizes = sorted(int(N) for N in set(sizes)
+                          if binding.hot_tuned_width(plan, int(np.argmax(sizes == N)), "yz_fused") > 0)
     finally:
         binding.hot_destroy(plan)
     del ws
@@ -269,6 +271,7 @@ def bench_batch(a):
         "eager_instances_per_sec": B / t_eager,
         "one_instance_per_call_instances_per_sec": B / t_single,
         "tuned_y_inv_columns": widths,
+        "fused_yz_sizes": yz_sizes,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / t_graph / 1e9,

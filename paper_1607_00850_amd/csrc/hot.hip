@@ -33,12 +33,13 @@ enum Pass : int {
   PASS_IMP_DECIDE,
   PASS_IMP_ADVANCE,
   PASS_X_FWD_RK,
+  PASS_YZ_FUSED,
   NUM_PASSES
 };
 
 static const char* kPassNames[NUM_PASSES] = {
     "gather", "x_inv_curl", "y_inv", "z_cross", "y_fwd", "x_fwd", "rk_stage", "scatter", "z_r2c", "z_c2r", "x_inv",
-    "imp_predict", "imp_update", "imp_decide", "imp_advance", "x_fwd_rk",
+    "imp_predict", "imp_update", "imp_decide", "imp_advance", "x_fwd_rk", "yz_fused",
 };
 
 template <typename T>
@@ -110,6 +111,7 @@ struct Group {
   int nparts = 0;                             // blocks of the implicit update
   int rot = 0, hist = 0;                      // implicit step: buffer rotation, history depth
   int fused = -1;  // RK4/RHS: x_fwd_rk variant fusing the x pass with the stage update, -1 = separate passes
+  int yz = -1;     // 0: the y and z passes fused (k_yz_fused), -1: y_inv, z_cross, y_fwd
   size_t bytes = 0;
   int variant[NUM_PASSES];  // strided column-width variant per pass (autotuned)
   int B() const { return (int)members.size(); }
@@ -374,6 +376,8 @@ int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) 
     // the x pass fused with the stage update: the stage traffic without the
     // nonlinear term (which stays in registers)
     case PASS_X_FWD_RK: b = p->op == HOT_OP_RK4 ? 3 * D1 + 12 * C : (p->op == HOT_OP_RHS ? 3 * D1 + 6 * C : 0); break;
+    // the y and z passes in one: six components of A1 in, three out
+    case PASS_YZ_FUSED: b = plain ? 0 : 6 * D1 + 3 * D1; break;
     default: return HOT_E_INVALID;
   }
   *bytes = b * e;
@@ -495,9 +499,24 @@ void forward_passes(Runner& r, const Group& G, const GroupPtrs& q, const int* ac
 // compact state `src` into Nh.
 void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, const int* act = nullptr,
                 bool x_fwd = true) {
-  inverse_passes(r, G, q, src, act);
-  r.pass(PASS_Z_CROSS, [&] { return G.ops.z_cross(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act); });
-  forward_passes(r, G, q, act, x_fwd);
+  if (G.yz < 0) {
+    inverse_passes(r, G, q, src, act);
+    r.pass(PASS_Z_CROSS, [&] { return G.ops.z_cross(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act); });
+    forward_passes(r, G, q, act, x_fwd);
+    return;
+  }
+  // small N: x inverse, then the y and z passes in one kernel on A1, then x forward
+  const int nb = G.B();
+  r.pass(PASS_X_INV_CURL, [&] {
+    return G.ops.x_inv_curl(r.s, G.variant[PASS_X_INV_CURL], src, G.C, 3 * G.C, q.A1, G.D1, 6 * G.D1, nb, G.g, act);
+  });
+  r.pass(PASS_YZ_FUSED, [&] { return G.ops.yz_fused(r.s, q.A1, G.D1, 6 * G.D1, nb, G.g, act); });
+  if (!x_fwd) return;
+  r.pass(PASS_X_FWD, [&] {
+    const long Q = (long)G.g.M * G.g.Mzp;
+    return G.ops.strided(r.s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3,
+                         6 * G.D1, 3 * G.C, nb, G.g, act);
+  });
 }
 
 // The stage update after the forward y pass (mode 0..3 RK4 stage, 4 plain
@@ -916,6 +935,48 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
       }
       G.variant[pid] = best_v;
     }
+    // small N: the y and z passes fused, or the three separate passes
+    if (rc == HOT_OK && G.ops.yz_fused && p->nranks == 1) {
+      float best = 1e30f;
+      int best_y = -1;
+      for (int yv = -1; yv <= 0 && rc == HOT_OK; ++yv) {
+        float t = 0.f;
+        for (int rep = 0; rep <= reps && rc == HOT_OK; ++rep) {
+          Runner r{p, s, false};
+          if (rep == 1) (void)hipEventRecord(a, s);
+          if (yv < 0) {
+            const long N = G.N, M = G.g.M, P = G.g.Mzp;
+            const int nb = G.B();
+            r.pass(PASS_Y_INV, [&] {
+              return G.ops.strided(s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P,
+                                   N * P, G.D1, G.D2, 6, 6 * G.D1, 6 * G.D2, nb, G.g, nullptr);
+            });
+            r.pass(PASS_Z_CROSS, [&] { return G.ops.z_cross(s, q.A2, G.D2, 6 * G.D2, N * N, nb, G.g, nullptr); });
+            r.pass(PASS_Y_FWD, [&] {
+              return G.ops.strided(s, G.variant[PASS_Y_FWD], -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P,
+                                   M * P, G.D2, G.D1, 3, 6 * G.D2, 6 * G.D1, nb, G.g, nullptr);
+            });
+          } else {
+            r.pass(PASS_YZ_FUSED, [&] { return G.ops.yz_fused(s, q.A1, G.D1, 6 * G.D1, G.B(), G.g, nullptr); });
+          }
+          rc = r.rc;
+        }
+        if (rc != HOT_OK) break;
+        hipError_t e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+        if (e != hipSuccess) {
+          p->last_hip = (int)e;
+          rc = HOT_E_HIP;
+          break;
+        }
+        if (t < best) {
+          best = t;
+          best_y = yv;
+        }
+      }
+      G.yz = best_y;
+    }
     // RK4 / RHS: the x pass with the stage update fused, or the two passes
     // (one stage-1 update on the workspace; every variant computes the same)
     if (rc == HOT_OK && (p->op == HOT_OP_RK4 || p->op == HOT_OP_RHS)) {
@@ -976,6 +1037,12 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
     for (auto& G : p->groups) G.fused = variant;
     return HOT_OK;
   }
+  if (pass == PASS_YZ_FUSED) {  // 0: fused wherever a size has the kernel
+    const bool plain = p->op == HOT_OP_R2C || p->op == HOT_OP_C2R;
+    if (variant < -1 || variant > 0 || plain || p->nranks > 1) return HOT_E_INVALID;
+    for (auto& G : p->groups) G.yz = (variant == 0 && G.ops.yz_fused) ? 0 : -1;
+    return HOT_OK;
+  }
   if (!tiled || variant < 0 || variant > 2) return HOT_E_INVALID;
   for (auto& G : p->groups) G.variant[pass] = variant;
   return HOT_OK;
@@ -986,6 +1053,7 @@ extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
   for (const auto& G : p->groups)
     if (G.N == p->n[instance]) {
       if (pass == PASS_X_FWD_RK) return G.fused < 0 ? 0 : G.ops.strided_width[G.fused];
+      if (pass == PASS_YZ_FUSED) return G.yz < 0 ? 0 : 1;
       return G.ops.strided_width[G.variant[pass]];
     }
   return HOT_E_INVALID;

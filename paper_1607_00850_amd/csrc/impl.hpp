@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "yz_fused.hpp"
 
 namespace hot {
 
@@ -65,6 +66,9 @@ struct Ops {
   // z_cross on lines that arrive in chunks of `chunk` coefficients, blocks blk
   // elements apart (the receive buffer of a z-slab all-to-all)
   hipError_t (*z_cross_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk);
+  // y inverse, z pass and y forward in one kernel, in place on A1 (NULL where
+  // the six planes of an x-plane do not fit in LDS)
+  hipError_t (*yz_fused)(hipStream_t, void* A, long csA, long isA, int nb, const Geo&, const int* act);
   hipError_t (*z_c2r)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
   hipError_t (*z_r2c)(hipStream_t, const void* in, void* out, long nlines, const Geo&);
   hipError_t (*rk_stage)(hipStream_t, const void* Nh, void* U0, void* U1, void* Acc, long C, long is, int nb,
@@ -198,6 +202,31 @@ struct Impl {
     if (chunk < 1) return hipErrorInvalidValue;
     return z_cross_za(s, A, csA, 0, nlines, 1, g, nullptr, ZBlocked{chunk, 1.0f / (float)chunk, blk});
   }
+  static constexpr bool kYz = N <= 64 && YzShape<T, P>::kFits;
+  static hipError_t yz_fused(hipStream_t s, void* A, long csA, long isA, int nb, const Geo& g, const int* act) {
+    if constexpr (kYz) {
+      const double n3 = double(N) * N * N;
+      const T scale = T(1.0 / (n3 * n3));
+      const size_t lds = (size_t)YzShape<T, P>::lds_bytes(g.Mz);
+      const dim3 grid((unsigned)N, (unsigned)nb);
+      constexpr int KL23 = z_loads<P>((N - 1) / 3 + 1), KLall = z_loads<P>(N / 2);
+      if (g.Mz <= KL23 * P::Tl) {
+        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, P, KL23>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_yz_fused<T, P, KL23>), grid, dim3(YzShape<T, P>::NT), lds, s, (cx<T>*)A, csA, isA, g, scale, act);
+      } else if (g.Mz <= KLall * P::Tl) {
+        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, P, KLall>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_yz_fused<T, P, KLall>), grid, dim3(YzShape<T, P>::NT), lds, s, (cx<T>*)A, csA, isA, g, scale, act);
+      } else {
+        return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    } else {
+      (void)s, (void)A, (void)csA, (void)isA, (void)nb, (void)g, (void)act;
+      return hipErrorInvalidValue;
+    }
+  }
   static hipError_t z_c2r(hipStream_t s, const void* in, void* out, long nlines, const Geo& g) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const T scale = T(1.0 / (double(N) * N * N));
@@ -264,9 +293,10 @@ struct Impl {
     return hipGetLastError();
   }
   static Ops ops() {
-    return Ops{&strided, &x_inv_curl,  &z_cross,    &z_cross_blocked, &z_c2r,       &z_r2c, &rk_stage,
-               &x_fwd_rk, &gather,    &scatter,    &imp_predict,     &imp_update,  &imp_advance, 3,
-               {WV0, W, WV2}};
+    return Ops{&strided,     &x_inv_curl, &z_cross,    &z_cross_blocked,
+               kYz ? &yz_fused : nullptr,   &z_c2r,      &z_r2c,      &rk_stage,
+               &x_fwd_rk,    &gather,     &scatter,    &imp_predict,
+               &imp_update,  &imp_advance, 3,          {WV0, W, WV2}};
   }
 };
 

@@ -1,0 +1,174 @@
+// The y and z passes of a right-hand side fused into one kernel, for sizes
+// whose six (y, kz) planes of one x-plane fit in LDS.  One block owns one
+// x-plane of one instance:
+//   load   A[6][x][M rows (ky)][Mzp] (compact rows) -> P[6][N][Mz] in LDS
+//          (row pitch Mz | 1: an odd pitch spreads a column over the banks),
+//          the rows outside the retained set as zeros
+//   y      inverse transform of every (component, kz) column, in place
+//   z      per y line: the z pass of k_z_cross (inverse real transforms of
+//          u and omega, u x omega scaled by 1/N^6, forward real transforms),
+//          components 0..2 of the row written back
+//   y      forward transform of every (component 0..2, kz) column, in place
+//   store  the retained rows of components 0..2 -> A[3][x][M][Mzp]
+// So the (x, y, kz) intermediate never goes to HBM: per x-plane the block
+// reads 6 M Mz and writes 3 M Mz values.  The transforms use the plans,
+// twiddles and arithmetic of the separate passes, so the results are the
+// same bits.  In place on A: a block reads and writes only its own x-plane.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace hot {
+
+// Stockham exchange view over one column of P (positions `stride` apart);
+// the column's lanes sit in one wave.
+template <typename T>
+struct LdsColumn {
+  cx<T>* base;
+  int stride;
+  __device__ __forceinline__ void put(int pos, cx<T> v) { base[pos * stride] = v; }
+  __device__ __forceinline__ cx<T> get(int pos) const { return base[pos * stride]; }
+  __device__ __forceinline__ void sync() { wave_sync(); }
+};
+
+// Block shape: enough waves for all N z lines of the plane in one round
+// (at most 8), so that the lanes stay busy at every size.
+template <typename T, class Plan>
+struct YzShape {
+  static constexpr int N = Plan::N, Tl = Plan::Tl;
+  static constexpr int LPW = Tl <= 64 ? 64 / Tl : 1;  // lines per wave (leftover lanes idle)
+  static constexpr int NW = (N + LPW - 1) / LPW < 8 ? (N + LPW - 1) / LPW : 8;
+  static constexpr int NT = 64 * NW;
+  static constexpr int LPR = NW * LPW;  // lines per round
+  static constexpr int ZL = LPR < N ? LPR : N;  // z lines in flight (exchange slots)
+  static constexpr int MZ = (N - 1) / 3 + 1 > N / 2 ? (N - 1) / 3 + 1 : N / 2;  // widest Mz (no dealiasing)
+  static constexpr int pitch(int Mz) { return Mz | 1; }
+  static constexpr long lds_bytes(int Mz) {
+    return (long)sizeof(cx<T>) * (6L * N * pitch(Mz) + (long)ZL * Plan::line_slots + N);
+  }
+  // the fused pass exists when a line sits in one wave and the widest
+  // retained z extent fits
+  static constexpr bool kFits = Tl <= 64 && lds_bytes(MZ) <= 163840;
+};
+
+template <typename T, class Plan, int KL>
+__global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __restrict__ A, long csA, long isA, Geo g, T scale,
+                                                  const int* __restrict__ act) {
+  using S = YzShape<T, Plan>;
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, LS = Plan::line_slots;
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* sm = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int NT = S::NT;
+  const int Mz = g.Mz, M = g.M;
+  const int Ps = S::pitch(Mz);         // row pitch of P
+  const long cs = (long)N * Ps;        // component stride of P
+  cx<T>* P = sm;                       // [6][N][Ps]
+  cx<T>* X = P + 6 * cs;               // z-line exchange slots [ZL][LS]
+  cx<T>* tws = X + (long)S::ZL * LS;   // stage twiddles [N]
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+  const bool lane_live = lane / Tl < S::LPW;
+  const int lslot = w * S::LPW + lane / Tl;  // line of this lane within a round
+  const int j = lane % Tl;
+  const long x = blockIdx.x;
+  A += blockIdx.y * isA;
+  const long plane = (long)M * g.Mzp;  // one x-plane of one component
+  TwStage<T, Plan, NT> twst;
+  twst.fetch(tid);
+  // load: the retained rows, zeros elsewhere
+  for (long e = tid; e < 6L * N * Mz; e += NT) {
+    const int c = (int)(e / ((long)N * Mz));
+    const int r = (int)(e - (long)c * N * Mz);
+    const int y = r / Mz, kz = r - y * Mz;
+    cx<T> v = {T(0), T(0)};
+    if (kept(y, g)) v = A[c * csA + x * plane + (long)crow(y, g) * g.Mzp + kz];
+    P[c * cs + (long)y * Ps + kz] = v;
+  }
+  twst.put(tws, tid);
+  __syncthreads();
+  const TwTab<T> tw{tws};
+  // y inverse: every (component, kz) column
+  for (int base = 0; base < 6 * Mz; base += S::LPR) {
+    const int id = base + lslot;
+    if (lane_live && id < 6 * Mz) {
+      const int c = id / Mz, kz = id - c * Mz;
+      LdsColumn<T> col{P + c * cs + kz, Ps};
+      cx<T> v[R];
+      static_for<0, R>([&](auto s) { v[s] = col.get(j + s * Tl); });
+      col.sync();
+      Plan::template fft<T, +1>(v, j, col, tw);
+      static_for<0, R>([&](auto s) { col.put(j + s * Tl, v[s]); });
+    }
+  }
+  __syncthreads();
+  // z lines: the computation of k_z_cross with the coefficients in P
+  for (int base = 0; base < N; base += S::ZL) {
+    const int y = base + lslot;
+    if (lane_live && lslot < S::ZL && y < N) {
+      LdsLine<T, Plan::SH, false> lds{X + (long)lslot * LS};
+      const cx<T>* row = P + (long)y * Ps;
+      cx<T> la[KL], lb[KL];
+      cx<T> ph[3][R];
+      static_for<0, 3>([&](auto pr) {
+        static_for<0, KL>([&](auto t) {
+          const int k = j + t * Tl;
+          la[t] = k < Mz ? row[(2 * pr) * cs + k] : cx<T>{T(0), T(0)};
+          lb[t] = k < Mz ? row[(2 * pr + 1) * cs + k] : cx<T>{T(0), T(0)};
+        });
+        put_completed<T, Plan, KL>(lds, la, lb, j, Mz);
+        lds.sync();
+        read_completed<T, Plan>(lds, ph[pr], j, Mz);
+        lds.sync();
+        Plan::template fft<T, +1>(ph[pr], j, lds, tw);
+      });
+      cx<T> z01[R], z2[R];
+      static_for<0, R>([&](auto s) {
+        const T u0 = ph[0][s].x, u1 = ph[0][s].y, u2 = ph[1][s].x;
+        const T w0 = ph[1][s].y, w1 = ph[2][s].x, w2 = ph[2][s].y;
+        z01[s] = {(u1 * w2 - u2 * w1) * scale, (u2 * w0 - u0 * w2) * scale};
+        z2[s] = {(u0 * w1 - u1 * w0) * scale, T(0)};
+      });
+      Plan::template fft<T, -1>(z2, j, lds, tw);
+      Plan::template fft<T, -1>(z01, j, lds, tw);
+      static_for<0, R>([&](auto s) { lds.put(j + s * Tl, z01[s]); });
+      lds.sync();
+      cx<T>* o = P + (long)y * Ps;
+      static_for<0, R>([&](auto s) {
+        const int k = j + s * Tl;
+        if (k < Mz) {
+          const cx<T> zk = lds.get(k);
+          const cx<T> zm = lds.get((N - k) % N);
+          o[k] = cx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+          o[cs + k] = cx<T>{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+          o[2 * cs + k] = z2[s];
+        }
+      });
+      lds.sync();  // the slot's next line overwrites the exchange region
+    }
+  }
+  __syncthreads();
+  // y forward: components 0..2
+  for (int base = 0; base < 3 * Mz; base += S::LPR) {
+    const int id = base + lslot;
+    if (lane_live && id < 3 * Mz) {
+      const int c = id / Mz, kz = id - c * Mz;
+      LdsColumn<T> col{P + c * cs + kz, Ps};
+      cx<T> v[R];
+      static_for<0, R>([&](auto s) { v[s] = col.get(j + s * Tl); });
+      col.sync();
+      Plan::template fft<T, -1>(v, j, col, tw);
+      static_for<0, R>([&](auto s) { col.put(j + s * Tl, v[s]); });
+    }
+  }
+  __syncthreads();
+  // store the retained rows of components 0..2
+  for (long e = tid; e < 3L * M * Mz; e += NT) {
+    const int c = (int)(e / ((long)M * Mz));
+    const int r = (int)(e - (long)c * M * Mz);
+    const int ky = r / Mz, kz = r - ky * Mz;
+    A[c * csA + x * plane + (long)ky * g.Mzp + kz] = P[c * cs + (long)cpos(ky, g) * Ps + kz];
+  }
+}
+
+}  // namespace hot

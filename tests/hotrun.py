@@ -80,13 +80,15 @@ def round32(x):
 
 
 def run_implicit(arrays, dtype="f64", nu=0.0, dt=1e-3, nsteps=1, tol=1e-10, max_iter=50, inplace=False,
-                 dealias="two_thirds"):
+                 dealias="two_thirds", variants=None):
     """The implicit step through the C ABI.  Returns (outputs, sweeps per
     instance, max_iter stops per instance, return code)."""
     torch = _torch()
     ns = [a.shape[1] for a in arrays]
     h, wsb = binding.hot_plan(ns, "implicit", dtype, dealias, nu, dt, tol, max_iter)
     try:
+        for name, v in (variants or {}).items():
+            binding.hot_set_variant(h, name, v)
         ins = [to_dev(a, dtype) for a in arrays]
         outs = ins if inplace else [empty_spectral(N, dtype) for N in ns]
         ws = workspace(wsb)

@@ -279,6 +279,50 @@ def test_set_variant_rules_without_the_gpu():
         binding.hot_destroy(h)
 
 
+def test_fused_yz_variant_rules_without_the_gpu():
+    lib = binding.library()
+    names = binding.pass_names()
+    yz = names.index("yz_fused")
+    assert names[-1] == "yz_fused"
+    # the fused y-z pass exists for small N only: a batch switches the sizes that have it
+    h, _ = binding.hot_plan([16, 64, 128, 1024], "rk4", "f32", nu=0.01, dt=1e-3)
+    try:
+        assert [binding.hot_tuned_width(h, i, "yz_fused") for i in range(4)] == [0, 0, 0, 0]
+        binding.hot_set_variant(h, "yz_fused", 0)
+        assert [binding.hot_tuned_width(h, i, "yz_fused") for i in range(4)] == [1, 1, 0, 0]
+        binding.hot_set_variant(h, "yz_fused", -1)
+        assert binding.hot_tuned_width(h, 0, "yz_fused") == 0
+        assert lib.hot_set_variant(h, yz, 1) == binding.HOT_E_INVALID
+        assert lib.hot_set_variant(h, yz, -2) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    # FP64: the six planes of N = 64 do not fit in LDS, those of N = 48 do
+    h, _ = binding.hot_plan([48, 64], "implicit", "f64", nu=0.01, dt=1e-3)
+    try:
+        binding.hot_set_variant(h, "yz_fused", 0)
+        assert [binding.hot_tuned_width(h, i, "yz_fused") for i in range(2)] == [1, 0]
+    finally:
+        binding.hot_destroy(h)
+    for op in ("r2c", "c2r"):
+        h, _ = binding.hot_plan(32, op, "f32")
+        try:
+            assert lib.hot_set_variant(h, yz, 0) == binding.HOT_E_INVALID
+        finally:
+            binding.hot_destroy(h)
+    h, _ = binding.hot_plan_slab(32, "rk4", 2, 0, "f32", nu=0.01, dt=1e-3)
+    try:
+        assert lib.hot_set_variant(h, yz, 0) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    h, _ = binding.hot_plan(64, "rk4", "f32", nu=0.01, dt=1e-3)
+    try:
+        K = 21
+        M, Mz = 2 * K + 1, K + 1
+        assert binding.hot_pass_bytes(h, 0, "yz_fused") == 9 * 64 * M * Mz * 8
+    finally:
+        binding.hot_destroy(h)
+
+
 def test_diagnostics_argument_checks_without_the_gpu():
     lib = binding.library()
     h, _ = binding.hot_plan(16, "rk4", "f64", nu=0.01, dt=1e-3)
