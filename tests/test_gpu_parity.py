@@ -129,6 +129,30 @@ def test_rk4_ten_steps_matches_oracle_fp64():
     assert rel_l2(got, ref) < 1e-11
 
 
+@pytest.mark.parametrize("kind", ["tg", "smooth", "rough"])
+def test_rk4_ten_steps_at_64_fp64(kind):
+    """The smallest configuration as the benchmark defines it: 64^3 FP64 at
+    the paper's Re = 1600 and dt = 1e-3 (Sec. 4), Taylor-Green and the two
+    random families, parity after 1 and after 10 steps."""
+    N = 64
+    print(f"rk4 10 steps N={N} {kind}", flush=True)
+    uh = field(kind, N, seed=0)
+    (one,) = run("rk4", [uh], "f64", nu=NU, dt=DT, nsteps=1)
+    (ten,) = run("rk4", [uh], "f64", nu=NU, dt=DT, nsteps=10)
+    ref1 = oracle.rk4(uh, NU, DT, 1)
+    assert rel_l2(one, ref1) < 1e-12
+    assert rel_l2(ten, oracle.rk4(ref1, NU, DT, 9)) < 1e-11
+
+
+def test_rk4_one_step_at_128_fp64():
+    """The paper's smallest whole mesh, 128^3 (Sec. 4), one FP64 RK4 step."""
+    N = 128
+    print(f"rk4 N={N} f64", flush=True)
+    uh = inputs.smooth_random(N, 1)
+    (got,) = run("rk4", [uh], "f64", nu=NU, dt=DT, nsteps=1)
+    assert rel_l2(got, oracle.rk4(uh, NU, DT, 1)) < 1e-12
+
+
 def test_rk4_in_place_and_zero_steps():
     N = 16
     uh = inputs.rough_random(N, 8, dealias="none")  # content outside the 2/3 set
