@@ -11,6 +11,9 @@ this one GPU with the all-to-all done by device copies (slab.exchange_local).
   a realistic size.
 * Edge cases: one share (the phases alone), a last share with a single
   retained kz, dealias "none", a 3-smooth N.
+* At the benchmark's shape (share 0 of 8 of 2048^3, FP32) one share alone:
+  an x-independent band-limited field whose right-hand side the oracle gives
+  exactly at 64^3 and whose exchange reduces to the share's own blocks.
 """
 import numpy as np
 import pytest
@@ -121,3 +124,80 @@ def test_shares_512_fp32_equal_the_single_field(R):
     del ws
     assert torch.equal(got, single)
     assert float(torch.linalg.vector_norm(single)) > 0
+
+
+def _x_independent_field(n, band, seed):
+    """A real solenoidal field that does not depend on x, band-limited to
+    |k_y|, |k_z| <= band, on an n^3 grid: u_x = phi(y, z), (u_y, u_z) =
+    (d psi/dz, -d psi/dy) for random trigonometric phi and psi."""
+    rng = np.random.default_rng(seed)
+    g = 2 * np.pi * np.arange(n) / n
+    Y, Z = np.meshgrid(g, g, indexing="ij")
+    phi = np.zeros((n, n))
+    uy = np.zeros((n, n))
+    uz = np.zeros((n, n))
+    for my in range(-band, band + 1):
+        for mz in range(0, band + 1):
+            if my == 0 and mz == 0:
+                continue
+            a, b, p, q = rng.standard_normal(4)
+            arg = my * Y + mz * Z
+            phi += a * np.cos(arg + p)
+            # psi = b sin(arg + q): u_y = d psi/dz, u_z = -d psi/dy
+            uy += b * mz * np.cos(arg + q)
+            uz += -b * my * np.cos(arg + q)
+    u = np.stack([phi, uy, uz])[:, None, :, :] * np.ones((1, n, 1, 1))
+    return u / np.sqrt(np.mean(u * u))
+
+
+def test_share_0_of_8_at_2048_rhs_fp32_matches_oracle_at_64():
+    """One share at the benchmark's shape (2048^3 over 8 shares, share 0,
+    FP32), checked alone.  The field does not depend on x and is band-limited
+    to |k_y|, |k_z| <= 8, so its right-hand side only has k_x = 0 and
+    |k_y|, k_z <= 16: it lies in share 0's kz slab, the oracle at 64^3 gives
+    it exactly (alias-free, nothing truncated) up to the (2048/64)^3 scale of
+    Eq. ffteq, and the exchange reduces to share 0's own blocks: every other
+    share's slab is empty going out, and every x-plane's z pass returns the
+    same values coming back."""
+    torch = _torch()
+    N, R, n = 2048, 8, 64
+    print(f"slab share 0 of {R} at N={N} f32 rhs", flush=True)
+    u = _x_independent_field(n, 8, 3)
+    uh = oracle.forward(u)
+    ref = oracle.rhs(round32(uh), NU)
+    h, wsb = binding.hot_plan_slab(N, "rhs", R, 0, "f32", "two_thirds", NU, DT)
+    try:
+        lay = binding.hot_slab_layout_of(h)
+        assert lay.kz0 == 0 and lay.nkz > 16
+        ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
+        big = np.where(np.arange(n) <= n // 2, np.arange(n), np.arange(n) - n) % N
+
+        def place(a, scale):
+            # the field's modes (rounding noise elsewhere left out)
+            nz = np.nonzero(np.abs(a).max(axis=0) > 1e-12 * np.abs(a).max())
+            x = torch.zeros((3, N, N, lay.nkz), dtype=torch.complex64, device="cuda")
+            idx = [torch.from_numpy(v).long().cuda() for v in (big[nz[0]], big[nz[1]], nz[2])]
+            x[:, idx[0], idx[1], idx[2]] = torch.from_numpy(a[:, nz[0], nz[1], nz[2]] * scale).to(torch.complex64).cuda()
+            return x, idx
+
+        x, _ = place(uh, (N / n) ** 3)
+        y = torch.empty_like(x)
+        send = slab._blocks(ws, lay, lay.send_offset, 6)
+        recv = slab._blocks(ws, lay, lay.recv_offset, 6)
+        binding.hot_slab_run(h, binding.HOT_SLAB_GATHER, ws, inp=x)
+        binding.hot_slab_run(h, binding.HOT_SLAB_INVERSE, ws, stage=4)
+        recv[:, 0].copy_(send[:, 0])  # the other shares' slabs are empty
+        binding.hot_slab_run(h, binding.HOT_SLAB_CROSS, ws, stage=4)
+        for q in range(R):  # every x-plane's z pass gives the same values
+            send[:3, q].copy_(recv[:3, 0])
+        binding.hot_slab_run(h, binding.HOT_SLAB_FORWARD, ws, stage=4)
+        binding.hot_slab_run(h, binding.HOT_SLAB_SCATTER, ws, out=y)
+        torch.cuda.synchronize()
+        del ws, x
+        exp, idx = place(ref, (N / n) ** 3)
+        assert int(idx[0].numel()) > 100
+        err = float(torch.linalg.vector_norm(y - exp) / torch.linalg.vector_norm(exp))
+        print(f"rel L2 {err:.3e}", flush=True)
+        assert err < fp32_tol(N)
+    finally:
+        binding.hot_destroy(h)
