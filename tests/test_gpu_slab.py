@@ -201,3 +201,33 @@ def test_share_0_of_8_at_2048_rhs_fp32_matches_oracle_at_64():
         assert err < fp32_tol(N)
     finally:
         binding.hot_destroy(h)
+
+
+def test_one_share_plan_runs_whole_with_hot_run():
+    """A one-share plan is the single-field plan: hot_run on it (tuned, so
+    the fused passes may be chosen) gives the single-field result."""
+    torch = _torch()
+    N = 48
+    u = inputs.rough_random(N, 12)
+    x = torch.from_numpy(u.astype(np.complex64)).cuda()
+    outs = []
+    for slab_plan in (True, False):
+        if slab_plan:
+            h, wsb = binding.hot_plan_slab(N, "rk4", 1, 0, "f32", "two_thirds", NU, DT)
+        else:
+            h, wsb = binding.hot_plan(N, "rk4", "f32", "two_thirds", NU, DT)
+        try:
+            ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
+            binding.hot_tune(h, ws)
+            for name in ("x_inv_curl", "y_inv", "y_fwd", "x_fwd"):
+                binding.hot_set_variant(h, name, 1)
+            binding.hot_set_variant(h, "x_fwd_rk", -1)
+            binding.hot_set_variant(h, "yz_fused", -1)
+            y = torch.empty_like(x)
+            binding.hot_run(h, [x], [y], ws, 2)
+            torch.cuda.synchronize()
+            outs.append(y.cpu().numpy())
+        finally:
+            binding.hot_destroy(h)
+    assert np.array_equal(outs[0], outs[1])
+    assert rel_l2(outs[0], oracle.rk4(round32(u), NU, DT, 2)) < fp32_tol(N)
