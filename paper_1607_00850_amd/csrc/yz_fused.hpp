@@ -12,8 +12,10 @@
 //   store  the retained rows of components 0..2 -> A[3][x][M][Mzp]
 // So the (x, y, kz) intermediate never goes to HBM: per x-plane the block
 // reads 6 M Mz and writes 3 M Mz values.  The transforms use the plans,
-// twiddles and arithmetic of the separate passes, so the results are the
-// same bits.  In place on A: a block reads and writes only its own x-plane.
+// twiddles and arithmetic of the separate passes; the compiler may still
+// contract multiplies and adds differently in the two kernels, so the results
+// agree to rounding.  In place on A: a block reads and writes only its own
+// x-plane.
 #pragma once
 
 #include "kernels.hpp"
