@@ -172,6 +172,43 @@ def batch_fields(sizes, dtype, first_seed=1000, modes=None):
     return ins, outs, keep
 
 
+def batch_cpu_baseline(sizes, per_size=2):
+    """The CPU oracle on the batch: one RK4 step of `per_size` instances of
+    every size (R1, the batch's seeds) on one pinned core, the mean time per
+    size summed over the batch's size counts (one core)."""
+    import numpy as np
+
+    import oracle
+    from paper_1607_00850_amd import inputs
+
+    allowed = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    if allowed:
+        os.sched_setaffinity(0, {allowed[0]})
+    try:
+        per = {}
+        for N in sorted(set(int(v) for v in sizes)):
+            first = [i for i, v in enumerate(sizes) if int(v) == N][:per_size]
+            fields = [inputs.smooth_random(N, 1000 + i) for i in first]
+            t0 = time.perf_counter()
+            for uh in fields:
+                oracle.rk4(uh, NU, DT, 1)
+            per[N] = (time.perf_counter() - t0) / len(fields)
+    finally:
+        if allowed:
+            os.sched_setaffinity(0, set(allowed))
+    counts = {int(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))}
+    total = sum(per[N] * c for N, c in counts.items())
+    return {
+        "value": len(sizes) / total,
+        "unit": "instances/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one FP64 oracle RK4 step of {per_size} instances per size, {sum(per.values()) * per_size:.1f} s; "
+                  f"mean seconds per instance by size {({N: round(t, 4) for N, t in per.items()})}, weighted by the "
+                  f"batch's size counts: {total:.1f} s per batch step on 1 core",
+    }
+
+
 def bench_batch(a):
     """Many uneven instances: one RK4 step of every instance per call."""
     import numpy as np
@@ -180,6 +217,7 @@ def bench_batch(a):
     from paper_1607_00850_amd import binding, inputs
 
     sizes = inputs.batch_sizes(a.batch, 0)
+    cpu = None if a.no_cpu_baseline else batch_cpu_baseline(sizes)
     t_gen = time.perf_counter()
     ins, outs, keep = batch_fields(sizes, a.dtype)
     t_gen = time.perf_counter() - t_gen
@@ -283,6 +321,8 @@ def bench_batch(a):
                     / t_graph / 1e9 / HBM_PEAK_GBS},
         "setup_seconds": {"fields": t_gen},
     }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     del keep
 
