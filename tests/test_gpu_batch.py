@@ -20,7 +20,7 @@ def _fields(dtype):
     return [inputs.rough_random(N, 300 + i) for i, N in enumerate(SIZES)]
 
 
-def _plan_run(fields, dtype, nsteps, op="rk4", stream=None, tune=False, graph_reps=0):
+def _plan_run(fields, dtype, nsteps, op="rk4", stream=None, tune=False, graph_reps=0, variants=None):
     import torch
     h, wsb = binding.hot_plan([f.shape[1] for f in fields], op, dtype, "two_thirds", NU, DT)
     try:
@@ -29,6 +29,8 @@ def _plan_run(fields, dtype, nsteps, op="rk4", stream=None, tune=False, graph_re
         outs = [torch.empty_like(x) for x in ins]
         if tune:
             binding.hot_tune(h, ws, stream)
+        for name, v in (variants or {}).items():
+            binding.hot_set_variant(h, name, v)
         binding.hot_run(h, ins, outs, ws, nsteps, stream)
         torch.cuda.synchronize()
         eager = [o.cpu().numpy() for o in outs]
@@ -85,6 +87,22 @@ def test_graph_replays_equal_eager_run():
     for rep in replays:
         for a, b in zip(rep, eager):
             assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_graph_replays_with_fused_passes_equal_eager_run():
+    """The fused y-z pass (small sizes) and the fused x pass inside a captured
+    graph: every replay equals the eager run bit for bit."""
+    import torch
+    s = torch.cuda.Stream()
+    fused = {"yz_fused": 0, "x_fwd_rk": 1}
+    with torch.cuda.stream(s):
+        eager, replays = _plan_run(_fields("f32"), "f32", 1, stream=s, graph_reps=3, variants=fused)
+    assert len(replays) == 3
+    for rep in replays:
+        for a, b in zip(rep, eager):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    for f, g in zip(_fields("f32"), eager):
+        assert rel_l2(g, oracle.rk4(round32(f), NU, DT, 1)) < fp32_tol(f.shape[1])
 
 
 def test_autotuned_plan_stays_correct():
