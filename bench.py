@@ -109,6 +109,17 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, command):
     print(json.dumps(out, indent=1))
 
 
+def calibrate_copy(mib):
+    """One plain device-to-device copy of `mib` MiB: a kernel of known
+    traffic for scaling the HBM byte counters."""
+    import torch
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def device_field(N, dtype, seed=0):
     """R1 (smooth random solenoidal field, E = 1/8) scattered on the GPU."""
     import torch
@@ -638,6 +649,8 @@ def bench_slab(a):
 
     N, R, rank, dtype = a.n, a.ranks, a.rank, a.dtype
     cdt = torch.complex64 if dtype == "f32" else torch.complex128
+    if a.calibrate_copy > 0:
+        calibrate_copy(a.calibrate_copy)
     plan, wsb = binding.hot_plan_slab(N, "rk4", R, rank, dtype, "two_thirds", NU, DT)
     try:
         lay = binding.hot_slab_layout_of(plan)
@@ -687,6 +700,7 @@ def bench_slab(a):
     step_bytes = sum(pass_bytes[k] * prof[k][1] for k in prof) / a.steps
     # per stage: six components out and three back, one block per peer each
     exch = 4 * (6 + 3) * (R - 1) * lay.block_bytes
+    workload = f"rk4_step_share_{rank}_of_{R}_{N}^3_{dtype}"
     line = {
         "metric": "instances/sec",
         "value": 1e3 / ms_step,
@@ -700,13 +714,13 @@ def bench_slab(a):
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic (R1 seed 0: the part in this share's kz slab)",
-        "config": {"workload": f"rk4_step_share_{rank}_of_{R}_{N}^3_{dtype}", "N": N, "shares": R, "share": rank,
+        "config": {"workload": workload, "N": N, "shares": R, "share": rank,
                    "x_planes": lay.nx, "kz0": lay.kz0, "retained_kz": lay.mz, "z_pitch": lay.pitch,
                    "nu": NU, "dt": DT, "exchange": "not run (one GPU)"},
         "elements_per_sec": float(N) ** 3 / R * 1e3 / ms_step,
         "exchange_bytes_per_step": {"sent": exch, "received": exch},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_counters(dom, workload)},
         "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (ms_step / 1e3) / 1e9,
                           "frac": step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "passes": passes,
@@ -774,6 +788,8 @@ def main():
                     help="write profiles/counters.json from two rocprofv3 --pmc counter_collection.csv files "
                          "(no GPU needed); use with --calibrate-copy MIB and --pmc-command")
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded with the counters")
+    ap.add_argument("--ingest-workload", default="",
+                    help="workload key for --ingest-counters (default: the single-field key of --n and --dtype)")
     ap.add_argument("--gen-workers", type=int, default=16, help="batch workloads: field generation processes")
     ap.add_argument("--tg-n", type=int, default=256, help="tg: points per axis")
     ap.add_argument("--tg-steps", type=int, default=20000, help="tg: RK4 steps (dt = 1e-3)")
@@ -795,7 +811,7 @@ def main():
 
     if a.ingest_counters:
         ingest_counters(a.ingest_counters[0], a.ingest_counters[1], a.calibrate_copy,
-                        f"rk4_step_{a.n}^3_{a.dtype}", a.pmc_command)
+                        a.ingest_workload or f"rk4_step_{a.n}^3_{a.dtype}", a.pmc_command)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -827,12 +843,7 @@ def main():
         return
 
     if a.calibrate_copy > 0:
-        nbytes = a.calibrate_copy << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibrate_copy(a.calibrate_copy)
 
     N, dtype = a.n, a.dtype
     x = device_field(N, dtype)
