@@ -31,7 +31,8 @@ Pins (tests marked "not gpu"): brute-force DFT sums of Eq. ffteq; the
 closed-form Taylor-Green right-hand side at t = 0; exact Beltrami decay under
 RK4; the brute-force Galerkin triad sum for the dealiased product; the energy
 budget, divergence and mean-mode identities; RK4 convergence order; numpy.cross
-for the component formula.
+for the component formula; the slab-decomposed transform with P virtual ranks
+against the serial one.
 """
 from __future__ import annotations
 
@@ -42,6 +43,8 @@ __all__ = [
     "retained_mask",
     "forward",
     "inverse",
+    "forward_slab",
+    "inverse_slab",
     "curl",
     "cross",
     "rhs",
@@ -91,6 +94,43 @@ def inverse(uh: np.ndarray, N: int) -> np.ndarray:
     """u(x) = (1/N^3) sum_k uhat_k exp(i k.x) (Eq. ffteq, first line) from the
     half-spectrum; the 1/N^3 is numpy's ``irfftn`` normalisation."""
     return np.fft.irfftn(uh, s=(N, N, N), axes=(-3, -2, -1))
+
+
+def forward_slab(u: np.ndarray, P: int) -> np.ndarray:
+    """The forward transform as the slab-decomposed 3D FFT of Sec. 3 ("Three
+    dimensional Fourier transforms with MPI") run by P virtual ranks, then
+    reassembled.  Rank r owns the physical x-planes [r Np, (r+1) Np),
+    Np = N/P.  Each rank transforms its planes along z (real to complex) and
+    y; an all-to-all then hands rank q the ky columns [q Np, (q+1) Np) of
+    every rank's planes, stacked in x order, and rank q finishes with the
+    transform along x.  Unnormalised, as forward()."""
+    N = u.shape[-1]
+    if N % P:
+        raise ValueError("P must divide N")
+    Np = N // P
+    planes = [np.fft.fft(np.fft.rfft(u[..., r * Np:(r + 1) * Np, :, :], axis=-1), axis=-2) for r in range(P)]
+    slabs = []
+    for q in range(P):
+        received = [planes[r][..., :, q * Np:(q + 1) * Np, :] for r in range(P)]
+        slabs.append(np.fft.fft(np.concatenate(received, axis=-3), axis=-3))
+    return np.concatenate(slabs, axis=-2)
+
+
+def inverse_slab(uh: np.ndarray, N: int, P: int) -> np.ndarray:
+    """The inverse of forward_slab in the reverse order (Sec. 2: the inverse
+    transforms run in the opposite order): rank q transforms its ky columns
+    back along x, an all-to-all returns the x-planes [r Np, (r+1) Np) to
+    rank r, which transforms along y and then z (complex to real).  With the
+    1/N^3 of Eq. ffteq, as inverse()."""
+    if N % P:
+        raise ValueError("P must divide N")
+    Np = N // P
+    cols = [np.fft.ifft(uh[..., :, q * Np:(q + 1) * Np, :], axis=-3) for q in range(P)]
+    planes = []
+    for r in range(P):
+        received = [cols[q][..., r * Np:(r + 1) * Np, :, :] for q in range(P)]
+        planes.append(np.fft.irfft(np.fft.ifft(np.concatenate(received, axis=-2), axis=-2), n=N, axis=-1))
+    return np.concatenate(planes, axis=-3)
 
 
 def curl(uh: np.ndarray) -> np.ndarray:

@@ -63,6 +63,20 @@ def test_inverse_matches_bruteforce_sum(N):
     np.testing.assert_allclose(back, direct, atol=1e-12)
 
 
+@pytest.mark.parametrize("N,P", [(8, 1), (8, 2), (12, 3), (16, 4), (16, 8)])
+def test_slab_transform_equals_serial(N, P):
+    """The slab algorithm with P virtual ranks and its all-to-all equals the
+    serial transform: forward bit for bit (the same 1D transforms in the
+    same order), inverse to rounding (x and y run in the other order)."""
+    rng = np.random.default_rng(7 * N + P)
+    u = rng.standard_normal((3, N, N, N))
+    uh = oracle.forward(u)
+    assert np.array_equal(oracle.forward_slab(u, P), uh)
+    back = oracle.inverse_slab(uh, N, P)
+    np.testing.assert_allclose(back, oracle.inverse(uh, N), rtol=0, atol=1e-14 * np.abs(u).max())
+    np.testing.assert_allclose(back, u, rtol=0, atol=1e-13)
+
+
 # -- component formulae ----------------------------------------------------------
 
 def test_cross_matches_numpy_cross():
