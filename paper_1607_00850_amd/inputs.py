@@ -20,6 +20,9 @@ order one, kinetic energy 1/8):
 * ``beltrami``      -- random helical field on one shell |k|^2 = K2.  Its
   vorticity is parallel to it, so the nonlinear term vanishes (used for exact
   decay checks).
+* ``wide_sparse_modes`` -- a random solenoidal field on a few modes that reach
+  the faces and corners of the retained box (full-size checks against the
+  triad-sum oracle).
 
 Randomness: numpy.random.default_rng(seed) (PCG64), drawn in an order that
 does not depend on N where stated.
@@ -39,6 +42,7 @@ __all__ = [
     "rough_random",
     "beltrami",
     "beltrami_modes",
+    "wide_sparse_modes",
     "kinetic_energy",
 ]
 
@@ -220,6 +224,29 @@ def rough_random(N: int, seed: int, dealias: str = "two_thirds") -> np.ndarray:
     return uh * np.sqrt(0.125 / E)
 
 
+def _shell_vectors(K2: int) -> np.ndarray:
+    """Integer vectors with |k|^2 = K2, in lexicographic (kx, ky, kz) order:
+    the rows of _band_vectors(floor(sqrt(K2))) that lie on the shell, found
+    per (kx, ky) column instead of by scanning the whole cube."""
+    kmax = int(np.floor(np.sqrt(K2)))
+    r = np.arange(-kmax, kmax + 1)
+    KX, KY = np.meshgrid(r, r, indexing="ij")
+    kx, ky = KX.ravel(), KY.ravel()
+    rem = K2 - kx * kx - ky * ky
+    ok = rem >= 0
+    kx, ky, rem = kx[ok], ky[ok], rem[ok]
+    s = np.floor(np.sqrt(rem.astype(np.float64))).astype(np.int64)
+    s += (s + 1) * (s + 1) <= rem  # exact integer square root
+    s -= s * s > rem
+    on = s * s == rem
+    kx, ky, s = kx[on], ky[on], s[on]
+    col = np.arange(len(kx))
+    two = s > 0  # kz = -s then +s; one row where s = 0
+    rows = np.concatenate([np.stack([kx[two], ky[two], -s[two]], -1), np.stack([kx, ky, s], -1)])
+    key = np.concatenate([2 * col[two], 2 * col + 1])
+    return rows[np.argsort(key, kind="stable")]
+
+
 def beltrami_modes(N: int, K2: int, seed: int, sign: int = 1):
     """Random field on the shell |k|^2 = K2 in sparse form: FFT indices
     (ix, iy, iz) and values (3, n) of the nonzero half-spectrum entries.
@@ -227,10 +254,7 @@ def beltrami_modes(N: int, K2: int, seed: int, sign: int = 1):
     i k x h = sign*|k| h, so the vorticity is sign*sqrt(K2) times the velocity
     and u x omega = 0.  Scaled to E = 1/8 on the N grid.  Requires the shell
     to survive the 2/3 rule."""
-    kmax = int(np.floor(np.sqrt(K2)))
-    k = _band_vectors(kmax)
-    on = np.sum(k * k, axis=-1) == K2
-    k = k[on]
+    k = _shell_vectors(K2)
     if len(k) == 0:
         raise ValueError("empty shell")
     if not np.all(_retained(N, k, "two_thirds")):
@@ -258,6 +282,45 @@ def beltrami(N: int, K2: int, seed: int, sign: int = 1) -> np.ndarray:
     uh = np.zeros(_half_shape(N), dtype=np.complex128)
     uh[:, ix, iy, iz] = vals
     return uh
+
+
+def wide_sparse_modes(N: int, count: int, seed: int, dealias: str = "two_thirds"):
+    """A random solenoidal field on a few modes spread over the whole retained
+    set, in the sparse form of smooth_random_modes: FFT indices (ix, iy, iz)
+    and values (3, n).  The modes are the corners, edge midpoints and face
+    centres of the retained box (components 0 and +-kmax, +-(kmax - 1)) and
+    `count` wavenumbers drawn uniformly from the retained half box.  On the
+    kz = 0 plane both k and -k are stored, with conjugate values.  E = 1/8 on
+    the N grid."""
+    kmax = (N - 1) // 3 if dealias == "two_thirds" else N // 2 - 1
+    rng = np.random.default_rng(seed)
+    drawn = np.stack([rng.integers(-kmax, kmax + 1, count), rng.integers(-kmax, kmax + 1, count),
+                      rng.integers(0, kmax + 1, count)], axis=-1)
+    c = np.array([-kmax, 0, kmax])
+    d = np.array([-(kmax - 1), kmax - 1])
+    box = np.stack(np.meshgrid(c, c, np.array([0, kmax]), indexing="ij"), -1).reshape(-1, 3)
+    near = np.stack(np.meshgrid(d, d, np.array([kmax - 1]), indexing="ij"), -1).reshape(-1, 3)
+    k = np.concatenate([box, near, drawn])
+    z0 = k[k[:, 2] == 0]
+    k = np.unique(np.concatenate([k, -z0]), axis=0)  # lexicographic, -k paired on kz = 0
+    k = k[np.any(k != 0, axis=-1)]
+    n = len(k)
+    a1 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    a2 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    e1, e2 = _plane_basis(k)
+    vals = (a1[:, None] * e1 + a2[:, None] * e2).T.copy()
+    # kz = 0: the row of -k takes the conjugate of the row of k (k > -k in
+    # lexicographic order keeps its own draw)
+    z = np.nonzero(k[:, 2] == 0)[0]
+    row = {tuple(k[m]): m for m in z}
+    for m in z:
+        q = row[tuple(-k[m])]
+        if tuple(k[m]) < tuple(k[q]):
+            vals[:, m] = np.conj(vals[:, q])
+    w = np.where(k[:, 2] == 0, 1.0, 2.0)
+    E = float(np.sum(w * np.sum(np.abs(vals) ** 2, axis=0)) / (2.0 * float(N) ** 6))
+    vals *= np.sqrt(0.125 / E)
+    return k[:, 0] % N, k[:, 1] % N, k[:, 2], vals
 
 
 BATCH_SIZES = (16, 18, 24, 32, 36, 48, 54, 64)

@@ -11,7 +11,12 @@ right-hand side the oracle computes at a small N:
     |k_i| <= 32, which the 2/3 rule keeps and does not alias at N = 128, so
     the oracle at N = 128 gives every nonzero coefficient of the 1024^3
     right-hand side.
-  * a Beltrami field decays exactly as R(z)^n under RK4.
+  * a few modes on the faces and corners of the retained box and spread over
+    it (inputs.wide_sparse_modes): the triad-sum oracle gives the exact
+    right-hand side at 1024^3, and the ragged last tiles and the 2/3 cut of
+    every pass see nonzero data.
+  * a Beltrami field decays exactly as R(z)^n under RK4, on a mid shell and
+    on the shell |k| = 341 that touches the faces of the retained box.
 The comparison runs on the GPU (torch) to avoid copying 13 GB to the host.
 """
 import numpy as np
@@ -111,13 +116,34 @@ def test_band_limited_rhs_1024_fp32_matches_oracle_at_128(tune):
 
 
 @pytest.mark.parametrize("tune", [False, True])
-def test_beltrami_rk4_1024_fp32_exact_decay(tune):
+def test_wide_sparse_rhs_1024_fp32_matches_triad_oracle(tune):
+    print(f"fullsize: wide sparse rhs tune={tune}", flush=True)
+    ix, iy, iz, vals = inputs.wide_sparse_modes(N, 128, seed=5)
+    v32 = vals.astype(np.complex64)
+    x = _sparse_to_gpu((ix, iy, iz), v32)
+    y = _run("rhs", x, tune=tune)
+    del x
+    s = inputs.signed_index(N)
+    kout, ref = oracle.rhs_triads(np.stack([s[ix], s[iy], iz], -1), v32.astype(np.complex128), N, NU)
+    assert np.abs(kout).max() == (N - 1) // 3 and len(kout) > 5000
+    expect = _sparse_to_gpu((kout[:, 0] % N, kout[:, 1] % N, kout[:, 2]), ref)
+    torch = _torch()
+    err = torch.linalg.vector_norm((y - expect).reshape(-1).to(torch.complex128))
+    den = torch.linalg.vector_norm(expect.reshape(-1).to(torch.complex128))
+    print(f"rel L2 {float(err / den):.3e} over {len(kout)} modes", flush=True)
+    assert float(err / den) < fp32_tol(N)
+
+
+@pytest.mark.parametrize("K2", [10000, 341**2])
+@pytest.mark.parametrize("tune", [False, True])
+def test_beltrami_rk4_1024_fp32_exact_decay(tune, K2):
     # Explicit RK4 is stable for the viscous term only while dt nu |k|^2 stays
     # inside its real stability interval (|z| < 2.78); at N = 1024 the largest
-    # retained |k|^2 is 3 * 341^2, so nu dt = 5e-6 gives |z| <= 1.75 there.  A
-    # high shell (|k|^2 = 10^4) makes the decay per step clearly visible.
-    print("fullsize: Beltrami rk4", flush=True)
-    K2, nu, dt, n = 10000, 1e-3, 5e-3, 2
+    # retained |k|^2 is 3 * 341^2, so nu dt = 5e-6 gives |z| <= 1.75 there.  The
+    # shells |k|^2 = 10^4 and 341^2 make the decay per step clearly visible;
+    # the second reaches k_i = +-341 on every axis, the last retained index.
+    print(f"fullsize: Beltrami rk4 K2={K2} tune={tune}", flush=True)
+    nu, dt, n = 1e-3, 5e-3, 2
     assert nu * dt * 3 * 341**2 < 2.78
     ix, iy, iz, vals = inputs.beltrami_modes(N, K2, seed=4)
     x = _sparse_to_gpu((ix, iy, iz), vals)
