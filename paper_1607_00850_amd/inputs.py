@@ -22,7 +22,8 @@ order one, kinetic energy 1/8):
   decay checks).
 * ``wide_sparse_modes`` -- a random solenoidal field on a few modes that reach
   the faces and corners of the retained box (full-size checks against the
-  triad-sum oracle).
+  triad-sum oracle); ``plane_sparse_modes`` -- the same for a field that does
+  not depend on x, with kz held below a bound (one slab share at full size).
 
 Randomness: numpy.random.default_rng(seed) (PCG64), drawn in an order that
 does not depend on N where stated.
@@ -43,6 +44,7 @@ __all__ = [
     "beltrami",
     "beltrami_modes",
     "wide_sparse_modes",
+    "plane_sparse_modes",
     "kinetic_energy",
 ]
 
@@ -311,6 +313,40 @@ def wide_sparse_modes(N: int, count: int, seed: int, dealias: str = "two_thirds"
     vals = (a1[:, None] * e1 + a2[:, None] * e2).T.copy()
     # kz = 0: the row of -k takes the conjugate of the row of k (k > -k in
     # lexicographic order keeps its own draw)
+    z = np.nonzero(k[:, 2] == 0)[0]
+    row = {tuple(k[m]): m for m in z}
+    for m in z:
+        q = row[tuple(-k[m])]
+        if tuple(k[m]) < tuple(k[q]):
+            vals[:, m] = np.conj(vals[:, q])
+    w = np.where(k[:, 2] == 0, 1.0, 2.0)
+    E = float(np.sum(w * np.sum(np.abs(vals) ** 2, axis=0)) / (2.0 * float(N) ** 6))
+    vals *= np.sqrt(0.125 / E)
+    return k[:, 0] % N, k[:, 1] % N, k[:, 2], vals
+
+
+def plane_sparse_modes(N: int, count: int, seed: int, kz_max: int):
+    """A random solenoidal field that does not depend on x (every mode has
+    kx = 0) on a few modes, in the sparse form of smooth_random_modes: ky
+    over the whole retained range (+-kmax included), kz in 0..kz_max (both
+    ends included).  On the kz = 0 plane both k and -k are stored, with
+    conjugate values.  E = 1/8 on the N grid."""
+    kmax = (N - 1) // 3
+    if not 0 < kz_max <= kmax:
+        raise ValueError("kz_max outside the retained range")
+    rng = np.random.default_rng(seed)
+    drawn = np.stack([np.zeros(count, dtype=np.int64), rng.integers(-kmax, kmax + 1, count),
+                      rng.integers(0, kz_max + 1, count)], axis=-1)
+    ends = np.array([[0, ky, kz] for ky in (-kmax, -1, 1, kmax) for kz in (0, kz_max)] + [[0, 0, kz_max]])
+    k = np.concatenate([ends, drawn])
+    z0 = k[k[:, 2] == 0]
+    k = np.unique(np.concatenate([k, -z0]), axis=0)
+    k = k[np.any(k != 0, axis=-1)]
+    n = len(k)
+    a1 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    a2 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    e1, e2 = _plane_basis(k)
+    vals = (a1[:, None] * e1 + a2[:, None] * e2).T.copy()
     z = np.nonzero(k[:, 2] == 0)[0]
     row = {tuple(k[m]): m for m in z}
     for m in z:

@@ -14,7 +14,7 @@ right-hand side the oracle computes at a small N:
   * a few modes on the faces and corners of the retained box and spread over
     it (inputs.wide_sparse_modes): the triad-sum oracle gives the exact
     right-hand side at 1024^3, and the ragged last tiles and the 2/3 cut of
-    every pass see nonzero data.
+    every pass see nonzero data (FP32, untuned and tuned, and FP64).
   * a Beltrami field decays exactly as R(z)^n under RK4, on a mid shell and
     on the shell |k| = 341 that touches the faces of the retained box.
 The comparison runs on the GPU (torch) to avoid copying 13 GB to the host.
@@ -185,6 +185,34 @@ def test_band_limited_rhs_1024_fp64_matches_oracle_at_128():
     assert np.linalg.norm(got - r) <= 1e-12 * np.linalg.norm(r)
     # every other coefficient is zero: the norms agree
     assert float(torch.linalg.vector_norm(y)) == pytest.approx(float(np.linalg.norm(r)), rel=1e-12)
+
+
+def test_wide_sparse_rhs_1024_fp64_matches_triad_oracle():
+    # the FP64 kernels' tiles at the faces of the retained box, at the FP64 bar
+    print("fullsize: wide sparse rhs fp64", flush=True)
+    torch = _torch()
+    ix, iy, iz, vals = inputs.wide_sparse_modes(N, 128, seed=6)
+    x = torch.zeros((3, N, N, N // 2 + 1), dtype=torch.complex128, device="cuda")
+    idx = [torch.from_numpy(np.asarray(a)).long().cuda() for a in (ix, iy, iz)]
+    x[:, idx[0], idx[1], idx[2]] = torch.from_numpy(np.asarray(vals)).cuda()
+    h, wsb = binding.hot_plan(N, "rhs", "f64", "two_thirds", NU, 1e-3)
+    try:
+        y = torch.empty_like(x)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        binding.hot_run(h, [x], [y], ws, 0)
+        torch.cuda.synchronize()
+        del ws, x
+    finally:
+        binding.hot_destroy(h)
+    s = inputs.signed_index(N)
+    kout, ref = oracle.rhs_triads(np.stack([s[ix], s[iy], iz], -1), vals, N, NU)
+    sel = [torch.from_numpy(a).long().cuda() for a in (kout[:, 0] % N, kout[:, 1] % N, kout[:, 2])]
+    got = y[:, sel[0], sel[1], sel[2]].cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"rel L2 {err:.3e} over {len(kout)} modes", flush=True)
+    assert err <= 1e-12
+    # every other coefficient is zero to rounding: the norms agree
+    assert float(torch.linalg.vector_norm(y)) == pytest.approx(float(np.linalg.norm(ref)), rel=1e-12)
 
 
 def test_implicit_beltrami_1024_fp32_crank_nicolson_factor():

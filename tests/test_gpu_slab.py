@@ -150,6 +150,27 @@ def _x_independent_field(n, band, seed):
     return u / np.sqrt(np.mean(u * u))
 
 
+def _share0_rhs_alone(h, lay, ws, x, R):
+    """One right-hand side on share 0 alone, for an x-independent field whose
+    modes and right-hand side lie in share 0's kz slab: every other share's
+    slab is empty going out, and every x-plane's z pass gives the same values
+    coming back, so the exchange reduces to share 0's own blocks."""
+    torch = _torch()
+    y = torch.empty_like(x)
+    send = slab._blocks(ws, lay, lay.send_offset, 6)
+    recv = slab._blocks(ws, lay, lay.recv_offset, 6)
+    binding.hot_slab_run(h, binding.HOT_SLAB_GATHER, ws, inp=x)
+    binding.hot_slab_run(h, binding.HOT_SLAB_INVERSE, ws, stage=4)
+    recv[:, 0].copy_(send[:, 0])
+    binding.hot_slab_run(h, binding.HOT_SLAB_CROSS, ws, stage=4)
+    for q in range(R):
+        send[:3, q].copy_(recv[:3, 0])
+    binding.hot_slab_run(h, binding.HOT_SLAB_FORWARD, ws, stage=4)
+    binding.hot_slab_run(h, binding.HOT_SLAB_SCATTER, ws, out=y)
+    torch.cuda.synchronize()
+    return y
+
+
 def test_share_0_of_8_at_2048_rhs_fp32_matches_oracle_at_64():
     """One share at the benchmark's shape (2048^3 over 8 shares, share 0,
     FP32), checked alone.  The field does not depend on x and is band-limited
@@ -181,18 +202,7 @@ def test_share_0_of_8_at_2048_rhs_fp32_matches_oracle_at_64():
             return x, idx
 
         x, _ = place(uh, (N / n) ** 3)
-        y = torch.empty_like(x)
-        send = slab._blocks(ws, lay, lay.send_offset, 6)
-        recv = slab._blocks(ws, lay, lay.recv_offset, 6)
-        binding.hot_slab_run(h, binding.HOT_SLAB_GATHER, ws, inp=x)
-        binding.hot_slab_run(h, binding.HOT_SLAB_INVERSE, ws, stage=4)
-        recv[:, 0].copy_(send[:, 0])  # the other shares' slabs are empty
-        binding.hot_slab_run(h, binding.HOT_SLAB_CROSS, ws, stage=4)
-        for q in range(R):  # every x-plane's z pass gives the same values
-            send[:3, q].copy_(recv[:3, 0])
-        binding.hot_slab_run(h, binding.HOT_SLAB_FORWARD, ws, stage=4)
-        binding.hot_slab_run(h, binding.HOT_SLAB_SCATTER, ws, out=y)
-        torch.cuda.synchronize()
+        y = _share0_rhs_alone(h, lay, ws, x, R)
         del ws, x
         exp, idx = place(ref, (N / n) ** 3)
         assert int(idx[0].numel()) > 100
@@ -231,3 +241,40 @@ def test_one_share_plan_runs_whole_with_hot_run():
             binding.hot_destroy(h)
     assert np.array_equal(outs[0], outs[1])
     assert rel_l2(outs[0], oracle.rk4(round32(u), NU, DT, 2)) < fp32_tol(N)
+
+
+def test_share_0_of_8_at_2048_sparse_rhs_fp32_matches_triad_oracle():
+    """The same share with an x-independent sparse field whose ky reach the
+    retained limit +-682 and whose kz reach 42, so that its right-hand side
+    (kz <= 84) stays in share 0's slab of 86 retained kz: the triad-sum
+    oracle gives it exactly at 2048^3, and the column tiles at the edges of
+    the retained ky range carry data."""
+    torch = _torch()
+    N, R = 2048, 8
+    print(f"slab share 0 of {R} at N={N} f32 rhs, sparse", flush=True)
+    ix, iy, iz, vals = inputs.plane_sparse_modes(N, 96, 8, kz_max=42)
+    v32 = vals.astype(np.complex64)
+    s = inputs.signed_index(N)
+    kout, ref = oracle.rhs_triads(np.stack([s[ix], s[iy], iz], -1), v32.astype(np.complex128), N, NU)
+    assert np.all(kout[:, 0] == 0) and kout[:, 2].max() <= 84 and np.abs(kout[:, 1]).max() == (N - 1) // 3
+    h, wsb = binding.hot_plan_slab(N, "rhs", R, 0, "f32", "two_thirds", NU, DT)
+    try:
+        lay = binding.hot_slab_layout_of(h)
+        assert lay.kz0 == 0 and lay.nkz > 84
+        ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
+
+        def dense(k, v):
+            d = torch.zeros((3, N, N, lay.nkz), dtype=torch.complex64, device="cuda")
+            idx = [torch.from_numpy(np.asarray(a)).long().cuda() for a in (k[:, 0] % N, k[:, 1] % N, k[:, 2])]
+            d[:, idx[0], idx[1], idx[2]] = torch.from_numpy(v).to(torch.complex64).cuda()
+            return d
+
+        x = dense(np.stack([ix, iy, iz], -1), v32)
+        y = _share0_rhs_alone(h, lay, ws, x, R)
+        del ws, x
+        exp = dense(kout, ref)
+        err = float(torch.linalg.vector_norm(y - exp) / torch.linalg.vector_norm(exp))
+        print(f"rel L2 {err:.3e} over {len(kout)} modes", flush=True)
+        assert err < fp32_tol(N)
+    finally:
+        binding.hot_destroy(h)

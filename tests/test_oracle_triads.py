@@ -148,3 +148,20 @@ def test_wide_sparse_modes_real_solenoidal_reaching_the_box(N, dealias):
         assert np.array_equal(vals[:, j], np.conj(vals[:, i]))
     w = np.where(k[:, 2] == 0, 1.0, 2.0)
     assert np.isclose(np.sum(w * np.sum(np.abs(vals) ** 2, axis=0)) / (2.0 * float(N) ** 6), 0.125)
+
+
+def test_plane_sparse_modes_x_independent_real_solenoidal():
+    N, kz_max = 2048, 42
+    ix, iy, iz, vals = inputs.plane_sparse_modes(N, 60, 9, kz_max)
+    k = _signed(ix, iy, iz, N)
+    assert np.all(k[:, 0] == 0) and k[:, 2].min() == 0 and k[:, 2].max() == kz_max
+    assert k[:, 1].min() == -((N - 1) // 3) and k[:, 1].max() == (N - 1) // 3
+    assert np.all(np.abs(np.sum(k.T * vals, axis=0)) < 1e-12 * np.linalg.norm(vals, axis=0) * (1 + np.abs(k).sum(-1)))
+    pos = {tuple(m): i for i, m in enumerate(k)}
+    for i in np.nonzero(k[:, 2] == 0)[0]:
+        assert np.array_equal(vals[:, pos[tuple(-k[i])]], np.conj(vals[:, i]))
+    # its right-hand side has kx = 0 and kz <= 2 kz_max
+    kout, _ = oracle.rhs_triads(k, vals, N, 0.01)
+    assert np.all(kout[:, 0] == 0) and kout[:, 2].max() <= 2 * kz_max
+    with pytest.raises(ValueError):
+        inputs.plane_sparse_modes(N, 4, 0, (N - 1) // 3 + 1)
