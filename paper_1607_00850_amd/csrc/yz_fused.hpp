@@ -78,15 +78,27 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
   const long plane = (long)M * g.Mzp;  // one x-plane of one component
   TwStage<T, Plan, NT> twst;
   twst.fetch(tid);
-  // load: the retained rows, zeros elsewhere
-  for (long e = tid; e < 6L * N * Mz; e += NT) {
-    const int c = (int)(e / ((long)N * Mz));
-    const int r = (int)(e - (long)c * N * Mz);
+  // load: the retained rows, zeros elsewhere.  A fixed count per thread (at
+  // the widest Mz), every lane loading from a valid address and selecting
+  // afterwards, so that all of a thread's loads are in flight together
+  // instead of one HBM latency per element.
+  constexpr int LD = (6 * N * S::MZ + NT - 1) / NT;
+  const int total = 6 * N * Mz;
+  cx<T> ld[LD];
+  int at[LD];
+  static_for<0, LD>([&](auto i) {
+    const int e = tid + i * NT;
+    const int c = e / (N * Mz);
+    const int r = e - c * N * Mz;
     const int y = r / Mz, kz = r - y * Mz;
-    cx<T> v = {T(0), T(0)};
-    if (kept(y, g)) v = A[c * csA + x * plane + (long)crow(y, g) * g.Mzp + kz];
-    P[c * cs + (long)y * Ps + kz] = v;
-  }
+    const bool kp = e < total && kept(y, g);
+    const cx<T> v = A[kp ? c * csA + x * plane + (long)crow(y, g) * g.Mzp + kz : 0];
+    ld[i] = kp ? v : cx<T>{T(0), T(0)};
+    at[i] = e < total ? c * (int)cs + y * Ps + kz : -1;
+  });
+  static_for<0, LD>([&](auto i) {
+    if (at[i] >= 0) P[at[i]] = ld[i];
+  });
   twst.put(tws, tid);
   __syncthreads();
   const TwTab<T> tw{tws};
