@@ -82,20 +82,30 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
   // the widest Mz), every lane loading from a valid address and selecting
   // afterwards, so that all of a thread's loads are in flight together
   // instead of one HBM latency per element.
+  // Element e = tid + i NT of [6][N][Mz] sits in row e / Mz at kz = e % Mz;
+  // both follow from the previous element by the constant step NT = sq Mz +
+  // sr, so one division per thread replaces two per element.
   constexpr int LD = (6 * N * S::MZ + NT - 1) / NT;
-  const int total = 6 * N * Mz;
+  const int sq = NT / Mz, sr = NT - sq * Mz;
   cx<T> ld[LD];
   int at[LD];
-  static_for<0, LD>([&](auto i) {
-    const int e = tid + i * NT;
-    const int c = e / (N * Mz);
-    const int r = e - c * N * Mz;
-    const int y = r / Mz, kz = r - y * Mz;
-    const bool kp = e < total && kept(y, g);
-    const cx<T> v = A[kp ? c * csA + x * plane + (long)crow(y, g) * g.Mzp + kz : 0];
-    ld[i] = kp ? v : cx<T>{T(0), T(0)};
-    at[i] = e < total ? c * (int)cs + y * Ps + kz : -1;
-  });
+  {
+    int row = tid / Mz, kz = tid - (tid / Mz) * Mz;
+    static_for<0, LD>([&](auto i) {
+      const int c = row / N, y = row - (row / N) * N;
+      const bool in = row < 6 * N;
+      const bool kp = in && kept(y, g);
+      const cx<T> v = A[kp ? c * csA + x * plane + (long)crow(y, g) * g.Mzp + kz : 0];
+      ld[i] = kp ? v : cx<T>{T(0), T(0)};
+      at[i] = in ? c * (int)cs + y * Ps + kz : -1;
+      kz += sr;
+      row += sq;
+      if (kz >= Mz) {
+        kz -= Mz;
+        ++row;
+      }
+    });
+  }
   static_for<0, LD>([&](auto i) {
     if (at[i] >= 0) P[at[i]] = ld[i];
   });
@@ -176,12 +186,24 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
     }
   }
   __syncthreads();
-  // store the retained rows of components 0..2
-  for (long e = tid; e < 3L * M * Mz; e += NT) {
-    const int c = (int)(e / ((long)M * Mz));
-    const int r = (int)(e - (long)c * M * Mz);
-    const int ky = r / Mz, kz = r - ky * Mz;
-    A[c * csA + x * plane + (long)ky * g.Mzp + kz] = P[c * cs + (long)cpos(ky, g) * Ps + kz];
+  // store the retained rows of components 0..2 ([3][M][Mz], stepped as the
+  // load)
+  {
+    int kz = tid - (tid / Mz) * Mz, ky = tid / Mz, c = ky / M;
+    ky -= c * M;
+    while (c < 3) {
+      A[c * csA + x * plane + (long)ky * g.Mzp + kz] = P[c * cs + (long)cpos(ky, g) * Ps + kz];
+      kz += sr;
+      ky += sq;
+      if (kz >= Mz) {
+        kz -= Mz;
+        ++ky;
+      }
+      while (ky >= M) {
+        ky -= M;
+        ++c;
+      }
+    }
   }
 }
 
