@@ -264,15 +264,17 @@ struct Impl {
   }
   static hipError_t gather(hipStream_t s, const void* in0, const void* const* in_tab, void* out, long C, long is,
                            int nb, const Geo& g) {
-    hipLaunchKernelGGL((k_gather<T>), dim3(grid_1d(3 * C, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in0,
-                       (const cx<T>* const*)in_tab, (cx<T>*)out, C, is, g);
+    const unsigned grid = grid_1d(3 * C, 256);
+    hipLaunchKernelGGL((k_gather<T>), dim3(grid, (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in0,
+                       (const cx<T>* const*)in_tab, (cx<T>*)out, C, is, g, pos4_of(256L * grid, g.M, g.M, g.Mzp));
     return hipGetLastError();
   }
   static hipError_t scatter(hipStream_t s, const void* in, void* out0, void* const* out_tab, long C, long is, int nb,
                             const Geo& g) {
     const long total = 3L * g.N * g.N * g.czp;
-    hipLaunchKernelGGL((k_scatter<T>), dim3(grid_1d(total, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in,
-                       (cx<T>*)out0, (cx<T>* const*)out_tab, C, is, g);
+    const unsigned grid = grid_1d(total, 256);
+    hipLaunchKernelGGL((k_scatter<T>), dim3(grid, (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in,
+                       (cx<T>*)out0, (cx<T>* const*)out_tab, C, is, g, pos4_of(256L * grid, g.N, g.N, g.czp));
     return hipGetLastError();
   }
   static hipError_t imp_predict(hipStream_t s, const void* U0, void* D, void* U1, const void* H1, const void* H2,

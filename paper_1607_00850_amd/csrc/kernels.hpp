@@ -879,47 +879,83 @@ __global__ __launch_bounds__(64) void k_diag_final(const double* __restrict__ pa
 // blockIdx.y is the instance of a batch; the canonical array of instance b
 // is tab[b] when a device pointer table is given.
 // ---------------------------------------------------------------------------
+// Position (c, a, b, z) of a flat index over [3][na][nb][nz], advanced by a
+// constant step with carries: the grid-stride loops below divide once per
+// thread instead of three times per element (64-bit divisions made them
+// VALU-bound).  The host decomposes the grid stride itself.
+struct Pos4 {
+  int c, a, b, z;
+};
+
+__host__ __device__ __forceinline__ Pos4 pos4_of(long e, int na, int nb, int nz) {
+  const long row = e / nz;
+  const long ab = row / nb;
+  Pos4 p;
+  p.z = (int)(e - row * nz);
+  p.b = (int)(row - ab * nb);
+  p.c = (int)(ab / na);
+  p.a = (int)(ab - (long)p.c * na);
+  return p;
+}
+
+// The same for a thread's first index (below 2^31: at most 65535 blocks of
+// 256 threads), in 32-bit arithmetic.
+__device__ __forceinline__ Pos4 pos4_first(unsigned e, unsigned na, unsigned nb, unsigned nz) {
+  const unsigned row = e / nz;
+  const unsigned ab = row / nb;
+  Pos4 p;
+  p.z = (int)(e - row * nz);
+  p.b = (int)(row - ab * nb);
+  p.c = (int)(ab / na);
+  p.a = (int)(ab - (unsigned)p.c * na);
+  return p;
+}
+
+__device__ __forceinline__ void pos4_add(Pos4& p, const Pos4& s, int na, int nb, int nz) {
+  p.z += s.z;
+  int k = p.z >= nz;
+  p.z -= k ? nz : 0;
+  p.b += s.b + k;
+  k = p.b >= nb;
+  p.b -= k ? nb : 0;
+  p.a += s.a + k;
+  k = p.a >= na;
+  p.a -= k ? na : 0;
+  p.c += s.c + k;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in0, const cx<T>* const* __restrict__ in_tab,
-                                                cx<T>* __restrict__ out, long C, long is, Geo g) {
+                                                cx<T>* __restrict__ out, long C, long is, Geo g, Pos4 st) {
   // instance blockIdx.y: its canonical input from the table (or in0 alone)
   const cx<T>* __restrict__ in = in_tab ? in_tab[blockIdx.y] : in0;
   out += blockIdx.y * is;
   const long stride = (long)gridDim.x * blockDim.x;
   const long Nh = g.czp;  // canonical z extent; its kz 0 is local column 0
-  const long MMz = (long)g.M * g.Mzp;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < 3 * C; e += stride) {
-    const int c = (int)(e / C);
-    const long r0 = e - c * C;
-    const int ix = (int)(r0 / MMz);
-    const long r = r0 - ix * MMz;
-    const int iy = (int)(r / g.Mzp);
-    const int kz = (int)(r - (long)iy * g.Mzp);
-    if (kz >= g.Mz) continue;
-    const long src = (((long)c * g.N + cpos(ix, g)) * g.N + cpos(iy, g)) * Nh + kz;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // compact [3][M][M][Mzp]; st: the grid stride in the same digits
+  Pos4 p = pos4_first((unsigned)e, g.M, g.M, g.Mzp);
+  for (; p.c < 3; e += stride, pos4_add(p, st, g.M, g.M, g.Mzp)) {
+    if (p.z >= g.Mz) continue;
+    const long src = (((long)p.c * g.N + cpos(p.a, g)) * g.N + cpos(p.b, g)) * Nh + p.z;
     store_stream(out + e, in[src]);
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, cx<T>* out0, cx<T>* const* __restrict__ out_tab,
-                                                 long C, long is, Geo g) {
+                                                 long C, long is, Geo g, Pos4 st) {
   cx<T>* __restrict__ out = out_tab ? out_tab[blockIdx.y] : out0;
   in += blockIdx.y * is;
   const long stride = (long)gridDim.x * blockDim.x;
-  const long Nh = g.czp;
-  const long plane = (long)g.N * Nh;
-  const long total = 3L * g.N * plane;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const int c = (int)(e / ((long)g.N * plane));
-    const long r0 = e - (long)c * g.N * plane;
-    const int px = (int)(r0 / plane);
-    const long r = r0 - px * plane;
-    const int py = (int)(r / Nh);
-    const int kz = (int)(r - (long)py * Nh);
+  const int Nh = g.czp;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // canonical [3][N][N][Nh]; st: the grid stride in the same digits
+  Pos4 p = pos4_first((unsigned)e, g.N, g.N, Nh);
+  for (; p.c < 3; e += stride, pos4_add(p, st, g.N, g.N, Nh)) {
     cx<T> v = {T(0), T(0)};
-    if (kz < g.Mz && kept(px, g) && kept(py, g))
-      v = in[(long)c * C + ((long)crow(px, g) * g.M + crow(py, g)) * g.Mzp + kz];
+    if (p.z < g.Mz && kept(p.a, g) && kept(p.b, g))
+      v = in[(long)p.c * C + ((long)crow(p.a, g) * g.M + crow(p.b, g)) * g.Mzp + p.z];
     store_stream(out + e, v);
   }
 }
