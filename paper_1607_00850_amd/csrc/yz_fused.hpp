@@ -2,8 +2,8 @@
 // whose six (y, kz) planes of one x-plane fit in LDS.  One block owns one
 // x-plane of one instance:
 //   load   A[6][x][M rows (ky)][Mzp] (compact rows) -> P[6][N][Mz] in LDS
-//          (row pitch Mz | 1: an odd pitch spreads a column over the banks),
-//          the rows outside the retained set as zeros
+//          (row pitch Mz | 1: an odd pitch spreads a column over the banks);
+//          the rows outside the retained set are read as zeros
 //   y      inverse transform of every (component, kz) column, in place
 //   z      per y line: the z pass of k_z_cross (inverse real transforms of
 //          u and omega, u x omega scaled by 1/N^6, forward real transforms),
@@ -78,37 +78,37 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
   const long plane = (long)M * g.Mzp;  // one x-plane of one component
   TwStage<T, Plan, NT> twst;
   twst.fetch(tid);
-  // load: the retained rows, zeros elsewhere.  A fixed count per thread (at
-  // the widest Mz), every lane loading from a valid address and selecting
-  // afterwards, so that all of a thread's loads are in flight together
-  // instead of one HBM latency per element.
-  // Element e = tid + i NT of [6][N][Mz] sits in row e / Mz at kz = e % Mz;
-  // both follow from the previous element by the constant step NT = sq Mz +
-  // sr, so one division per thread replaces two per element.
-  constexpr int LD = (6 * N * S::MZ + NT - 1) / NT;
-  const int sq = NT / Mz, sr = NT - sq * Mz;
-  cx<T> ld[LD];
-  int at[LD];
+  // load: the retained rows of the six components into their rows of P.  A
+  // thread keeps one kz and walks the (component, compact row) pairs a
+  // block-size step apart, twelve loads in flight at a time; the rows of P
+  // outside the retained set are never written here, and the y inverse
+  // takes them as zeros.
   {
-    int row = tid / Mz, kz = tid - (tid / Mz) * Mz;
-    static_for<0, LD>([&](auto i) {
-      const int c = row / N, y = row - (row / N) * N;
-      const bool in = row < 6 * N;
-      const bool kp = in && kept(y, g);
-      const cx<T> v = A[kp ? c * csA + x * plane + (long)crow(y, g) * g.Mzp + kz : 0];
-      ld[i] = kp ? v : cx<T>{T(0), T(0)};
-      at[i] = in ? c * (int)cs + y * Ps + kz : -1;
-      kz += sr;
-      row += sq;
-      if (kz >= Mz) {
-        kz -= Mz;
-        ++row;
-      }
-    });
+    constexpr int B = 12;
+    const int q = NT / Mz;  // rows one pass of the block covers
+    const int kz = tid - (tid / Mz) * Mz;
+    const int rho = tid / Mz;
+    const int qc = q / M, qm = q - (q / M) * M;
+    int c = rho / M, ky = rho - (rho / M) * M;
+    for (int r0 = rho; rho < q && r0 < 6 * M; r0 += B * q) {
+      cx<T> ld[B];
+      int at[B];
+      static_for<0, B>([&](auto i) {
+        const bool in = c < 6;
+        ld[i] = A[in ? c * csA + x * plane + (long)ky * g.Mzp + kz : 0];
+        at[i] = in ? c * (int)cs + cpos(ky, g) * Ps + kz : -1;
+        ky += qm;
+        c += qc;
+        if (ky >= M) {
+          ky -= M;
+          ++c;
+        }
+      });
+      static_for<0, B>([&](auto i) {
+        if (at[i] >= 0) P[at[i]] = ld[i];
+      });
+    }
   }
-  static_for<0, LD>([&](auto i) {
-    if (at[i] >= 0) P[at[i]] = ld[i];
-  });
   twst.put(tws, tid);
   __syncthreads();
   const TwTab<T> tw{tws};
@@ -119,7 +119,11 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
       const int c = id / Mz, kz = id - c * Mz;
       LdsColumn<T> col{P + c * cs + kz, Ps};
       cx<T> v[R];
-      static_for<0, R>([&](auto s) { v[s] = col.get(j + s * Tl); });
+      static_for<0, R>([&](auto s) {
+        const int p = j + s * Tl;
+        const cx<T> t = col.get(p);  // rows outside the retained set hold no data
+        v[s] = kept(p, g) ? t : cx<T>{T(0), T(0)};
+      });
       col.sync();
       Plan::template fft<T, +1>(v, j, col, tw);
       static_for<0, R>([&](auto s) { col.put(j + s * Tl, v[s]); });
@@ -189,6 +193,7 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
   // store the retained rows of components 0..2 ([3][M][Mz], stepped as the
   // load)
   {
+    const int sq = NT / Mz, sr = NT - (NT / Mz) * Mz;
     int kz = tid - (tid / Mz) * Mz, ky = tid / Mz, c = ky / M;
     ky -= c * M;
     while (c < 3) {
