@@ -329,6 +329,8 @@ struct LinePlan {
   // padding slot every 2^SH positions below).
   static constexpr int SH = ilog2<FirstOf<Rs...>::value>();
   static constexpr int line_slots = SH >= 4 ? N_ : N_ + (N_ >> SH) + 1;
+  // distance between the LDS regions of two lines held by one wave
+  static constexpr int line_stride = line_slots;
   template <typename T>
   static constexpr StageTw<T, N_> twiddles() {
     return make_stage_tw<T, N_, Rs...>();
@@ -337,6 +339,14 @@ struct LinePlan {
   __device__ __forceinline__ static void fft(cx<T>* v, int j, L& lds, const TW& tw) {
     Stages<T, DIR, N_, R_, 1, 0, Rs...>::run(v, j, lds, tw);
   }
+};
+
+// A plan whose lines sit S slots apart in LDS instead of line_slots, so that
+// the lines of one wave fall on different LDS banks.
+template <class Plan, int S>
+struct StridedLines : Plan {
+  static_assert(S >= Plan::line_slots, "lines would overlap");
+  static constexpr int line_stride = S;
 };
 
 // Stage-major twiddles of a plan, in device memory.

@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "yz_fused.hpp"
 
@@ -37,6 +39,25 @@ template <int N>
 struct LPz {
   using P = typename LP<N>::P;
 };
+// FP32 z lines of the short lengths: LDS slots per line picked with a model of
+// the 64 four-byte LDS banks (8-byte accesses served 32 lanes at a time) so
+// that the lines of a wave fall on different banks in the z pass's exchanges
+// (Stockham stages, Hermitian completion and split): the summed conflict
+// degree drops from 1935 / 108 / 213 / 147 / 109 / 333 / 291 / 227 to
+// 0 / 72 / 9 / 4 / 105 / 21 / 168 / 11 at N = 16 / 18 / 24 / 32 / 36 / 48 / 54 / 64
+// (zline_banks.py).
+template <int N>
+struct LPz32 {
+  using P = typename LPz<N>::P;
+};
+template <> struct LPz32<16> { using P = StridedLines<LP<16>::P, 17>; };
+template <> struct LPz32<18> { using P = StridedLines<LP<18>::P, 35>; };
+template <> struct LPz32<24> { using P = StridedLines<LP<24>::P, 34>; };
+template <> struct LPz32<32> { using P = StridedLines<LP<32>::P, 44>; };
+template <> struct LPz32<36> { using P = StridedLines<LP<36>::P, 58>; };
+template <> struct LPz32<48> { using P = StridedLines<LP<48>::P, 68>; };
+template <> struct LPz32<54> { using P = StridedLines<LP<54>::P, 70>; };
+template <> struct LPz32<64> { using P = StridedLines<LP<64>::P, 88>; };
 
 // Columns per block of a strided pass: at least one 128-byte segment per row
 // (16 FP32 / 8 FP64 complex values), more while the LDS tile stays within
@@ -172,7 +193,7 @@ struct Impl {
       default: return x_inv_curl_w<W>(s, U, csU, isU, A, csA, isA, nb, g, act);
     }
   }
-  using PZ = typename LPz<N>::P;
+  using PZ = std::conditional_t<std::is_same_v<T, float>, typename LPz32<N>::P, typename LPz<N>::P>;
   static constexpr int lines_per_block() { return ZShape<PZ>::LPB; }
   template <class ZA>
   static hipError_t z_cross_za(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
@@ -202,22 +223,22 @@ struct Impl {
     if (chunk < 1) return hipErrorInvalidValue;
     return z_cross_za(s, A, csA, 0, nlines, 1, g, nullptr, ZBlocked{chunk, 1.0f / (float)chunk, blk});
   }
-  static constexpr bool kYz = N <= 64 && YzShape<T, P>::kFits;
+  static constexpr bool kYz = N <= 64 && YzShape<T, PZ>::kFits;
   static hipError_t yz_fused(hipStream_t s, void* A, long csA, long isA, int nb, const Geo& g, const int* act) {
     if constexpr (kYz) {
       const double n3 = double(N) * N * N;
       const T scale = T(1.0 / (n3 * n3));
-      const size_t lds = (size_t)YzShape<T, P>::lds_bytes(g.Mz);
+      const size_t lds = (size_t)YzShape<T, PZ>::lds_bytes(g.Mz);
       const dim3 grid((unsigned)N, (unsigned)nb);
-      constexpr int KL23 = z_loads<P>((N - 1) / 3 + 1), KLall = z_loads<P>(N / 2);
-      if (g.Mz <= KL23 * P::Tl) {
-        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, P, KL23>,
+      constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
+      if (g.Mz <= KL23 * PZ::Tl) {
+        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KL23>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_yz_fused<T, P, KL23>), grid, dim3(YzShape<T, P>::NT), lds, s, (cx<T>*)A, csA, isA, g, scale, act);
-      } else if (g.Mz <= KLall * P::Tl) {
-        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, P, KLall>,
+        hipLaunchKernelGGL((k_yz_fused<T, PZ, KL23>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA, isA, g, scale, act);
+      } else if (g.Mz <= KLall * PZ::Tl) {
+        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KLall>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_yz_fused<T, P, KLall>), grid, dim3(YzShape<T, P>::NT), lds, s, (cx<T>*)A, csA, isA, g, scale, act);
+        hipLaunchKernelGGL((k_yz_fused<T, PZ, KLall>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA, isA, g, scale, act);
       } else {
         return hipErrorInvalidValue;
       }

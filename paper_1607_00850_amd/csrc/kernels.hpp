@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   if (act && !act[blockIdx.y]) return;  // instance no longer iterating
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
-  constexpr int LS = Plan::line_slots;
+  constexpr int LS = Plan::line_stride;
   __shared__ cx<T> sm[ZShape<Plan>::SLOTS * LS];
   __shared__ cx<T> tws[N];
   TwStage<T, Plan, 256> twst;
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(256) void k_z_c2r(const cx<T>* __restrict__ in, T* 
                                                Geo g, T scale) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, KL = z_loads<Plan>();
   constexpr int LPB = ZShape<Plan>::LPB;
-  constexpr int LS = Plan::line_slots;
+  constexpr int LS = Plan::line_stride;
   __shared__ cx<T> sm[ZShape<Plan>::SLOTS * LS];
   __shared__ cx<T> tws[N];
   stage_twiddles<T, Plan>(tws);
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(256) void k_z_r2c(const T* __restrict__ in, cx<T>* 
                                                Geo g) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
-  constexpr int LS = Plan::line_slots;
+  constexpr int LS = Plan::line_stride;
   __shared__ cx<T> sm[ZShape<Plan>::SLOTS * LS];
   __shared__ cx<T> tws[N];
   stage_twiddles<T, Plan>(tws);

@@ -46,7 +46,7 @@ struct YzShape {
   static constexpr int MZ = (N - 1) / 3 + 1 > N / 2 ? (N - 1) / 3 + 1 : N / 2;  // widest Mz (no dealiasing)
   static constexpr int pitch(int Mz) { return Mz | 1; }
   static constexpr long lds_bytes(int Mz) {
-    return (long)sizeof(cx<T>) * (6L * N * pitch(Mz) + (long)ZL * Plan::line_slots + N);
+    return (long)sizeof(cx<T>) * (6L * N * pitch(Mz) + (long)ZL * Plan::line_stride + N);
   }
   // the fused pass exists when a line sits in one wave and the widest
   // retained z extent fits
@@ -57,7 +57,7 @@ template <typename T, class Plan, int KL>
 __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __restrict__ A, long csA, long isA, Geo g, T scale,
                                                   const int* __restrict__ act) {
   using S = YzShape<T, Plan>;
-  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, LS = Plan::line_slots;
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, LS = Plan::line_stride;
   if (act && !act[blockIdx.y]) return;  // instance no longer iterating
   extern __shared__ unsigned char smem_raw[];
   cx<T>* sm = reinterpret_cast<cx<T>*>(smem_raw);
