@@ -285,7 +285,7 @@ struct Impl {
   }
   static hipError_t gather(hipStream_t s, const void* in0, const void* const* in_tab, void* out, long C, long is,
                            int nb, const Geo& g) {
-    const unsigned grid = grid_1d(3 * C, 256);
+    const unsigned grid = grid_1d((3 * C + 3) / 4, 256);  // a few elements per thread
     hipLaunchKernelGGL((k_gather<T>), dim3(grid, (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in0,
                        (const cx<T>* const*)in_tab, (cx<T>*)out, C, is, g, pos4_of(256L * grid, g.M, g.M, g.Mzp));
     return hipGetLastError();
@@ -293,7 +293,7 @@ struct Impl {
   static hipError_t scatter(hipStream_t s, const void* in, void* out0, void* const* out_tab, long C, long is, int nb,
                             const Geo& g) {
     const long total = 3L * g.N * g.N * g.czp;
-    const unsigned grid = grid_1d(total, 256);
+    const unsigned grid = grid_1d((total + 3) / 4, 256);  // a few elements per thread
     hipLaunchKernelGGL((k_scatter<T>), dim3(grid, (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in,
                        (cx<T>*)out0, (cx<T>* const*)out_tab, C, is, g, pos4_of(256L * grid, g.N, g.N, g.czp));
     return hipGetLastError();
