@@ -174,15 +174,22 @@ struct Impl {
                                    cs_out, ncomp, is_in, is_out, nb, g, act);
     }
   }
+  // short FP32 lines: all six outputs of a tile in one block (k_x_inv_curl6)
+  static constexpr bool kCurl6 = std::is_same_v<T, float> && N <= 64;
   template <int WW>
   static hipError_t x_inv_curl_w(hipStream_t s, const void* U, long csU, long isU, void* A, long csA, long isA,
                                  int nb, const Geo& g, const int* act) {
     const long Q = (long)g.M * g.Mzp;
     const int ntiles = (int)((Q + WW - 1) / WW);
     constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
-    const unsigned nblk = 8u * 6u * (unsigned)((ntiles + 8 * pair - 1) / (8 * pair) * pair);
-    hipLaunchKernelGGL((k_x_inv_curl<T, P, WW>), dim3(nblk, (unsigned)nb), dim3(WW * Tl), 0, s, (const cx<T>*)U, csU,
-                       isU, (cx<T>*)A, csA, isA, ntiles, g, act);
+    const unsigned ngrp = (unsigned)((ntiles + 8 * pair - 1) / (8 * pair) * pair);
+    if constexpr (kCurl6) {
+      hipLaunchKernelGGL((k_x_inv_curl6<T, P, WW>), dim3(8u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
+                         (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
+    } else {
+      hipLaunchKernelGGL((k_x_inv_curl<T, P, WW>), dim3(8u * 6u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
+                         (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
+    }
     return hipGetLastError();
   }
   static hipError_t x_inv_curl(hipStream_t s, int variant, const void* U, long csU, long isU, void* A, long csA,

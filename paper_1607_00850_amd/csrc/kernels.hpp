@@ -306,6 +306,71 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
   }
 }
 
+// P1 for short lines: one block computes all six outputs of a tile (u_c, then
+// w_c = i (k x u)_c) from a single load of the three velocity components,
+// transforming them one after another through the same LDS tile.  Six times
+// fewer blocks than k_x_inv_curl and three component loads per tile instead
+// of nine.  No barrier is needed between two transforms: every exchange ends
+// with one after its reads, and the last stage works in registers.
+template <typename T, class Plan, int W>
+__global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __restrict__ U, long csU, long isU,
+                                                             cx<T>* __restrict__ A, long csA, long isA,
+                                                             int ntiles, Geo g, const int* __restrict__ act) {
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+  __shared__ cx<T> sm[N * W];
+  __shared__ cx<T> tws[N];
+  const int blk = blockIdx.x;
+  const int xcd = blk & 7, rest = blk >> 3;
+  const int tile = ((rest / PAIR) * 8 + xcd) * PAIR + rest % PAIR;
+  if (tile >= ntiles) return;           // whole block leaves together
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
+  const int tid = threadIdx.x;
+  TwStage<T, Plan, W * Tl> tw;  // to LDS, ordered before use by the first exchange barrier
+  tw.fetch(tid);
+  const int c = tid % W, j = tid / W;
+  const long Q = (long)g.M * g.Mzp;
+  const long q = (long)tile * W + c;
+  const int iy = (int)(q / g.Mzp);
+  const int kz = (int)(q - (long)iy * g.Mzp);
+  const bool valid = q < Q && kz < g.Mz;
+  const T ky = T(kwave(cpos(valid ? iy : 0, g), N));
+  const T kzf = T(kz + g.kz0);
+  const long qq = valid ? q : 0;
+  U += blockIdx.y * isU;
+  A += blockIdx.y * isA;
+  cx<T> u[3][R];
+  static_for<0, 3>([&](auto comp) {
+    static_for<0, R>([&](auto s) {
+      const int p = j + s * Tl;
+      const bool kp = valid && kept(p, g);
+      const cx<T> x = U[comp * csU + qq + (kp ? (long)crow(p, g) * Q : 0)];
+      u[comp][s] = kp ? x : cx<T>{T(0), T(0)};
+    });
+  });
+  tw.put(tws, tid);
+  LdsCols<T, N, W> lds{sm, c};
+  static_for<0, 6>([&](auto o) {
+    cx<T> v[R];
+    static_for<0, R>([&](auto s) {
+      if constexpr (o < 3) {
+        v[s] = u[o][s];
+      } else {
+        const T kx = T(kwave(j + s * Tl, N));
+        // w_x = i (ky u_z - kz u_y), w_y = i (kz u_x - kx u_z), w_z = i (kx u_y - ky u_x)
+        if constexpr (o == 3) v[s] = mul_i(u[2][s] * ky - u[1][s] * kzf);
+        else if constexpr (o == 4) v[s] = mul_i(u[0][s] * kzf - u[2][s] * kx);
+        else v[s] = mul_i(u[1][s] * kx - u[0][s] * ky);
+      }
+    });
+    Plan::template fft<T, +1>(v, j, lds, TwTab<T>{tws});
+    if (valid) {
+      cx<T>* dst = A + o * csA + q;
+      static_for<0, R>([&](auto s) { store_out<PAIR == 1>(dst + (long)(j + s * Tl) * Q, v[s]); });
+    }
+  });
+}
+
 // ---------------------------------------------------------------------------
 // z-axis lines.  A group of Tl = N/R lanes owns one line (see ZShape).
 // ---------------------------------------------------------------------------
