@@ -228,7 +228,7 @@ def bench_batch(a):
     from paper_1607_00850_amd import binding, inputs
 
     sizes = inputs.batch_sizes(a.batch, 0)
-    cpu = None if a.no_cpu_baseline else batch_cpu_baseline(sizes)
+    cpu = None if (a.no_cpu_baseline or a.replays_only) else batch_cpu_baseline(sizes)
     t_gen = time.perf_counter()
     ins, outs, keep = batch_fields(sizes, a.dtype)
     t_gen = time.perf_counter() - t_gen
@@ -236,6 +236,27 @@ def bench_batch(a):
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
     res = {}
+    if a.replays_only:
+        # for kernel traces of the graph alone: tune, capture, pause half a
+        # second (it marks the start of the replays in a trace), replay
+        try:
+            with torch.cuda.stream(s):
+                binding.hot_tune(plan, ws, s)
+                g = binding.hot_graph_create(plan, ins, outs, ws, 1, s)
+                binding.hot_graph_launch(g, s)
+                torch.cuda.synchronize()
+                time.sleep(0.5)
+                t0 = time.perf_counter()
+                for _ in range(a.replays_only):
+                    binding.hot_graph_launch(g, s)
+                torch.cuda.synchronize()
+                t = (time.perf_counter() - t0) / a.replays_only
+                binding.hot_graph_destroy(g)
+        finally:
+            binding.hot_destroy(plan)
+        print(json.dumps({"replays": a.replays_only, "ms_per_replay": t * 1e3, "instances_per_sec": len(sizes) / t}),
+              flush=True)
+        return None
     try:
         with torch.cuda.stream(s):
             binding.hot_tune(plan, ws, s)
@@ -805,6 +826,9 @@ def main():
     ap.add_argument("--ranks", type=int, default=8, help="slab: shares of the field")
     ap.add_argument("--rank", type=int, default=0, help="slab: the share timed")
     ap.add_argument("--batch", type=int, default=4096, help="instances of the batch workload")
+    ap.add_argument("--replays-only", type=int, default=0, metavar="K",
+                    help="batch: tune, capture, pause 0.5 s, replay the graph K times and print only that "
+                         "(for kernel traces of the replays)")
     a = ap.parse_args()
     global GEN_WORKERS
     GEN_WORKERS = a.gen_workers
