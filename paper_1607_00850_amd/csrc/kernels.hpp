@@ -404,13 +404,23 @@ __device__ __forceinline__ void put_completed(L& lds, const cx<T> (&la)[KL], con
   });
 }
 
-template <typename T, class Plan, class L>
+// With at most KL coefficients per lane (Mz <= KL Tl), the registers s whose
+// positions j + s Tl lie in [KL Tl, N - KL Tl] for every lane are zero
+// without a read; the others read their position (inside the line's region)
+// and keep it where a coefficient reaches.
+template <typename T, class Plan, int KL = Plan::R, class L>
 __device__ __forceinline__ void read_completed(const L& lds, cx<T>* v, int j, int Mz) {
   constexpr int N = Plan::N, Tl = Plan::Tl;
   static_for<0, Plan::R>([&](auto s) {
-    const int p = j + s * Tl;
-    const bool live = (p < Mz) || (N - p < Mz);
-    v[s] = live ? lds.get(p) : cx<T>{T(0), T(0)};
+    constexpr bool dead = s * Tl >= KL * Tl && (s + 1) * Tl - 1 <= N - KL * Tl;
+    if constexpr (dead) {
+      v[s] = cx<T>{T(0), T(0)};
+    } else {
+      const int p = j + s * Tl;
+      const bool live = (p < Mz) || (N - p < Mz);
+      const cx<T> t = lds.get(p);
+      v[s] = live ? t : cx<T>{T(0), T(0)};
+    }
   });
 }
 
@@ -487,7 +497,7 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   static_for<0, 3>([&](auto pr) {
     put_completed<T, Plan, KL>(lds, la, lb, j, Mz);
     lds.sync();
-    read_completed<T, Plan>(lds, ph[pr], j, Mz);
+    read_completed<T, Plan, KL>(lds, ph[pr], j, Mz);
     lds.sync();
     if constexpr (pr < 2) {
       load_line<T, Plan, KL>(la, A + (2 * pr + 2) * csA + base, j, Mz, valid, za);

@@ -146,7 +146,7 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
         });
         put_completed<T, Plan, KL>(lds, la, lb, j, Mz);
         lds.sync();
-        read_completed<T, Plan>(lds, ph[pr], j, Mz);
+        read_completed<T, Plan, KL>(lds, ph[pr], j, Mz);
         lds.sync();
         Plan::template fft<T, +1>(ph[pr], j, lds, tw);
       });
