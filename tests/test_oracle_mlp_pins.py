@@ -111,3 +111,87 @@ def test_zero_network_predicts_the_extrapolation():
     p = oracle.surrogate_predict(theta, u, d1, d2, 0.01, 0.01)
     M = oracle.retained_mask(N)
     np.testing.assert_allclose(p, (2 * d1 - d2) * M, rtol=0, atol=1e-12 * np.abs(d1).max())
+
+
+def _row_of(N, kidx):
+    """Row of the retained mode at canonical index kidx in the oracle's order."""
+    rows = np.nonzero(oracle.retained_mask(N))
+    hits = [i for i in range(len(rows[0])) if (rows[0][i], rows[1][i], rows[2][i]) == kidx]
+    assert len(hits) == 1
+    return hits[0]
+
+
+def _two_mode_fields(N):
+    """Hand-made increments on two retained modes, with values chosen so that
+    every quantity below is exact in binary: mode A = (2, -1, 1) with
+    s = ||d1_A|| = 2, mode B = (-3, 0, 2) with s = ||d1_B|| = 0.5."""
+    z = np.zeros((3, N, N, N // 2 + 1), complex)
+    d, d1, d2 = z.copy(), z.copy(), z.copy()
+    A, B = (2, N - 1, 1), (N - 3, 0, 2)
+    d1[(slice(None),) + A] = [1.2j, 0, 1.6]     # s_A = 2
+    d2[(slice(None),) + A] = [0.5, 0.25j, 0]
+    d[(slice(None),) + A] = [1 + 3j, -0.5, 2.5j]
+    d1[(slice(None),) + B] = [0, 0.3, -0.4j]    # s_B = 0.5
+    d2[(slice(None),) + B] = [0, 0, 0.75]
+    d[(slice(None),) + B] = [0.125j, 0.5, -1]
+    return d, d1, d2, A, B
+
+
+def test_target_by_hand_on_two_modes():
+    # Sec. 2 leaves the integrator open; the surrogate's target is the error
+    # of the plain extrapolation 2 d1 - d2 in units of s = ||d1_k||.  Hand
+    # values: t = (d - 2 d1 + d2) / s per (re, im) of x, y, z.
+    N = 16
+    d, d1, d2, A, B = _two_mode_fields(N)
+    _, s = oracle.surrogate_features(np.zeros_like(d), d1, d2, 0.01, 0.01)
+    t = oracle.surrogate_target(d, d1, d2, s)
+    rA, rB = _row_of(N, A), _row_of(N, B)
+    assert s[rA] == 2.0 and s[rB] == 0.5
+    # mode A: d - 2 d1 + d2 = (1.5 + 0.6j, -0.5 + 0.25j, -3.2 + 2.5j), over 2
+    np.testing.assert_allclose(t[rA], [0.75, 0.3, -0.25, 0.125, -1.6, 1.25], rtol=0, atol=1e-15)
+    # mode B: d - 2 d1 + d2 = (0.125j, -0.1, -0.25 + 0.8j), over 0.5
+    np.testing.assert_allclose(t[rB], [0, 0.25, -0.2, 0, -0.5, 1.6], rtol=0, atol=1e-15)
+    # every row with s = 0 has target 0 (here: all but A and B, even where d is not 0)
+    others = np.ones(len(s), bool)
+    others[[rA, rB]] = False
+    assert np.all(s[others] == 0) and np.all(t[others] == 0)
+
+
+def test_target_is_zero_where_s_is_zero_even_with_a_nonzero_increment():
+    N = 16
+    d, d1, d2, A, B = _two_mode_fields(N)
+    d[:, 1, 1, 1] = [1, 2j, 3]  # an increment on a mode whose d1 is 0
+    _, s = oracle.surrogate_features(np.zeros_like(d), d1, d2, 0.01, 0.01)
+    t = oracle.surrogate_target(d, d1, d2, s)
+    r = _row_of(N, (1, 1, 1))
+    assert s[r] == 0 and np.all(t[r] == 0)
+
+
+def test_predict_adds_s_times_the_network_output():
+    # zero weights and b4 = c: the network outputs c on every row, so the warm
+    # start must be 2 d1 - d2 + s c on every retained mode (s = ||d1_k||),
+    # which pins both the sign and the scale of the s MLP(f) term.
+    N = 16
+    d, d1, d2, A, B = _two_mode_fields(N)
+    theta = np.zeros(oracle.mlp_param_count())
+    c = np.array([0.5, -1.0, 0.25, 2.0, -0.75, 1.5])
+    theta[-6:] = c
+    p = oracle.surrogate_predict(theta, np.zeros_like(d), d1, d2, 0.01, 0.01)
+    cc = c[0::2] + 1j * c[1::2]  # per component x, y, z
+    want = (2 * d1 - d2).copy()
+    want[(slice(None),) + A] += 2.0 * cc
+    want[(slice(None),) + B] += 0.5 * cc
+    np.testing.assert_allclose(p, want * oracle.retained_mask(N), rtol=0, atol=1e-15)
+
+
+def test_target_and_predict_close_the_loop():
+    # a network that outputs exactly the target reproduces the true increment:
+    # predict(b4 = t_A) at mode A equals d at mode A
+    N = 16
+    d, d1, d2, A, B = _two_mode_fields(N)
+    _, s = oracle.surrogate_features(np.zeros_like(d), d1, d2, 0.01, 0.01)
+    t = oracle.surrogate_target(d, d1, d2, s)
+    theta = np.zeros(oracle.mlp_param_count())
+    theta[-6:] = t[_row_of(N, A)]
+    p = oracle.surrogate_predict(theta, np.zeros_like(d), d1, d2, 0.01, 0.01)
+    np.testing.assert_allclose(p[(slice(None),) + A], d[(slice(None),) + A], rtol=0, atol=1e-14)
