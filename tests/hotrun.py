@@ -3,6 +3,9 @@
 Only marshalling lives here: numpy arrays go to device tensors, the C ABI is
 called, results come back to numpy.
 """
+import json
+import os
+
 import numpy as np
 
 from paper_1607_00850_amd import binding
@@ -66,12 +69,27 @@ def run(op, arrays, dtype="f64", dealias="two_thirds", nu=0.0, dt=0.0, nsteps=0,
 def rel_l2(a, b):
     a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) or np.iscomplexobj(b) else np.float64)
     den = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a))
+    return note(float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a)))
+
+
+def note(err):
+    """Record an observed relative error under the running test's id when
+    HOT_ERRLOG names a file (the per-family error tables); returns err."""
+    log = os.environ.get("HOT_ERRLOG")
+    if log:
+        with open(log, "a") as f:
+            f.write(json.dumps({"test": os.environ.get("PYTEST_CURRENT_TEST", "?"), "err": float(err)}) + "\n")
+    return err
+
+
+# unit roundoff of FP32 (round to nearest): 2^-24
+U32 = 2.0**-24
 
 
 def fp32_tol(N, C=10.0):
-    """Tolerance for the FP32 path: C * eps32 * log2(N^3)."""
-    return C * float(np.finfo(np.float32).eps) * np.log2(float(N) ** 3)
+    """Tolerance for the FP32 path: C * u32 * log2(N^3), u32 = 2^-24 the unit
+    roundoff (1.07e-5 at N = 64, 1.79e-5 at N = 1024)."""
+    return C * U32 * np.log2(float(N) ** 3)
 
 
 def round32(x):
@@ -95,6 +113,8 @@ def run_implicit(arrays, dtype="f64", nu=0.0, dt=1e-3, nsteps=1, tol=1e-10, max_
         rc = binding.hot_run(h, ins, outs, ws, nsteps)
         torch.cuda.synchronize()
         sweeps, nonconv = binding.hot_implicit_stats(h, len(arrays))
+        if rc == binding.HOT_OK and any(nonconv):
+            rc = binding.HOT_E_NOCONVERGE  # as hot_implicit_stats reports it
         return [o.cpu().numpy() for o in outs], sweeps, nonconv, rc
     finally:
         binding.hot_destroy(h)

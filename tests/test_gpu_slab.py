@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 from paper_1607_00850_amd import binding, inputs, slab
-from hotrun import CDT, fp32_tol, rel_l2, round32, run
+from hotrun import CDT, fp32_tol, note, rel_l2, round32, run
 
 pytestmark = pytest.mark.gpu
 
@@ -208,7 +208,7 @@ def test_share_0_of_8_at_2048_rhs_fp32_matches_oracle_at_64():
         assert int(idx[0].numel()) > 100
         err = float(torch.linalg.vector_norm(y - exp) / torch.linalg.vector_norm(exp))
         print(f"rel L2 {err:.3e}", flush=True)
-        assert err < fp32_tol(N)
+        assert note(err) < fp32_tol(N)
     finally:
         binding.hot_destroy(h)
 
@@ -275,6 +275,6 @@ def test_share_0_of_8_at_2048_sparse_rhs_fp32_matches_triad_oracle():
         exp = dense(kout, ref)
         err = float(torch.linalg.vector_norm(y - exp) / torch.linalg.vector_norm(exp))
         print(f"rel L2 {err:.3e} over {len(kout)} modes", flush=True)
-        assert err < fp32_tol(N)
+        assert note(err) < fp32_tol(N)
     finally:
         binding.hot_destroy(h)
