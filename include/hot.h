@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define HOT_ABI_VERSION 2
+#define HOT_ABI_VERSION 3
 
 /* Return codes. */
 #define HOT_OK 0
@@ -45,7 +45,8 @@ extern "C" {
 #define HOT_E_WORKSPACE (-3)   /* workspace pointer null or misaligned */
 #define HOT_E_HIP (-4)         /* a HIP call failed; hot_last_hip_error() has the code */
 #define HOT_E_NONFINITE (-5)   /* HOT_FLAG_CHECK_FINITE: a result holds a NaN or an infinity */
-#define HOT_E_NOCONVERGE (-6)  /* IMPLICIT: an instance hit max_iter sweeps (its last iterate is kept) */
+#define HOT_E_NOCONVERGE (-6)  /* IMPLICIT: an instance hit max_iter sweeps (its last iterate is kept);
+                                  reported by hot_implicit_stats, and by hot_run for CHECK_FINITE plans */
 
 /* Element type. */
 #define HOT_F64 0
@@ -81,9 +82,10 @@ extern "C" {
  *       extrapolation 2 d^{n-1} - d^{n-2} after that (or the surrogate's
  *       warm start, see hot_set_surrogate; with HOT_FLAG_KEEP_HISTORY the
  *       history carries over from the previous call).  Each instance stops on
- *       its own.  The call synchronises the stream once per sweep (to read
- *       the stopping flags); it cannot be captured in a graph.  in == out
- *       allowed. */
+ *       its own: every step enqueues max_iter sweeps, whose kernels return at
+ *       once for an instance that has stopped, so the host never waits for
+ *       the stopping test.  The sweep counts stay on the device (hot_stats,
+ *       hot_implicit_stats).  in == out allowed. */
 #define HOT_OP_R2C 0
 #define HOT_OP_C2R 1
 #define HOT_OP_RHS 2
@@ -119,6 +121,23 @@ typedef struct hot_desc {
 
 typedef struct hot_plan_s* hot_plan_t;
 
+/* Per-instance statistics of a hot_run call (RHS, RK4, IMPLICIT), written
+ * on the stream into a caller's device array [batch] (stats_dev):
+ *   energy       E = (1/2N^6) sum_k |u_k|^2, the kinetic energy by Parseval
+ *                under Eq. ffteq, of the state (the RHS input, the RK4 and
+ *                IMPLICIT result; sums over the full spectrum, FP64);
+ *   dissipation  eps = nu (1/N^6) sum_k |k|^2 |u_k|^2 = nu <|w|^2> of it,
+ *                the rate at which the viscous term of Eq. NSfinal removes
+ *                energy;
+ *   sweeps       IMPLICIT: Picard sweeps summed over the call's steps;
+ *   nonconv      IMPLICIT: steps that stopped at max_iter (0 for the others). */
+typedef struct hot_stats {
+  double energy;
+  double dissipation;
+  int32_t sweeps;
+  int32_t nonconv;
+} hot_stats;
+
 /* Supported sizes: N in {8, 16, 18, 24, 32, 36, 48, 54, 64, 128, 256, 512, 1024}. */
 
 /* Validate d, build a plan and report the workspace size in bytes.
@@ -127,38 +146,42 @@ typedef struct hot_plan_s* hot_plan_t;
 int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes);
 
 /* Enqueue the planned operation on stream (a hipStream_t; NULL = default).
+ * The call never synchronises (a CHECK_FINITE plan excepted).
  * in[i], out[i]: device pointers of instance i (layouts above; R2C reads
  * physical and writes spectral, C2R the reverse, RHS/RK4/IMPLICIT spectral
  * both).  Instances must not overlap each other (in[i] == out[i] is allowed).
  * workspace: device buffer of at least the planned size.  nsteps: RK4 or
- * IMPLICIT steps (>= 0; ignored by other ops).  Asynchronous except for
- * IMPLICIT (see HOT_OP_IMPLICIT); inputs must stay valid until the stream
- * reaches the end of the call.
+ * IMPLICIT steps (>= 0; ignored by other ops).  stats_dev: NULL, or a
+ * device array of batch hot_stats records (8-byte aligned; RHS, RK4 and
+ * IMPLICIT only) filled on the stream at the end of the call.  Inputs must
+ * stay valid until the stream reaches the end of the call.
  * Batches: for RHS, RK4 and IMPLICIT, instances of equal N run together, each pass as
  * one launch over all of them (the instance is a grid dimension).  The
- * device tables of their in/out pointers live in the workspace: hot_run
- * uploads them, and synchronises the stream, only when the pointers or the
- * workspace differ from the previous call's; calls with the same pointers
- * only enqueue kernels.
- * Errors: HOT_E_INVALID (null plan/pointer, nsteps < 0), HOT_E_WORKSPACE,
- * HOT_E_HIP (launch failure; the plan keeps the HIP error code),
- * HOT_E_NOCONVERGE (IMPLICIT only: the whole call ran, some step of some
- * instance stopped at max_iter; hot_implicit_stats says which),
- * HOT_E_NONFINITE (HOT_FLAG_CHECK_FINITE: the whole call ran and a result
- * holds a NaN or an infinity; takes precedence over HOT_E_NOCONVERGE). */
-int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps, void* stream);
+ * device tables of their in/out pointers live in the workspace; every call
+ * writes them on the stream with a small kernel whose arguments carry the
+ * pointers (no host synchronisation).
+ * Errors: HOT_E_INVALID (null plan/pointer, nsteps < 0, stats_dev for
+ * R2C/C2R or misaligned), HOT_E_WORKSPACE, HOT_E_HIP (launch failure; the
+ * plan keeps the HIP error code).  A CHECK_FINITE plan, which synchronises,
+ * also returns HOT_E_NONFINITE (the whole call ran and a result holds a NaN
+ * or an infinity) or, for IMPLICIT, HOT_E_NOCONVERGE (some step of some
+ * instance stopped at max_iter), the first taking precedence. */
+int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps, void* stats_dev,
+            void* stream);
 
 /* A captured hot_run: the whole operation (every pass of every instance and
  * step) recorded once into a HIP graph and replayed with one launch.
  * hot_graph_create captures on stream, which must not be the legacy default
- * stream (NULL); the pointer tables are uploaded first, outside the capture.
- * The graph keeps the pointers it was created with.  Per-pass profiling is
+ * stream (NULL).  stats_dev: NULL or as for hot_run.  The graph keeps the
+ * pointers it was created with: a replay rewrites the pointer tables itself,
+ * so hot_run calls with other arrays on the same workspace between replays
+ * do not change what a replay reads and writes.  Per-pass profiling is
  * not recorded inside graphs.  Errors as hot_run; HOT_E_UNSUPPORTED for
- * IMPLICIT, whose sweep count is decided on the host, and for plans with
- * HOT_FLAG_CHECK_FINITE. */
+ * plans with HOT_FLAG_CHECK_FINITE (it needs the host) or
+ * HOT_FLAG_KEEP_HISTORY (a replay would not continue the history). */
 typedef struct hot_graph_s* hot_graph_t;
 int hot_graph_create(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
-                     void* stream, hot_graph_t* graph);
+                     void* stats_dev, void* stream, hot_graph_t* graph);
 int hot_graph_launch(hot_graph_t graph, void* stream);
 int hot_graph_destroy(hot_graph_t graph);
 
@@ -178,14 +201,18 @@ int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
 
 /* Set what hot_tune would choose, for every size of the plan: for a
  * column-tiled pass the width variant 0 (narrow), 1 (default) or 2 (wide);
- * for x_fwd_rk -1 (separate x_fwd and rk_stage passes), 0 or 1 (fused, narrow
- * or default width).  Host only.  Errors: HOT_E_INVALID. */
+ * for x_fwd_rk -1 (separate x_fwd and rk_stage passes), 0, 1 or 2 (fused,
+ * at half, the default or a quarter of the default width).  Host only.
+ * Errors: HOT_E_INVALID. */
 int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant);
 
-/* IMPLICIT statistics of the plan's last hot_run, per instance i (host
- * arrays of p's batch size, either may be NULL): sweeps[i] = Picard sweeps
- * summed over the call's steps, nonconv[i] = steps that stopped at max_iter.
- * Host only.  Errors: HOT_E_INVALID (null plan, op not IMPLICIT). */
+/* IMPLICIT statistics of the plan's last hot_run (or graph capture), per
+ * instance i (host arrays of p's batch size, either may be NULL): sweeps[i] =
+ * Picard sweeps summed over the call's steps, nonconv[i] = steps that stopped
+ * at max_iter.  Waits for the stream of that call, then copies the counters
+ * from its workspace (a graph replay must have finished before this call).
+ * Returns HOT_OK, or HOT_E_NOCONVERGE when some nonconv[i] > 0.
+ * Errors: HOT_E_INVALID (null plan, op not IMPLICIT), HOT_E_HIP. */
 int hot_implicit_stats(hot_plan_t p, int32_t* sweeps, int32_t* nonconv);
 
 /* ------------------------------------------------------------------------

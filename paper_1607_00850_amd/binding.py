@@ -12,7 +12,7 @@ import os
 
 from .build import LIB
 
-HOT_ABI_VERSION = 2
+HOT_ABI_VERSION = 3
 HOT_OK = 0
 HOT_E_INVALID = -1
 HOT_E_UNSUPPORTED = -2
@@ -91,7 +91,7 @@ def _lib():
         vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
         lib.hot_plan.argtypes = [ctypes.POINTER(HotDesc), ctypes.POINTER(vp), ctypes.POINTER(sz)]
         lib.hot_plan.restype = ctypes.c_int
-        lib.hot_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32, vp]
+        lib.hot_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32, vp, vp]
         lib.hot_run.restype = ctypes.c_int
         lib.hot_destroy.argtypes = [vp]
         lib.hot_destroy.restype = ctypes.c_int
@@ -107,7 +107,8 @@ def _lib():
         lib.hot_pass_name.restype = ctypes.c_char_p
         lib.hot_pass_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
         lib.hot_pass_bytes.restype = ctypes.c_int
-        lib.hot_graph_create.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32, vp, ctypes.POINTER(vp)]
+        lib.hot_graph_create.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32, vp, vp,
+                                         ctypes.POINTER(vp)]
         lib.hot_graph_create.restype = ctypes.c_int
         lib.hot_graph_launch.argtypes = [vp, vp]
         lib.hot_graph_launch.restype = ctypes.c_int
@@ -194,18 +195,20 @@ def _stream(stream):
     return stream.cuda_stream
 
 
-def hot_run(plan, ins, outs, workspace, nsteps=0, stream=None):
+def hot_run(plan, ins, outs, workspace, nsteps=0, stream=None, stats=None):
     """Enqueue the planned op.  ins/outs: sequences of device tensors (or raw
     pointers), one per instance; workspace: device tensor or pointer;
     stream: a torch.cuda.Stream, a raw hipStream_t, or None for torch's
-    current stream.  Returns HOT_OK, HOT_E_NOCONVERGE when an implicit
-    step stopped at max_iter (see hot_implicit_stats), or HOT_E_NONFINITE
-    when a plan with check_finite found a NaN or infinity; raises otherwise."""
+    current stream; stats: None, or a device buffer of batch hot_stats
+    records (24 bytes each, see stats_view).  Returns HOT_OK, or for a plan
+    with check_finite HOT_E_NONFINITE (a NaN or infinity) or
+    HOT_E_NOCONVERGE (an implicit step stopped at max_iter); raises
+    otherwise."""
     stream = _stream(stream)
     n = len(ins)
     pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
     pout = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
-    rc = _lib().hot_run(plan, pin, pout, _ptr(workspace), int(nsteps), stream)
+    rc = _lib().hot_run(plan, pin, pout, _ptr(workspace), int(nsteps), _ptr(stats), stream)
     if rc not in (HOT_OK, HOT_E_NOCONVERGE, HOT_E_NONFINITE):
         raise HotError(rc, "hot_run", _lib().hot_last_hip_error(plan))
     return rc
@@ -262,15 +265,17 @@ def pass_names():
     return names
 
 
-def hot_graph_create(plan, ins, outs, workspace, nsteps=0, stream=None):
+def hot_graph_create(plan, ins, outs, workspace, nsteps=0, stream=None, stats=None):
     """Capture the whole operation into a HIP graph; returns a graph handle.
-    stream must be a non-default stream (torch.cuda.Stream or hipStream_t)."""
+    stream must be a non-default stream (torch.cuda.Stream or hipStream_t);
+    stats as for hot_run."""
     stream = _stream(stream)
     n = len(ins)
     pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
     pout = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
     g = ctypes.c_void_p()
-    rc = _lib().hot_graph_create(plan, pin, pout, _ptr(workspace), int(nsteps), stream, ctypes.byref(g))
+    rc = _lib().hot_graph_create(plan, pin, pout, _ptr(workspace), int(nsteps), _ptr(stats), stream,
+                                 ctypes.byref(g))
     if rc != HOT_OK:
         raise HotError(rc, "hot_graph_create", _lib().hot_last_hip_error(plan))
     return g
@@ -309,13 +314,32 @@ def hot_tuned_width(plan, instance, pass_name):
 
 def hot_implicit_stats(plan, batch):
     """Per instance of the last implicit call: (sweeps summed over its steps,
-    steps that stopped at max_iter), as two lists."""
+    steps that stopped at max_iter), as two lists.  Waits for that call."""
     sw = (ctypes.c_int32 * batch)()
     nc = (ctypes.c_int32 * batch)()
     rc = _lib().hot_implicit_stats(plan, sw, nc)
-    if rc != HOT_OK:
-        raise HotError(rc, "hot_implicit_stats")
+    if rc not in (HOT_OK, HOT_E_NOCONVERGE):
+        raise HotError(rc, "hot_implicit_stats", _lib().hot_last_hip_error(plan))
     return list(sw), list(nc)
+
+
+STATS_BYTES = 24  # sizeof(hot_stats)
+
+
+def stats_buffer(batch):
+    """A device buffer for batch hot_stats records."""
+    import torch
+    return torch.zeros(batch * STATS_BYTES, dtype=torch.uint8, device="cuda")
+
+
+def stats_view(buf):
+    """(energy, dissipation, sweeps, nonconv) per instance of a stats buffer
+    read back to the host (numpy arrays)."""
+    import numpy as np
+    raw = buf.cpu().numpy().view(np.uint8)
+    rec = np.dtype([("energy", "<f8"), ("dissipation", "<f8"), ("sweeps", "<i4"), ("nonconv", "<i4")])
+    r = raw.view(rec)
+    return r["energy"].copy(), r["dissipation"].copy(), r["sweeps"].copy(), r["nonconv"].copy()
 
 
 _KEEP = {}  # plan handle -> packed surrogate tensor the plan points to

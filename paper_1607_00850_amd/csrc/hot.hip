@@ -3,6 +3,7 @@
 // (and, for the surrogate warm start, mlp.hpp).
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -34,12 +35,14 @@ enum Pass : int {
   PASS_IMP_ADVANCE,
   PASS_X_FWD_RK,
   PASS_YZ_FUSED,
+  PASS_TABLES,
+  PASS_STATS,
   NUM_PASSES
 };
 
 static const char* kPassNames[NUM_PASSES] = {
     "gather", "x_inv_curl", "y_inv", "z_cross", "y_fwd", "x_fwd", "rk_stage", "scatter", "z_r2c", "z_c2r", "x_inv",
-    "imp_predict", "imp_update", "imp_decide", "imp_advance", "x_fwd_rk", "yz_fused",
+    "imp_predict", "imp_update", "imp_decide", "imp_advance", "x_fwd_rk", "yz_fused", "tables", "stats",
 };
 
 template <typename T>
@@ -88,6 +91,7 @@ static Geo make_geo(int N, int mode, int elem) {
 }
 
 static const size_t kAlign = 256;
+static const int kStatParts = 64;  // blocks of partial sums per instance (hot_stats)
 static inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // All instances of one N.  For the right-hand side, RK4 and the implicit step
@@ -95,7 +99,10 @@ static inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAl
 // [B][3][C] each, A1 = [B][6][D1], A2 = [B][6][D2], then for B > 1 the device
 // tables of the members' input and output pointers.  The implicit step adds
 // two increment histories H1, H2 = [B][3][C] (its iterate d lives in Acc),
-// the stopping flags act[B] and the partial sums part[B][nparts][2].  Plain
+// the stopping flags act[B], the partial sums part[B][nparts][2] and the
+// per-instance counters cnt[2][B] (sweeps, steps stopped at max_iter).  Every
+// such group also keeps the partial sums of its statistics diag[B][64][2]
+// (hot_stats).  Plain
 // transforms run one instance at a time in a shared region.
 struct Group {
   int N = 0;
@@ -106,7 +113,8 @@ struct Group {
   double lC = 0, lD1 = 0, lD2 = 0;  // live values per component (Mz)
   size_t off = 0;                   // byte offset of the group's region
   size_t oU0 = 0, oU1 = 0, oAcc = 0, oNh = 0, oA1 = 0, oA2 = 0, oTab = 0;
-  size_t oH[2] = {0, 0}, oAct = 0, oPart = 0;  // implicit step only
+  size_t oH[2] = {0, 0}, oAct = 0, oPart = 0, oCnt = 0;  // implicit step only
+  size_t oDiag = 0;                                      // statistics partial sums
   size_t oZ = 0;                              // z-slab share: receive buffer of the all-to-all
   int nparts = 0;                             // blocks of the implicit update
   int rot = 0, hist = 0;                      // implicit step: buffer rotation, history depth
@@ -136,15 +144,14 @@ struct hot_plan_s {
   size_t o_finite = 0;              // HOT_FLAG_CHECK_FINITE: byte offset of the flag in the workspace
   const void* surrogate = nullptr;  // packed MLP for the implicit warm start
   void* hist_ws = nullptr;          // workspace holding the kept history
+  void* cnt_ws = nullptr;           // implicit step: workspace and stream of the last call (its counters)
+  hipStream_t cnt_stream = nullptr;
   size_t elem;  // bytes per complex element
   int batch;
   std::vector<int> n;
   std::vector<Group> groups;
   size_t ws_bytes;
   int last_hip;
-  // device pointer tables: what was last uploaded, and where
-  std::vector<const void*> tab_in, tab_out;
-  void* tab_ws = nullptr;
   // profiling
   bool prof;
   struct Rec {
@@ -205,7 +212,9 @@ static int layout_groups(hot_plan_s* p, int op) {
     G.oA1 = 4 * sC;
     G.oA2 = G.oA1 + align_up(B * 6 * (size_t)G.D1 * e);
     G.oTab = G.oA2 + align_up(B * 6 * (size_t)G.D2 * e);
-    G.bytes = G.oTab + (B > 1 ? align_up(2 * B * sizeof(void*)) : 0);
+    // for B > 1: the in and out pointer tables and the members' instance indices
+    G.oDiag = G.oTab + (B > 1 ? align_up(3 * B * sizeof(void*)) : 0);
+    G.bytes = G.oDiag + align_up(B * (size_t)kStatParts * 2 * sizeof(double));
     if (p->slab) {
       G.oZ = G.bytes;
       G.bytes += align_up(B * 6 * (size_t)G.D2 * e);
@@ -216,7 +225,8 @@ static int layout_groups(hot_plan_s* p, int op) {
       G.oH[1] = G.oH[0] + sC;
       G.oAct = G.oH[1] + sC;
       G.oPart = G.oAct + align_up(B * sizeof(int));
-      G.bytes = G.oPart + align_up(B * (size_t)G.nparts * 2 * sizeof(double));
+      G.oCnt = G.oPart + align_up(B * (size_t)G.nparts * 2 * sizeof(double));
+      G.bytes = G.oCnt + align_up(2 * B * sizeof(int));
     }
     off += G.bytes;
   }
@@ -378,6 +388,8 @@ int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) 
     case PASS_X_FWD_RK: b = p->op == HOT_OP_RK4 ? 3 * D1 + 12 * C : (p->op == HOT_OP_RHS ? 3 * D1 + 6 * C : 0); break;
     // the y and z passes in one: six components of A1 in, three out
     case PASS_YZ_FUSED: b = plain ? 0 : 6 * D1 + 3 * D1; break;
+    case PASS_TABLES: b = 0; break;  // a few pointers per instance
+    case PASS_STATS: b = plain ? 0 : 3 * C; break;  // reads the compact state once
     default: return HOT_E_INVALID;
   }
   *bytes = b * e;
@@ -387,6 +399,10 @@ int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) 
 }  // extern "C"
 
 namespace {
+
+static_assert(sizeof(StatsRec) == sizeof(hot_stats) && offsetof(StatsRec, sweeps) == offsetof(hot_stats, sweeps) &&
+                  offsetof(StatsRec, nonconv) == offsetof(hot_stats, nonconv),
+              "device statistics record must match hot_stats");
 
 struct Runner {
   hot_plan_s* p;
@@ -432,8 +448,11 @@ struct GroupPtrs {
   char* H[2];  // implicit step: increment histories
   int* act;
   double* part;
+  int* cnt;  // implicit step: sweeps[B], then nonconv[B]
+  double* diag;
   const void* const* in_tab;
   void* const* out_tab;
+  const long* idx_tab;  // instance index of each member (B > 1)
 };
 
 GroupPtrs group_ptrs(const Group& G, void* workspace) {
@@ -450,8 +469,11 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
   q.H[1] = base + G.oH[1];
   q.act = (int*)(base + G.oAct);
   q.part = (double*)(base + G.oPart);
+  q.cnt = (int*)(base + G.oCnt);
+  q.diag = (double*)(base + G.oDiag);
   q.in_tab = G.B() > 1 ? (const void* const*)(base + G.oTab) : nullptr;
   q.out_tab = G.B() > 1 ? (void* const*)(base + G.oTab + G.B() * sizeof(void*)) : nullptr;
+  q.idx_tab = G.B() > 1 ? (const long*)(base + G.oTab + 2 * G.B() * sizeof(void*)) : nullptr;
   return q;
 }
 
@@ -539,39 +561,57 @@ void stage_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src
   stage_update(r, G, q, mode, nu, dt);
 }
 
-// Upload the members' input/output pointer tables of every batched group
-// into the workspace when they differ from the last upload (synchronises the
-// stream when it does).
-int ensure_tables(hot_plan_s* p, void* const* in, void* const* out, void* workspace, hipStream_t s) {
-  bool need = false;
-  for (const auto& G : p->groups) need = need || G.B() > 1;
-  if (!need) return HOT_OK;
-  bool same = p->tab_ws == workspace && (int)p->tab_in.size() == p->batch;
-  for (int i = 0; same && i < p->batch; ++i) same = p->tab_in[i] == in[i] && p->tab_out[i] == out[i];
-  if (same) return HOT_OK;
-  for (const auto& G : p->groups) {
-    if (G.B() < 2) continue;
-    std::vector<const void*> host(2 * G.B());
-    for (int m = 0; m < G.B(); ++m) {
-      host[m] = in[G.members[m]];
-      host[G.B() + m] = out[G.members[m]];
-    }
-    char* dst = (char*)workspace + G.off + G.oTab;
-    hipError_t e = hipMemcpyAsync(dst, host.data(), host.size() * sizeof(void*), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      p->last_hip = (int)e;
-      return HOT_E_HIP;
+// Write a batched group's tables of its members' canonical input and output
+// pointers into the workspace, in stream order (k_write_tab).  Every call
+// writes them, so no earlier call, graph or plan sharing the workspace can
+// leave stale pointers behind.
+void write_tables(Runner& r, const Group& G, const GroupPtrs& q, void* const* in, void* const* out) {
+  const int nb = G.B();
+  if (nb < 2) return;
+  for (int side = 0; side < 3; ++side) {
+    // in pointers, out pointers, instance indices (as pointer-sized integers)
+    const void** dst = side == 0 ? (const void**)q.in_tab : (side == 1 ? (const void**)q.out_tab : (const void**)q.idx_tab);
+    for (int m0 = 0; m0 < nb && r.rc == HOT_OK; m0 += kTabChunk) {
+      TabChunk c{};
+      const int n = nb - m0 < kTabChunk ? nb - m0 : kTabChunk;
+      for (int m = 0; m < n; ++m) {
+        const int i = G.members[m0 + m];
+        c.p[m] = side == 0 ? in[i] : (side == 1 ? (const void*)out[i] : (const void*)(intptr_t)i);
+      }
+      r.pass(PASS_TABLES, [&] {
+        hipLaunchKernelGGL(k_write_tab<>, dim3(1), dim3(256), 0, r.s, dst + m0, c, n);
+        return hipGetLastError();
+      });
     }
   }
-  p->tab_in.assign(in, in + p->batch);
-  p->tab_out.assign(out, out + p->batch);
-  p->tab_ws = workspace;
-  return HOT_OK;
 }
 
-int check_run_args(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps) {
+// hot_stats of every instance of a group from its compact state X (and, for
+// the implicit step, its counters), written to stats[instance].
+void state_stats(Runner& r, const hot_plan_s* p, const Group& G, const GroupPtrs& q, const char* X, StatsRec* stats,
+                 bool counters) {
+  const int nb = G.B();
+  r.pass(PASS_STATS, [&] {
+    const dim3 grid((unsigned)kStatParts, (unsigned)nb);
+    if (p->dtype == HOT_F64)
+      hipLaunchKernelGGL(k_state_sums<double>, grid, dim3(256), 0, r.s, (const cx<double>*)X, G.C, 3 * G.C, G.g,
+                         q.diag);
+    else
+      hipLaunchKernelGGL(k_state_sums<float>, grid, dim3(256), 0, r.s, (const cx<float>*)X, G.C, 3 * G.C, G.g,
+                         q.diag);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_state_final<>, dim3(nb), dim3(64), 0, r.s, (const double*)q.diag, kStatParts, G.N, p->nu,
+                       q.idx_tab, (long)G.members[0], counters ? (const int*)q.cnt : nullptr,
+                       counters ? (const int*)q.cnt + nb : nullptr, stats);
+    return hipGetLastError();
+  });
+}
+
+int check_run_args(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
+                   const void* stats) {
   if (!p || !in || !out || nsteps < 0) return HOT_E_INVALID;
+  if (stats && (p->op == HOT_OP_R2C || p->op == HOT_OP_C2R || ((uintptr_t)stats % 8) != 0)) return HOT_E_INVALID;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return HOT_E_WORKSPACE;
   for (int i = 0; i < p->batch; ++i) {
     if (!in[i] || !out[i]) return HOT_E_INVALID;
@@ -582,7 +622,7 @@ int check_run_args(hot_plan_s* p, void* const* in, void* const* out, void* works
 
 // Enqueue the whole operation (the pointer tables are already in place).
 int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t stream,
-            bool record) {
+            bool record, StatsRec* stats) {
   Runner r{p, stream, record};
   const size_t e = p->elem;
   if (p->op == HOT_OP_R2C || p->op == HOT_OP_C2R) {
@@ -630,6 +670,7 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
     const long isU = 3 * G.C;
     const void* in0 = in[G.members[0]];
     void* out0 = out[G.members[0]];
+    write_tables(r, G, q, in, out);
     r.pass(PASS_GATHER, [&] { return o.gather(r.s, in0, q.in_tab, q.U0, G.C, isU, nb, g); });
     if (p->op == HOT_OP_RHS) {
       stage_passes(r, G, q, q.U0, 4, p->nu, p->dt);
@@ -639,23 +680,23 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
         for (int st = 0; st < 4; ++st) stage_passes(r, G, q, st == 0 ? q.U0 : q.U1, st, p->nu, p->dt);
       r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.U0, out0, q.out_tab, G.C, isU, nb, g); });
     }
+    // the state: the input of a right-hand side, the result of RK4 steps
+    if (stats) state_stats(r, p, G, q, q.U0, stats, false);
   }
   return r.rc;
 }
 
 // The implicit step, group by group and step by step.  Each step: the
-// predictor, then Picard sweeps (the right-hand-side passes on the midpoint,
-// the update of d, the stopping test) until every instance of the group has
-// stopped or max_iter sweeps have run.  The stopping flags come back to the
-// host after every sweep; instances that stopped skip the later sweeps.
-// The iterate d lives in Acc and the two increment histories in H1, H2; the
-// three buffers rotate at the end of a step (d becomes the newest history).
-int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t s) {
-  Runner r{p, s, true};
-  p->imp_sweeps.assign(p->batch, 0);
-  p->imp_nonconv.assign(p->batch, 0);
-  bool stalled = false;
-  std::vector<int> flags, live;
+// predictor, then max_iter Picard sweeps (the right-hand-side passes on the
+// midpoint, the update of d, the stopping test); every pass kernel returns at
+// once for an instance whose stopping flag is clear, so each instance stops on
+// its own and the host never waits for the flags.  The counters of the call
+// (sweeps, steps stopped at max_iter) stay on the device.  The iterate d lives
+// in Acc and the two increment histories in H1, H2; the three buffers rotate
+// at the end of a step (d becomes the newest history).
+int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t s,
+                 bool record, StatsRec* stats) {
+  Runner r{p, s, record};
   const bool keep = (p->flags & HOT_FLAG_KEEP_HISTORY) && p->hist_ws == workspace;
   for (auto& G : p->groups) {
     if (r.rc != HOT_OK) break;
@@ -670,10 +711,14 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
     const long isU = 3 * G.C;
     const void* in0 = in[G.members[0]];
     void* out0 = out[G.members[0]];
+    write_tables(r, G, q, in, out);
+    r.pass(PASS_IMP_DECIDE, [&] {  // the call's counters start at zero
+      hipLaunchKernelGGL(k_fill_int<>, dim3(grid_1d(2 * nb, 256)), dim3(256), 0, r.s, q.cnt, 2L * nb, 0);
+      return hipGetLastError();
+    });
     r.pass(PASS_GATHER, [&] { return o.gather(r.s, in0, q.in_tab, q.U0, G.C, isU, nb, g); });
     // the iterate d and the histories H1 (newest), H2 rotate through three buffers
     char* buf[3] = {q.Acc, q.H[0], q.H[1]};
-    flags.assign(nb, 0);
     for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
       char *D = buf[G.rot], *H1 = buf[(G.rot + 1) % 3], *H2 = buf[(G.rot + 2) % 3];
       const int hist = G.hist;
@@ -688,7 +733,6 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
       else
         r.pass(PASS_IMP_PREDICT,
                [&] { return o.imp_predict(r.s, q.U0, D, q.U1, H1, H2, G.C, isU, nb, g, hist, q.act); });
-      live.assign(nb, 1);
       for (int sw = 0; sw < p->max_iter && r.rc == HOT_OK; ++sw) {
         rhs_passes(r, G, q, q.U1, q.act);
         r.pass(PASS_IMP_UPDATE, [&] {
@@ -696,40 +740,54 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
         });
         r.pass(PASS_IMP_DECIDE, [&] {
           hipLaunchKernelGGL(k_imp_decide<>, dim3(nb), dim3(64), 0, r.s, (const double*)q.part, G.nparts, q.act,
-                             p->tol * p->tol);
+                             p->tol * p->tol, q.cnt);
           return hipGetLastError();
         });
-        if (r.rc != HOT_OK) break;
-        hipError_t e = hipMemcpyAsync(flags.data(), q.act, nb * sizeof(int), hipMemcpyDeviceToHost, r.s);
-        if (e == hipSuccess) e = hipStreamSynchronize(r.s);
-        if (e != hipSuccess) {
-          p->last_hip = (int)e;
-          r.rc = HOT_E_HIP;
-          break;
-        }
-        int running = 0;
-        for (int m = 0; m < nb; ++m) {
-          if (!live[m]) continue;
-          p->imp_sweeps[G.members[m]] += 1;
-          live[m] = flags[m];
-          running += live[m];
-        }
-        if (running == 0) break;
       }
-      for (int m = 0; m < nb; ++m)
-        if (live[m]) {
-          p->imp_nonconv[G.members[m]] += 1;
-          stalled = true;
-        }
+      r.pass(PASS_IMP_DECIDE, [&] {  // instances still active stopped at max_iter
+        hipLaunchKernelGGL(k_imp_close<>, dim3(grid_1d(nb, 256)), dim3(256), 0, r.s, (const int*)q.act, q.cnt + nb,
+                           nb);
+        return hipGetLastError();
+      });
       r.pass(PASS_IMP_ADVANCE, [&] { return o.imp_advance(r.s, q.U0, D, G.C, isU, nb, g); });
       G.rot = (G.rot + 2) % 3;  // d becomes H1, H1 becomes H2, H2's buffer the next d
       if (G.hist < 2) ++G.hist;
     }
     r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.U0, out0, q.out_tab, G.C, isU, nb, g); });
+    if (stats) state_stats(r, p, G, q, q.U0, stats, true);
   }
   p->hist_ws = workspace;
-  if (r.rc == HOT_OK && stalled) return HOT_E_NOCONVERGE;
+  p->cnt_ws = workspace;
+  p->cnt_stream = s;
   return r.rc;
+}
+
+// The implicit counters of the plan's last call (on workspace ws), read back
+// to the host after the stream has finished; returns HOT_E_NOCONVERGE when a
+// step of some instance stopped at max_iter.
+int read_counters(hot_plan_s* p) {
+  p->imp_sweeps.assign(p->batch, 0);
+  p->imp_nonconv.assign(p->batch, 0);
+  if (!p->cnt_ws) return HOT_OK;
+  hipError_t e = hipStreamSynchronize(p->cnt_stream);
+  bool stalled = false;
+  std::vector<int> h;
+  for (const auto& G : p->groups) {
+    if (e != hipSuccess) break;
+    const GroupPtrs q = group_ptrs(G, p->cnt_ws);
+    h.assign(2 * G.B(), 0);
+    e = hipMemcpy(h.data(), q.cnt, h.size() * sizeof(int), hipMemcpyDeviceToHost);
+    for (int m = 0; m < G.B() && e == hipSuccess; ++m) {
+      p->imp_sweeps[G.members[m]] = h[m];
+      p->imp_nonconv[G.members[m]] = h[G.B() + m];
+      stalled = stalled || h[G.B() + m] > 0;
+    }
+  }
+  if (e != hipSuccess) {
+    p->last_hip = (int)e;
+    return HOT_E_HIP;
+  }
+  return stalled ? HOT_E_NOCONVERGE : HOT_OK;
 }
 
 }  // namespace
@@ -772,12 +830,13 @@ extern "C" int hot_set_surrogate(hot_plan_t p, const void* packed) {
 
 extern "C" int hot_implicit_stats(hot_plan_t p, int32_t* sweeps, int32_t* nonconv) {
   if (!p || p->op != HOT_OP_IMPLICIT) return HOT_E_INVALID;
+  const int rc = read_counters(p);
+  if (rc == HOT_E_HIP) return rc;
   for (int i = 0; i < p->batch; ++i) {
-    const bool ran = (int)p->imp_sweeps.size() == p->batch;
-    if (sweeps) sweeps[i] = ran ? p->imp_sweeps[i] : 0;
-    if (nonconv) nonconv[i] = ran ? p->imp_nonconv[i] : 0;
+    if (sweeps) sweeps[i] = p->imp_sweeps[i];
+    if (nonconv) nonconv[i] = p->imp_nonconv[i];
   }
-  return HOT_OK;
+  return rc;
 }
 
 // HOT_FLAG_CHECK_FINITE: scan every instance's compact result (Acc for a
@@ -808,39 +867,41 @@ static int check_finite(hot_plan_s* p, void* workspace, hipStream_t s) {
 }
 
 extern "C" int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
-                       void* stream) {
-  int rc = check_run_args(p, in, out, workspace, nsteps);
+                       void* stats_dev, void* stream) {
+  int rc = check_run_args(p, in, out, workspace, nsteps, stats_dev);
   if (rc != HOT_OK) return rc;
   if (p->nranks > 1) return HOT_E_UNSUPPORTED;  // a share runs by phases (hot_slab_run)
   hipStream_t s = (hipStream_t)stream;
-  rc = ensure_tables(p, in, out, workspace, s);
-  if (rc != HOT_OK) return rc;
+  StatsRec* stats = (StatsRec*)stats_dev;
   if (p->op == HOT_OP_IMPLICIT)
-    rc = run_implicit(p, in, out, workspace, nsteps, s);
+    rc = run_implicit(p, in, out, workspace, nsteps, s, true, stats);
   else
-    rc = enqueue(p, in, out, workspace, nsteps, s, true);
-  if ((p->flags & HOT_FLAG_CHECK_FINITE) && (rc == HOT_OK || rc == HOT_E_NOCONVERGE)) {
+    rc = enqueue(p, in, out, workspace, nsteps, s, true, stats);
+  if ((p->flags & HOT_FLAG_CHECK_FINITE) && rc == HOT_OK) {
+    // this plan synchronises anyway: report a max_iter stop as well
     const int fc = check_finite(p, workspace, s);
     if (fc != HOT_OK) return fc;
+    if (p->op == HOT_OP_IMPLICIT) return read_counters(p);
   }
   return rc;
 }
 
 extern "C" int hot_graph_create(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
-                                void* stream, hot_graph_t* graph) {
+                                void* stats_dev, void* stream, hot_graph_t* graph) {
   if (graph) *graph = nullptr;
   if (!graph || !stream) return HOT_E_INVALID;  // the legacy default stream cannot be captured
-  int rc = check_run_args(p, in, out, workspace, nsteps);
+  int rc = check_run_args(p, in, out, workspace, nsteps, stats_dev);
   if (rc != HOT_OK) return rc;
-  if (p->op == HOT_OP_IMPLICIT || (p->flags & HOT_FLAG_CHECK_FINITE) || p->nranks > 1) return HOT_E_UNSUPPORTED;
+  // a kept implicit history depends on the calls before: not replayable
+  if ((p->flags & (HOT_FLAG_CHECK_FINITE | HOT_FLAG_KEEP_HISTORY)) || p->nranks > 1) return HOT_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
-  rc = ensure_tables(p, in, out, workspace, s);
-  if (rc != HOT_OK) return rc;
   hot_graph_s* G = new (std::nothrow) hot_graph_s();
   if (!G) return HOT_E_INVALID;
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    rc = enqueue(p, in, out, workspace, nsteps, s, false);
+    StatsRec* stats = (StatsRec*)stats_dev;
+    rc = p->op == HOT_OP_IMPLICIT ? run_implicit(p, in, out, workspace, nsteps, s, false, stats)
+                                  : enqueue(p, in, out, workspace, nsteps, s, false, stats);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s, &g);
     G->graph = g;
@@ -982,8 +1043,9 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
     if (rc == HOT_OK && (p->op == HOT_OP_RK4 || p->op == HOT_OP_RHS)) {
       float best = 1e30f;
       int best_f = -1;
-      for (int f = -1; f < 2 && rc == HOT_OK; ++f) {
+      for (int f = -1; f < 3 && rc == HOT_OK; ++f) {
         if (f == 0 && G.ops.strided_width[0] == G.ops.strided_width[1]) continue;  // same kernel as f = 1
+        if (f == 2 && G.ops.fused_quarter_width == G.ops.strided_width[0]) continue;  // same kernel as f = 0
         G.fused = f;
         float t = 0.f;
         for (int rep = 0; rep <= reps && rc == HOT_OK; ++rep) {
@@ -1033,7 +1095,7 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
   if (!p) return HOT_E_INVALID;
   const bool tiled = pass == PASS_X_INV_CURL || pass == PASS_Y_INV || pass == PASS_Y_FWD || pass == PASS_X_FWD;
   if (pass == PASS_X_FWD_RK) {
-    if (variant < -1 || variant > 1 || (p->op != HOT_OP_RK4 && p->op != HOT_OP_RHS)) return HOT_E_INVALID;
+    if (variant < -1 || variant > 2 || (p->op != HOT_OP_RK4 && p->op != HOT_OP_RHS)) return HOT_E_INVALID;
     for (auto& G : p->groups) G.fused = variant;
     return HOT_OK;
   }
@@ -1052,7 +1114,8 @@ extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
   if (!p || instance < 0 || instance >= p->batch || pass < 0 || pass >= NUM_PASSES) return HOT_E_INVALID;
   for (const auto& G : p->groups)
     if (G.N == p->n[instance]) {
-      if (pass == PASS_X_FWD_RK) return G.fused < 0 ? 0 : G.ops.strided_width[G.fused];
+      if (pass == PASS_X_FWD_RK)
+        return G.fused < 0 ? 0 : (G.fused == 2 ? G.ops.fused_quarter_width : G.ops.strided_width[G.fused]);
       if (pass == PASS_YZ_FUSED) return G.yz < 0 ? 0 : 1;
       return G.ops.strided_width[G.variant[pass]];
     }

@@ -45,7 +45,7 @@ struct LPz {
 // (Stockham stages, Hermitian completion and split): the summed conflict
 // degree drops from 1935 / 108 / 213 / 147 / 109 / 333 / 291 / 227 to
 // 0 / 72 / 9 / 4 / 105 / 21 / 168 / 11 at N = 16 / 18 / 24 / 32 / 36 / 48 / 54 / 64
-// (zline_banks.py).
+// (the bank model tests/zline_banks.py, checked by tests/test_line_strides.py).
 template <int N>
 struct LPz32 {
   using P = typename LPz<N>::P;
@@ -109,6 +109,7 @@ struct Ops {
   hipError_t (*imp_advance)(hipStream_t, void* U0, const void* D, long C, long is, int nb, const Geo&);
   int strided_variants;       // number of column widths the autotuner may pick from
   int strided_width[3];       // columns per block of each variant
+  int fused_quarter_width;    // columns per block of x_fwd_rk variant 2
 };
 
 static inline unsigned grid_1d(long work, int block) {
@@ -187,8 +188,14 @@ struct Impl {
       hipLaunchKernelGGL((k_x_inv_curl6<T, P, WW>), dim3(8u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
                          (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
     } else {
-      hipLaunchKernelGGL((k_x_inv_curl<T, P, WW>), dim3(8u * 6u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
-                         (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
+      // registers that can hold a retained row: the 2/3-rule count, or all
+      constexpr int KL23 = (((N - 1) / 3 + 1) + Tl - 1) / Tl;
+      if (g.lo <= KL23 * Tl && g.hi <= KL23 * Tl)
+        hipLaunchKernelGGL((k_x_inv_curl3<T, P, WW, KL23>), dim3(8u * 3u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
+                           (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
+      else
+        hipLaunchKernelGGL((k_x_inv_curl3<T, P, WW, P::R>), dim3(8u * 3u * ngrp, (unsigned)nb), dim3(WW * Tl), 0,
+                           s, (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
     }
     return hipGetLastError();
   }
@@ -280,14 +287,23 @@ struct Impl {
     const long ntiles = (Q + WW - 1) / WW;
     const long group = 8L * pair;
     const dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)nb);
-    hipLaunchKernelGGL((k_x_fwd_rk<T, P, WW>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)A, csA, isA, (cx<T>*)U0,
-                       (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
+    // registers that can hold a retained row: the 2/3-rule count, or all
+    constexpr int KL23 = (((N - 1) / 3 + 1) + Tl - 1) / Tl;
+    if (g.lo <= KL23 * Tl && g.hi <= KL23 * Tl)
+      hipLaunchKernelGGL((k_x_fwd_rk<T, P, WW, KL23>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)A, csA, isA,
+                         (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
+    else
+      hipLaunchKernelGGL((k_x_fwd_rk<T, P, WW, P::R>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)A, csA, isA,
+                         (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
     return hipGetLastError();
   }
-  // fused variants: W/2 and W (three components in registers)
+  // fused variants: W/2, W and W/4 (three components in registers); W/4 only
+  // where it still makes a whole wave
+  static constexpr int WQ = fits(W / 4) ? W / 4 : WV0;
   static hipError_t x_fwd_rk(hipStream_t s, int variant, const void* A, long csA, long isA, void* U0, void* U1,
                              void* Acc, long C, long isU, int nb, const Geo& g, int mode, double nu, double dt) {
     if (variant == 0) return x_fwd_rk_w<WV0>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
+    if (variant == 2) return x_fwd_rk_w<WQ>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
     return x_fwd_rk_w<W>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
   }
   static hipError_t gather(hipStream_t s, const void* in0, const void* const* in_tab, void* out, long C, long is,
@@ -326,7 +342,7 @@ struct Impl {
     return Ops{&strided,     &x_inv_curl, &z_cross,    &z_cross_blocked,
                kYz ? &yz_fused : nullptr,   &z_c2r,      &z_r2c,      &rk_stage,
                &x_fwd_rk,    &gather,     &scatter,    &imp_predict,
-               &imp_update,  &imp_advance, 3,          {WV0, W, WV2}};
+               &imp_update,  &imp_advance, 3,          {WV0, W, WV2}, WQ};
   }
 };
 

@@ -306,6 +306,87 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
   }
 }
 
+// Registers of a column that can hold a retained row: with lo, hi <= KL Tl
+// the rows j + s Tl with KL <= s < R - KL lie in [lo, N - hi) for every lane
+// j, so they are never loaded and their values are zero at compile time.
+template <class Plan, int KL>
+constexpr bool col_live(int s) {
+  return s < KL || s >= Plan::R - KL;
+}
+
+// P1 with three blocks per tile: block m in {0, 1, 2} loads u_m and u_{m+1}
+// (indices mod 3) and writes w_{m+2} = i (k_m u_{m+1} - k_{m+1} u_m), then
+// u_m (the cyclic form of w = i k x u: w_z = i (kx u_y - ky u_x), w_x =
+// i (ky u_z - kz u_y), w_y = i (kz u_x - kx u_z)).  Six component loads per
+// tile instead of nine, and half as many blocks as k_x_inv_curl.  The three
+// blocks of a tile go to one XCD, so each input row comes from HBM once.
+// KL: retained rows reach at most KL registers from either end (col_live).
+template <typename T, class Plan, int W, int KL>
+__global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl3(const cx<T>* __restrict__ U, long csU, long isU,
+                                                             cx<T>* __restrict__ A, long csA, long isA,
+                                                             int ntiles, Geo g, const int* __restrict__ act) {
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+  __shared__ cx<T> sm[N * W];
+  __shared__ cx<T> tws[N];
+  const int blk = blockIdx.x;
+  const int xcd = blk & 7, slot = blk >> 3;
+  const int m = slot % 3;
+  const int rest = slot / 3;
+  const int tile = ((rest / PAIR) * 8 + xcd) * PAIR + rest % PAIR;
+  if (tile >= ntiles) return;           // whole block leaves together
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
+  const int tid = threadIdx.x;
+  TwStage<T, Plan, W * Tl> tw;  // to LDS, ordered before use by the first exchange barrier
+  tw.fetch(tid);
+  const int c = tid % W, j = tid / W;
+  const long Q = (long)g.M * g.Mzp;
+  const long q = (long)tile * W + c;
+  const int iy = (int)(q / g.Mzp);
+  const int kz = (int)(q - (long)iy * g.Mzp);
+  const bool valid = q < Q && kz < g.Mz;
+  const T ky = T(kwave(cpos(valid ? iy : 0, g), N));
+  const T kzf = T(kz + g.kz0);
+  const long qq = valid ? q : 0;
+  U += blockIdx.y * isU;  // instance of a batch
+  A += blockIdx.y * isA;
+  const int m1 = m == 2 ? 0 : m + 1;
+  const cx<T>* pa = U + m * csU + qq;
+  const cx<T>* pb = U + m1 * csU + qq;
+  // every lane loads from a valid address (row 0 when the position is not
+  // retained) and selects afterwards: no branches around the loads
+  cx<T> a[R], v[R];
+  static_for<0, R>([&](auto s) {
+    if constexpr (col_live<Plan, KL>(s)) {
+      const int p = j + s * Tl;
+      const bool kp = valid && kept(p, g);
+      const long off = kp ? (long)crow(p, g) * Q : 0;
+      const cx<T> x = pa[off], y = pb[off];
+      const T kx = T(kwave(p, N));
+      const T km = m == 0 ? kx : (m == 1 ? ky : kzf);
+      const T kn = m == 0 ? ky : (m == 1 ? kzf : kx);
+      a[s] = kp ? x : cx<T>{T(0), T(0)};
+      v[s] = kp ? mul_i(y * km - x * kn) : cx<T>{T(0), T(0)};
+    } else {
+      a[s] = cx<T>{T(0), T(0)};
+      v[s] = cx<T>{T(0), T(0)};
+    }
+  });
+  tw.put(tws, tid);
+  LdsCols<T, N, W> lds{sm, c};
+  const int ow = m == 0 ? 5 : (m == 1 ? 3 : 4);  // w_z, w_x, w_y
+  Plan::template fft<T, +1>(v, j, lds, TwTab<T>{tws});
+  if (valid) {
+    cx<T>* dst = A + ow * csA + q;
+    static_for<0, R>([&](auto s) { store_out<PAIR == 1>(dst + (long)(j + s * Tl) * Q, v[s]); });
+  }
+  Plan::template fft<T, +1>(a, j, lds, TwTab<T>{tws});
+  if (valid) {
+    cx<T>* dst = A + m * csA + q;
+    static_for<0, R>([&](auto s) { store_out<PAIR == 1>(dst + (long)(j + s * Tl) * Q, a[s]); });
+  }
+}
+
 // P1 for short lines: one block computes all six outputs of a tile (u_c, then
 // w_c = i (k x u)_c) from a single load of the three velocity components,
 // transforming them one after another through the same LDS tile.  Six times
@@ -691,7 +772,7 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
 // A[3][N rows (x)][Q = M*Mzp cols (ky, kz)]; the state arrays are compact
 // [3][M][Q].  blockIdx.y is the instance of a batch.
 // ---------------------------------------------------------------------------
-template <typename T, class Plan, int W>
+template <typename T, class Plan, int W, int KL>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restrict__ A, long csA, long isA,
                                                           cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
                                                           cx<T>* __restrict__ Acc, long C, long isU, Geo g, int mode,
@@ -716,6 +797,8 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restric
   Acc += blockIdx.y * isU;
   TwStage<T, Plan, W * Tl> tw;
   tw.fetch(tid);
+  // every component's loads in flight together (their registers hold the
+  // transformed values afterwards anyway)
   cx<T> v[3][R];
   static_for<0, 3>([&](auto comp) {
     const cx<T>* a = A + comp * csA + qq;
@@ -723,17 +806,23 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restric
       const cx<T> x = a[(long)(j + s * Tl) * Q];
       v[comp][s] = valid ? x : cx<T>{T(0), T(0)};
     });
-    if constexpr (comp == 0) tw.put(tws, tid);
+  });
+  tw.put(tws, tid);
+  static_for<0, 3>([&](auto comp) {
     LdsCols<T, N, W> lds{sm, c};
     Plan::template fft<T, -1>(v[comp], j, lds, TwTab<T>{tws});
   });
   if (!valid) return;
   const int kyi = kwave(cpos(iy, g), N);
+  // rows reach at most KL registers from either end (col_live): the others
+  // are never kept, and their outputs are not computed
   static_for<0, R>([&](auto s) {
-    const int p = j + s * Tl;
-    if (kept(p, g))
-      rk_update((long)crow(p, g) * Q + q, v[0][s], v[1][s], v[2][s], kwave(p, N), kyi, kz + g.kz0, U0, U1, Acc, C,
-                mode, nu, dt);
+    if constexpr (col_live<Plan, KL>(s)) {
+      const int p = j + s * Tl;
+      if (kept(p, g))
+        rk_update((long)crow(p, g) * Q + q, v[0][s], v[1][s], v[2][s], kwave(p, N), kyi, kz + g.kz0, U0, U1, Acc,
+                  C, mode, nu, dt);
+    }
   });
 }
 
@@ -857,9 +946,10 @@ __global__ __launch_bounds__(256) void k_imp_update(const cx<T>* __restrict__ Nh
 
 // Stopping test of instance blockIdx.x (one wave): sum its nparts partial
 // sums in a fixed order and clear act when ||d_new - d|| <= tau ||d_new||.
+// The sweep just run is counted in sweeps[b].
 template <int Unused = 0>
 __global__ __launch_bounds__(64) void k_imp_decide(const double* __restrict__ part, int nparts, int* __restrict__ act,
-                                                   double tau2) {
+                                                   double tau2, int* __restrict__ sweeps) {
   const int b = blockIdx.x;
   if (!act[b]) return;
   double su = 0.0, si = 0.0;
@@ -871,7 +961,24 @@ __global__ __launch_bounds__(64) void k_imp_decide(const double* __restrict__ pa
     su += __shfl_xor(su, o, 64);
     si += __shfl_xor(si, o, 64);
   }
-  if (threadIdx.x == 0 && su <= tau2 * si) act[b] = 0;
+  if (threadIdx.x == 0) {
+    sweeps[b] += 1;
+    if (su <= tau2 * si) act[b] = 0;
+  }
+}
+
+// After the last allowed sweep of a step: an instance still active stopped
+// at max_iter; count it in nonconv[b].
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void k_imp_close(const int* __restrict__ act, int* __restrict__ nonconv, int nb) {
+  for (int b = blockIdx.x * 256 + threadIdx.x; b < nb; b += gridDim.x * 256)
+    if (act[b]) nonconv[b] += 1;
+}
+
+// p[0..n) = v (a fill kernel: graph-safe, unlike a memset node).
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void k_fill_int(int* __restrict__ p, long n, int v) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) p[i] = v;
 }
 
 // End of a step: U0 += D.
@@ -947,6 +1054,71 @@ __global__ __launch_bounds__(64) void k_diag_final(const double* __restrict__ pa
   }
 }
 
+// Per-instance statistics of a call (the hot_stats record of include/hot.h):
+// E and eps, as k_diag defines them, of a compact state U [B][3][C] (every
+// other mode of the canonical array is zero), plus the implicit step's
+// counters.  k_state_sums: per-block FP64 partial sums part[b][block][2];
+// k_state_final (one wave per instance) adds them in a fixed order.
+struct StatsRec {
+  double energy, dissipation;
+  int sweeps, nonconv;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_state_sums(const cx<T>* __restrict__ U, long C, long is, Geo g,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4];
+  U += blockIdx.y * is;
+  double se = 0.0, sd = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < C; e += (long)gridDim.x * 256) {
+    ModeK m;
+    if (!mode_of(e, g, m)) continue;
+    double a = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const cx<T> v = U[c * C + e];
+      a += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    const double w = (m.kz == 0 || 2 * m.kz == g.N) ? 1.0 : 2.0;
+    se += w * a;
+    sd += w * (double)(m.kx * m.kx + m.ky * m.ky + m.kz * m.kz) * a;
+  }
+  se = block_sum_256(se, red);
+  sd = block_sum_256(sd, red);
+  if (threadIdx.x == 0) {
+    double* q = part + 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
+    q[0] = se;
+    q[1] = sd;
+  }
+}
+
+// Instance blockIdx.x of the group is instance idx[b] of the call (idx NULL:
+// the group's single instance is idx0).  sweeps / nonconv NULL: zeros.
+template <int Unused = 0>
+__global__ __launch_bounds__(64) void k_state_final(const double* __restrict__ part, int nparts, int N, double nu,
+                                                    const long* __restrict__ idx, long idx0,
+                                                    const int* __restrict__ sweeps, const int* __restrict__ nonconv,
+                                                    StatsRec* __restrict__ out) {
+  const int b = blockIdx.x;
+  double se = 0.0, sd = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 64) {
+    se += part[2 * ((long)b * nparts + i)];
+    sd += part[2 * ((long)b * nparts + i) + 1];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    se += __shfl_xor(se, o, 64);
+    sd += __shfl_xor(sd, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    const double n6 = (double)N * N * N * N * N * N;
+    StatsRec r;
+    r.energy = se / (2.0 * n6);
+    r.dissipation = nu * sd / n6;
+    r.sweeps = sweeps ? sweeps[b] : 0;
+    r.nonconv = nonconv ? nonconv[b] : 0;
+    out[idx ? idx[b] : idx0] = r;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Canonical <-> compact.  Canonical: [3][N][N][N/2+1].  Compact:
 // [3][M][M][Mzp].  Gather drops the modes outside the retained set
@@ -997,6 +1169,21 @@ __device__ __forceinline__ void pos4_add(Pos4& p, const Pos4& s, int na, int nb,
   k = p.a >= na;
   p.a -= k ? na : 0;
   p.c += s.c + k;
+}
+
+// Device pointer tables of a batch (the canonical arrays of its instances):
+// the pointers travel as kernel arguments, so the tables are written in
+// stream order with no host synchronisation, and a call captured into a graph
+// records them by value.
+constexpr int kTabChunk = 240;
+struct TabChunk {
+  const void* p[kTabChunk];
+};
+
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void k_write_tab(const void** __restrict__ dst, TabChunk c, int n) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = c.p[i];
 }
 
 template <typename T>

@@ -87,13 +87,13 @@ def test_run_rejects_bad_pointers_without_touching_the_gpu():
     try:
         arr = (ctypes.c_void_p * 1)(256 * 1000)
         nul = (ctypes.c_void_p * 1)(None)
-        assert lib.hot_run(h, arr, arr, None, 0, None) == binding.HOT_E_WORKSPACE
-        assert lib.hot_run(h, arr, arr, ctypes.c_void_p(256 * 7 + 3), 0, None) == binding.HOT_E_WORKSPACE
-        assert lib.hot_run(h, nul, arr, ctypes.c_void_p(256 * 9), 0, None) == binding.HOT_E_INVALID
+        assert lib.hot_run(h, arr, arr, None, 0, None, None) == binding.HOT_E_WORKSPACE
+        assert lib.hot_run(h, arr, arr, ctypes.c_void_p(256 * 7 + 3), 0, None, None) == binding.HOT_E_WORKSPACE
+        assert lib.hot_run(h, nul, arr, ctypes.c_void_p(256 * 9), 0, None, None) == binding.HOT_E_INVALID
         mis = (ctypes.c_void_p * 1)(256 * 1000 + 8)
-        assert lib.hot_run(h, mis, arr, ctypes.c_void_p(256 * 9), 0, None) == binding.HOT_E_INVALID
-        assert lib.hot_run(h, arr, arr, ctypes.c_void_p(256 * 9), -1, None) == binding.HOT_E_INVALID
-        assert lib.hot_run(None, arr, arr, ctypes.c_void_p(256 * 9), 0, None) == binding.HOT_E_INVALID
+        assert lib.hot_run(h, mis, arr, ctypes.c_void_p(256 * 9), 0, None, None) == binding.HOT_E_INVALID
+        assert lib.hot_run(h, arr, arr, ctypes.c_void_p(256 * 9), -1, None, None) == binding.HOT_E_INVALID
+        assert lib.hot_run(None, arr, arr, ctypes.c_void_p(256 * 9), 0, None, None) == binding.HOT_E_INVALID
     finally:
         binding.hot_destroy(h)
     assert lib.hot_destroy(None) == 0
@@ -115,7 +115,8 @@ def test_workspace_size_formula(N, dtype, elem):
     C, D1, D2 = M * M * P, N * M * P, N * N * P
     h, ws = binding.hot_plan(N, "rk4", dtype, nu=0.01, dt=1e-3)
     binding.hot_destroy(h)
-    assert ws == 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem)
+    # + the partial sums of the per-instance statistics: 64 blocks x (E, eps) in FP64
+    assert ws == 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem) + _align(64 * 2 * 8)
     h, ws = binding.hot_plan(N, "r2c", dtype)
     binding.hot_destroy(h)
     assert ws == 2 * _align(3 * N * N * (N // 2 + 1) * elem)
@@ -148,7 +149,7 @@ def test_graph_and_tune_reject_bad_arguments_without_the_gpu():
         arr = (ctypes.c_void_p * 3)(256 * 1000, 256 * 2000, 256 * 3000)
         g = ctypes.c_void_p()
         # the legacy default stream cannot be captured
-        assert lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, None, ctypes.byref(g)) == \
+        assert lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, None, None, ctypes.byref(g)) == \
             binding.HOT_E_INVALID
         assert not g.value
         assert lib.hot_tune(h, ctypes.c_void_p(256 * 9), None, 0) == binding.HOT_E_INVALID
@@ -179,8 +180,9 @@ def test_implicit_plan_validation_and_workspace():
     h, ws = binding.hot_plan(N, "implicit", "f64", nu=0.01, dt=1e-3, tol=1e-8, max_iter=20)
     binding.hot_destroy(h)
     nparts = -(-C // 256)
-    base = 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem)
-    assert ws == base + 2 * _align(3 * C * elem) + _align(4) + _align(nparts * 16)
+    base = 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem) + _align(64 * 2 * 8)
+    # + two histories, the flag, the partial sums and the two counters
+    assert ws == base + 2 * _align(3 * C * elem) + _align(4) + _align(nparts * 16) + _align(2 * 4)
 
 
 def test_implicit_stats_and_graph_rules_without_the_gpu():
@@ -194,11 +196,25 @@ def test_implicit_stats_and_graph_rules_without_the_gpu():
     try:
         # nothing ran yet: zero sweeps
         assert binding.hot_implicit_stats(h, 2) == ([0, 0], [0, 0])
-        # the sweep count is decided on the host: no graph capture
+    finally:
+        binding.hot_destroy(h)
+    # a kept history continues from the calls before: no graph capture
+    h, _ = binding.hot_plan([16, 32], "implicit", "f32", nu=0.01, dt=1e-3, tol=1e-5, max_iter=8, keep_history=True)
+    try:
         arr = (ctypes.c_void_p * 2)(256 * 1000, 256 * 2000)
         g = ctypes.c_void_p()
-        rc = lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, ctypes.c_void_p(256), ctypes.byref(g))
+        rc = lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, None, ctypes.c_void_p(256), ctypes.byref(g))
         assert rc == binding.HOT_E_UNSUPPORTED and not g.value
+        # statistics only for the ops with a state, and 8-byte aligned
+        assert lib.hot_run(h, arr, arr, ctypes.c_void_p(256 * 9), 1, ctypes.c_void_p(256 + 4), None) == \
+            binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    h, _ = binding.hot_plan(16, "r2c", "f32")
+    try:
+        arr = (ctypes.c_void_p * 1)(256 * 1000)
+        assert lib.hot_run(h, arr, arr, ctypes.c_void_p(256 * 9), 0, ctypes.c_void_p(256), None) == \
+            binding.HOT_E_INVALID
     finally:
         binding.hot_destroy(h)
     assert lib.hot_error_string(binding.HOT_E_NOCONVERGE) != lib.hot_error_string(-99)
@@ -221,7 +237,7 @@ def test_check_finite_flag_rules_without_the_gpu():
     try:
         arr = (ctypes.c_void_p * 1)(256 * 1000)
         g = ctypes.c_void_p()
-        rc = lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, ctypes.c_void_p(256), ctypes.byref(g))
+        rc = lib.hot_graph_create(h, arr, arr, ctypes.c_void_p(256 * 9), 1, None, ctypes.c_void_p(256), ctypes.byref(g))
         assert rc == binding.HOT_E_UNSUPPORTED and not g.value
     finally:
         binding.hot_destroy(h)
@@ -259,10 +275,10 @@ def test_set_variant_rules_without_the_gpu():
     names = binding.pass_names()
     h, _ = binding.hot_plan(32, "rk4", "f32", nu=0.01, dt=1e-3)
     try:
-        for v in (-1, 0, 1):
+        for v in (-1, 0, 1, 2):
             binding.hot_set_variant(h, "x_fwd_rk", v)
             assert (binding.hot_tuned_width(h, 0, "x_fwd_rk") == 0) == (v < 0)
-        assert lib.hot_set_variant(h, names.index("x_fwd_rk"), 2) == binding.HOT_E_INVALID
+        assert lib.hot_set_variant(h, names.index("x_fwd_rk"), 3) == binding.HOT_E_INVALID
         assert lib.hot_set_variant(h, names.index("y_inv"), 3) == binding.HOT_E_INVALID
         assert lib.hot_set_variant(h, names.index("z_cross"), 1) == binding.HOT_E_INVALID
         binding.hot_set_variant(h, "y_inv", 0)
@@ -283,7 +299,7 @@ def test_fused_yz_variant_rules_without_the_gpu():
     lib = binding.library()
     names = binding.pass_names()
     yz = names.index("yz_fused")
-    assert names[-1] == "yz_fused"
+    assert names[-3:] == ["yz_fused", "tables", "stats"]
     # the fused y-z pass exists for small N only: a batch switches the sizes that have it
     h, _ = binding.hot_plan([16, 64, 128, 1024], "rk4", "f32", nu=0.01, dt=1e-3)
     try:
@@ -367,7 +383,7 @@ def test_slab_share_geometry_and_workspace():
     K = (N - 1) // 3
     M, C = 2 * K + 1, (2 * K + 1) ** 2 * 6
     D1, D2 = N * M * 6, N * N * 6
-    assert wss[0] == 4 * _align(3 * C * e) + _align(6 * D1 * e) + 2 * _align(6 * D2 * e)
+    assert wss[0] == 4 * _align(3 * C * e) + _align(6 * D1 * e) + 2 * _align(6 * D2 * e) + _align(64 * 2 * 8)
     # 128-byte pitch once chunks are long enough: N = 1024 FP32 over 4 shares
     h, _ = binding.hot_plan_slab(1024, "rk4", 4, 3, "f32", nu=0.01, dt=1e-3)
     l = binding.hot_slab_layout_of(h)
@@ -397,9 +413,9 @@ def test_slab_plan_and_run_rules_without_the_gpu():
     try:
         arr = (ctypes.c_void_p * 1)(256 * 1000)
         ws = ctypes.c_void_p(256 * 9)
-        assert lib.hot_run(h, arr, arr, ws, 1, None) == binding.HOT_E_UNSUPPORTED
+        assert lib.hot_run(h, arr, arr, ws, 1, None, None) == binding.HOT_E_UNSUPPORTED
         g = ctypes.c_void_p()
-        assert lib.hot_graph_create(h, arr, arr, ws, 1, ctypes.c_void_p(256), ctypes.byref(g)) == \
+        assert lib.hot_graph_create(h, arr, arr, ws, 1, None, ctypes.c_void_p(256), ctypes.byref(g)) == \
             binding.HOT_E_UNSUPPORTED
         assert lib.hot_diagnostics(h, arr, ws, ctypes.c_void_p(256), None) == binding.HOT_E_UNSUPPORTED
         run = lib.hot_slab_run

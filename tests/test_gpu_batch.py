@@ -130,3 +130,40 @@ def test_pointer_tables_follow_new_arrays():
             assert rel_l2(o2.cpu().numpy(), oracle.rhs(2.0 * f, NU)) < 1e-12
     finally:
         binding.hot_destroy(h)
+
+
+def test_graph_keeps_its_pointers_after_a_run_on_other_arrays():
+    # a graph made on arrays A, then an eager call on arrays B over the same
+    # workspace, then a replay: the replay must read and write A only
+    import torch
+    fields = _fields("f32")[:6]
+    h, wsb = binding.hot_plan([f.shape[1] for f in fields], "rk4", "f32", "two_thirds", NU, DT)
+    try:
+        ws = workspace(wsb)
+        ins_a = [to_dev(f, "f32") for f in fields]
+        outs_a = [torch.zeros_like(x) for x in ins_a]
+        ins_b = [to_dev(inputs.rough_random(f.shape[1], 900 + i), "f32") for i, f in enumerate(fields)]
+        outs_b = [torch.zeros_like(x) for x in ins_b]
+        s = torch.cuda.Stream()  # graphs are captured on a non-default stream
+        torch.cuda.synchronize()
+        g = binding.hot_graph_create(h, ins_a, outs_a, ws, 1, s)
+        try:
+            binding.hot_run(h, ins_b, outs_b, ws, 1, s)
+            torch.cuda.synchronize()
+            want_b = [o.cpu().numpy() for o in outs_b]
+            for o in outs_b:
+                o.fill_(7.0)
+            torch.cuda.synchronize()
+            binding.hot_graph_launch(g, s)
+            torch.cuda.synchronize()
+        finally:
+            binding.hot_graph_destroy(g)
+        for o in outs_b:  # B untouched by the replay
+            assert bool((o == 7.0).all())
+        for f, o in zip(fields, outs_a):
+            assert rel_l2(o.cpu().numpy(), oracle.rk4(round32(f), NU, DT, 1)) < fp32_tol(f.shape[1])
+        for f, w in zip(ins_b, want_b):
+            ref = oracle.rk4(f.cpu().numpy().astype(np.complex128), NU, DT, 1)
+            assert rel_l2(w, ref) < fp32_tol(f.shape[1])
+    finally:
+        binding.hot_destroy(h)

@@ -29,6 +29,9 @@ def _run(op, arrays, dtype, check, **kw):
         ws = workspace(wsb)
         rc = binding.hot_run(h, ins, outs, ws, 0 if op == "rhs" else 2)
         torch.cuda.synchronize()
+        if op == "implicit" and rc == binding.HOT_OK:
+            # without the flag hot_run does not wait: a max_iter stop shows in the statistics
+            rc = binding.library().hot_implicit_stats(h, None, None)
         return rc, [o.cpu().numpy() for o in outs]
     finally:
         binding.hot_destroy(h)
