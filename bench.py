@@ -33,13 +33,6 @@ NU = 1.0 / 1600.0  # Re = 1600 (Sec. 4)
 DT = 1e-3          # Sec. 4
 
 
-def unpruned_step_bytes(N, elem):
-    """Bytes of one RK4 step in the unpruned three-pass model: 204 passes of a
-    full half-spectrum component, S(N) = N^2 (N/2 + 1) complex values.  The
-    pruned passes here move less; this model is only a reference point."""
-    return 204.0 * N * N * (N // 2 + 1) * elem
-
-
 def source_hash():
     """Hash of the sources of the right-hand-side and RK4 kernels."""
     h = hashlib.sha256()
@@ -214,6 +207,7 @@ def batch_cpu_baseline(sizes, per_size=2):
         "unit": "instances/s",
         "cores": 1,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "sample": f"one FP64 oracle RK4 step of {per_size} instances per size, {sum(per.values()) * per_size:.1f} s; "
                   f"mean seconds per instance by size {({N: round(t, 4) for N, t in per.items()})}, weighted by the "
                   f"batch's size counts: {total:.1f} s per batch step on 1 core",
@@ -346,11 +340,6 @@ def bench_batch(a):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / t_graph / 1e9,
                           "frac": step_bytes / t_graph / 1e9 / HBM_PEAK_GBS},
-        "step_roofline_unpruned_model": {
-            "model_bytes_per_step": float(sum(unpruned_step_bytes(int(n), 8 if a.dtype == "f32" else 16)
-                                              for n in sizes)),
-            "frac": float(sum(unpruned_step_bytes(int(n), 8 if a.dtype == "f32" else 16) for n in sizes))
-                    / t_graph / 1e9 / HBM_PEAK_GBS},
         "setup_seconds": {"fields": t_gen},
     }
     if cpu is not None:
@@ -361,7 +350,7 @@ def bench_batch(a):
 
 IMP_DT = 1e-2  # implicit step: 10x the RK4 step of Sec. 4
 BF16_PEAK_TFLOPS = 2500.0
-MLP_FLOP_PER_ROW = 2 * (32 * 256 + 2 * 256 * 256 + 256 * 16)  # the output layer runs 16 padded columns
+MLP_FLOP_PER_ROW = 2 * (32 * 256 + 2 * 256 * 256 + 256 * 6)  # the six real outputs (not the padded tile)
 
 
 def _implicit_trajectory(binding, torch, N, seed, nsteps, nu, dt):
@@ -751,6 +740,20 @@ def bench_slab(a):
     print(json.dumps(line), flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), and its core count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name}, {os.cpu_count()} logical cores"
+
+
 def cpu_baseline(N_work, seconds=12.0, max_procs=16):
     """Time the CPU oracle on RK4 steps at N = 128 and scale to instances/s of
     an N_work^3 step by the FFT cost N^3 log2 N: once on one pinned core (the
@@ -775,6 +778,14 @@ def cpu_baseline(N_work, seconds=12.0, max_procs=16):
         "kind": "oracle",
         "sample": f"{steps} RK4 steps of the FP64 oracle at N={n} (R1 seed 0) in {el:.1f} s on 1 core = "
                   f"{pps:.3g} point-steps/s; scaled to N={N_work} by log2(N) ({scale:.3f}x per point)",
+    }
+    out["cpu_model"] = cpu_model()
+    # one measured step at 256^3 beside the extrapolation from 128^3
+    s256, el256 = _oracle_rk4_rate(0.0, n=256)
+    out["measured_256"] = {
+        "seconds_per_rk4_step": el256 / s256,
+        "point_steps_per_s": 256**3 * s256 / el256,
+        "scaled_from_128": pps * np.log2(128) / np.log2(256),
     }
     cores = allowed[:max_procs]
     if len(cores) > 1:
@@ -926,9 +937,6 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "step_roofline": {"model_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (ms_step / 1e3) / 1e9,
                           "frac": step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
-        "step_roofline_unpruned_model": {
-            "model_bytes_per_step": unpruned_step_bytes(N, 8 if dtype == "f32" else 16),
-            "frac": unpruned_step_bytes(N, 8 if dtype == "f32" else 16) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "passes": passes,
         "tuned_columns": widths,
     }

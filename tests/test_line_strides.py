@@ -1,5 +1,5 @@
 """The per-line LDS strides of the FP32 z lines (LPz32 in csrc/impl.hpp) are
-the ones the bank model in csrc/zline_banks.py picks, and no stride lets two
+the ones the bank model in tests/zline_banks.py picks, and no stride lets two
 lines overlap."""
 import importlib.util
 import os
@@ -10,7 +10,8 @@ CSRC = os.path.join(ROOT, "paper_1607_00850_amd", "csrc")
 
 
 def _model():
-    spec = importlib.util.spec_from_file_location("zline_banks", os.path.join(CSRC, "zline_banks.py"))
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("zline_banks", os.path.join(here, "zline_banks.py"))
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
     return mod
