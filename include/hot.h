@@ -45,6 +45,7 @@ extern "C" {
 #define HOT_E_WORKSPACE (-3)   /* workspace pointer null or misaligned */
 #define HOT_E_HIP (-4)         /* a HIP call failed; hot_last_hip_error() has the code */
 #define HOT_E_NONFINITE (-5)   /* HOT_FLAG_CHECK_FINITE: a result holds a NaN or an infinity */
+#define HOT_E_TOOBIG (-7)      /* hot_run_noalloc: the plan's workspace exceeds the static scratch */
 #define HOT_E_NOCONVERGE (-6)  /* IMPLICIT: an instance hit max_iter sweeps (its last iterate is kept);
                                   reported by hot_implicit_stats, and by hot_run for CHECK_FINITE plans */
 
@@ -168,6 +169,19 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes);
  * instance stopped at max_iter), the first taking precedence. */
 int hot_run(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps, void* stats_dev,
             void* stream);
+
+/* hot_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation with the library's own static scratch, 16 MiB per device
+ * (held from the first use on a device until the process ends), as the
+ * workspace.  It calls no allocating routine.  Every call on a device shares
+ * that device's scratch, which keeps the last call's contents: calls that
+ * overlap on one device race (order them on one stream), and a plan with
+ * HOT_FLAG_KEEP_HISTORY is rejected (HOT_E_UNSUPPORTED).  Plans whose
+ * workspace (hot_plan's workspace_bytes) exceeds 16 MiB return HOT_E_TOOBIG;
+ * single instances up to N = 64 fit in FP32 and up to N = 48 in FP64 for
+ * RK4.  Per-pass profiling is not recorded.  Otherwise as hot_run. */
+int hot_run_noalloc(hot_plan_t p, void* const* in, void* const* out, int32_t nsteps, void* stats_dev, void* stream);
 
 /* A captured hot_run: the whole operation (every pass of every instance and
  * step) recorded once into a HIP graph and replayed with one launch.

@@ -20,6 +20,7 @@ HOT_E_WORKSPACE = -3
 HOT_E_HIP = -4
 HOT_E_NONFINITE = -5
 HOT_E_NOCONVERGE = -6
+HOT_E_TOOBIG = -7
 
 HOT_F64, HOT_F32 = 0, 1
 HOT_DEALIAS_TWO_THIRDS, HOT_DEALIAS_NONE = 0, 1
@@ -93,6 +94,8 @@ def _lib():
         lib.hot_plan.restype = ctypes.c_int
         lib.hot_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i32, vp, vp]
         lib.hot_run.restype = ctypes.c_int
+        lib.hot_run_noalloc.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp]
+        lib.hot_run_noalloc.restype = ctypes.c_int
         lib.hot_destroy.argtypes = [vp]
         lib.hot_destroy.restype = ctypes.c_int
         lib.hot_error_string.argtypes = [ctypes.c_int]
@@ -211,6 +214,20 @@ def hot_run(plan, ins, outs, workspace, nsteps=0, stream=None, stats=None):
     rc = _lib().hot_run(plan, pin, pout, _ptr(workspace), int(nsteps), _ptr(stats), stream)
     if rc not in (HOT_OK, HOT_E_NOCONVERGE, HOT_E_NONFINITE):
         raise HotError(rc, "hot_run", _lib().hot_last_hip_error(plan))
+    return rc
+
+
+def hot_run_noalloc(plan, ins, outs, nsteps=0, stream=None, stats=None):
+    """hot_run on the library's static 16 MiB scratch instead of a workspace
+    (for callers that cannot allocate).  Returns as hot_run; raises HotError
+    (code HOT_E_TOOBIG) for plans whose workspace does not fit."""
+    stream = _stream(stream)
+    n = len(ins)
+    pin = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
+    pout = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
+    rc = _lib().hot_run_noalloc(plan, pin, pout, int(nsteps), _ptr(stats), stream)
+    if rc not in (HOT_OK, HOT_E_NOCONVERGE, HOT_E_NONFINITE):
+        raise HotError(rc, "hot_run_noalloc", _lib().hot_last_hip_error(plan))
     return rc
 
 

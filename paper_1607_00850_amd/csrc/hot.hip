@@ -178,6 +178,7 @@ const char* hot_error_string(int code) {
     case HOT_E_HIP: return "HIP error";
     case HOT_E_NOCONVERGE: return "implicit step stopped at max_iter sweeps";
     case HOT_E_NONFINITE: return "result holds a NaN or an infinity";
+    case HOT_E_TOOBIG: return "plan needs more than the library's static scratch (hot_run_noalloc)";
     default: return "unknown error";
   }
 }
@@ -884,6 +885,56 @@ extern "C" int hot_run(hot_plan_t p, void* const* in, void* const* out, void* wo
     if (p->op == HOT_OP_IMPLICIT) return read_counters(p);
   }
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// hot_run without a caller workspace, for callers that cannot allocate
+// ---------------------------------------------------------------------------
+// The workspace lives in a file-scope device array; every device the library
+// runs on holds its own copy until the process ends.  On the host the array's
+// name is only a stand-in: its device address comes from hipGetSymbolAddress,
+// once per device, and only that address is handed to kernels.
+static constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+static int scratch_address(hot_plan_s* p, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess && (dev < 0 || dev >= kMaxDevices)) return HOT_E_UNSUPPORTED;
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e == hipSuccess && (!ptr || ((uintptr_t)ptr % kAlign) != 0)) e = hipErrorInvalidSymbol;
+      if (e == hipSuccess) g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+  }
+  if (e != hipSuccess) {
+    p->last_hip = (int)e;
+    return HOT_E_HIP;
+  }
+  return HOT_OK;
+}
+
+extern "C" int hot_run_noalloc(hot_plan_t p, void* const* in, void* const* out, int32_t nsteps, void* stats_dev,
+                               void* stream) {
+  if (!p) return HOT_E_INVALID;
+  if (p->ws_bytes > kScratchBytes) return HOT_E_TOOBIG;
+  // a kept history would not survive other calls through the shared scratch
+  if (p->flags & HOT_FLAG_KEEP_HISTORY) return HOT_E_UNSUPPORTED;
+  void* ws = nullptr;
+  const int rc = scratch_address(p, &ws);
+  if (rc != HOT_OK) return rc;
+  const bool prof = p->prof;
+  p->prof = false;  // no profiling events: nothing is created on this path
+  const int r = hot_run(p, in, out, ws, nsteps, stats_dev, stream);
+  p->prof = prof;
+  return r;
 }
 
 extern "C" int hot_graph_create(hot_plan_t p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
