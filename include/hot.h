@@ -186,7 +186,10 @@ int hot_run_noalloc(hot_plan_t p, void* const* in, void* const* out, int32_t nst
 /* A captured hot_run: the whole operation (every pass of every instance and
  * step) recorded once into a HIP graph and replayed with one launch.
  * hot_graph_create captures on stream, which must not be the legacy default
- * stream (NULL).  stats_dev: NULL or as for hot_run.  The graph keeps the
+ * stream (NULL).  With several distinct N each size is a branch of the graph
+ * (see the "graph" variant of hot_set_variant); the plan creates one side
+ * stream per size for the capture (default priority) and keeps them until
+ * hot_destroy.  stats_dev: NULL or as for hot_run.  The graph keeps the
  * pointers it was created with: a replay rewrites the pointer tables itself,
  * so hot_run calls with other arrays on the same workspace between replays
  * do not change what a replay reads and writes.  Per-pass profiling is
@@ -216,8 +219,14 @@ int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
 /* Set what hot_tune would choose, for every size of the plan: for a
  * column-tiled pass the width variant 0 (narrow), 1 (default) or 2 (wide);
  * for x_fwd_rk -1 (separate x_fwd and rk_stage passes), 0, 1 or 2 (fused,
- * at half, the default or a quarter of the default width).  Host only.
- * Errors: HOT_E_INVALID. */
+ * at half, the default or a quarter of the default width); for z_cross 1
+ * (the default: the y and z passes carry u and w as packed pairs of complex
+ * lines) or 0 (six separate component rows, the z pass completing the
+ * Hermitian halves itself); for "graph" (no kernel of its own) the layout of
+ * graphs hot_graph_create captures from then on: 1 (the default) one branch
+ * per distinct N, forked from and joined back into the capturing stream, so
+ * the passes of small sizes run beside those of large ones; 0 the sizes one
+ * after another.  Host only.  Errors: HOT_E_INVALID. */
 int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant);
 
 /* IMPLICIT statistics of the plan's last hot_run (or graph capture), per

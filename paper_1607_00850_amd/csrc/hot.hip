@@ -37,12 +37,13 @@ enum Pass : int {
   PASS_YZ_FUSED,
   PASS_TABLES,
   PASS_STATS,
+  PASS_GRAPH,  // no kernel: the layout of captured graphs (hot_set_variant)
   NUM_PASSES
 };
 
 static const char* kPassNames[NUM_PASSES] = {
     "gather", "x_inv_curl", "y_inv", "z_cross", "y_fwd", "x_fwd", "rk_stage", "scatter", "z_r2c", "z_c2r", "x_inv",
-    "imp_predict", "imp_update", "imp_decide", "imp_advance", "x_fwd_rk", "yz_fused", "tables", "stats",
+    "imp_predict", "imp_update", "imp_decide", "imp_advance", "x_fwd_rk", "yz_fused", "tables", "stats", "graph",
 };
 
 template <typename T>
@@ -120,6 +121,7 @@ struct Group {
   int rot = 0, hist = 0;                      // implicit step: buffer rotation, history depth
   int fused = -1;  // RK4/RHS: x_fwd_rk variant fusing the x pass with the stage update, -1 = separate passes
   int yz = -1;     // 0: the y and z passes fused (k_yz_fused), -1: y_inv, z_cross, y_fwd
+  bool zpack = false;  // the y and z passes on packed pair rows (hot_set_variant z_cross 1, the default)
   size_t bytes = 0;
   int variant[NUM_PASSES];  // strided column-width variant per pass (autotuned)
   int B() const { return (int)members.size(); }
@@ -160,6 +162,11 @@ struct hot_plan_s {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
+  // graph capture of several sizes: one side stream per group (a branch of the
+  // graph each) and the events of the fork and the join
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_ev;
+  bool graph_branches = true;  // hot_set_variant(graph_branches): 1 branch per group, 0 one chain
 };
 
 struct hot_graph_s {
@@ -290,6 +297,7 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
         return HOT_E_UNSUPPORTED;
       }
       G.g = make_geo(N, plain ? 2 : d->dealias, (int)p->elem);
+      G.zpack = !plain;
       for (int k = 0; k < NUM_PASSES; ++k) G.variant[k] = 1;
       p->groups.push_back(G);
       gp = &p->groups.back();
@@ -313,6 +321,8 @@ int hot_destroy(hot_plan_t p) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : p->pool) (void)hipEventDestroy(e);
+  for (auto e : p->side_ev) (void)hipEventDestroy(e);
+  for (auto st : p->side) (void)hipStreamDestroy(st);
   delete p;
   return HOT_OK;
 }
@@ -391,6 +401,7 @@ int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) 
     case PASS_YZ_FUSED: b = plain ? 0 : 6 * D1 + 3 * D1; break;
     case PASS_TABLES: b = 0; break;  // a few pointers per instance
     case PASS_STATS: b = plain ? 0 : 3 * C; break;  // reads the compact state once
+    case PASS_GRAPH: b = 0; break;
     default: return HOT_E_INVALID;
   }
   *bytes = b * e;
@@ -478,6 +489,37 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
   return q;
 }
 
+// The y inverse pass of a group (A1 -> A2), the z pass (in place on A2) and
+// the y forward pass (A2 -> A1): on packed pair rows where the group uses them.
+void y_inv_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
+  const long N = G.N, M = G.g.M, P = G.g.Mzp;
+  r.pass(PASS_Y_INV, [&] {
+    if (G.zpack)
+      return G.ops.y_inv_pack(r.s, G.variant[PASS_Y_INV], q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2,
+                              6 * G.D1, 6 * G.D2, G.B(), G.g, act);
+    return G.ops.strided(r.s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1,
+                         G.D2, 6, 6 * G.D1, 6 * G.D2, G.B(), G.g, act);
+  });
+}
+
+void z_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
+  r.pass(PASS_Z_CROSS, [&] {
+    return G.zpack ? G.ops.z_cross_packed(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act)
+                   : G.ops.z_cross(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act);
+  });
+}
+
+void y_fwd_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
+  const long N = G.N, M = G.g.M, P = G.g.Mzp;
+  r.pass(PASS_Y_FWD, [&] {
+    if (G.zpack)
+      return G.ops.y_fwd_unpack(r.s, G.variant[PASS_Y_FWD], q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1,
+                                6 * G.D2, 6 * G.D1, G.B(), G.g, act);
+    return G.ops.strided(r.s, G.variant[PASS_Y_FWD], -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2,
+                         G.D1, 3, 6 * G.D2, 6 * G.D1, G.B(), G.g, act);
+  });
+}
+
 // The inverse half of a right-hand side for every instance of a group: the x
 // pass (curl fused) from compact state `src`, then the y pass, into A2.
 void inverse_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, const int* act) {
@@ -490,10 +532,7 @@ void inverse_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* s
     return o.x_inv_curl(r.s, G.variant[PASS_X_INV_CURL], src, G.C, isU, q.A1, G.D1, isA1, nb, g, act);
   });
   // y inverse: 6 components, batch over x, rows ky (compact) -> y (all N)
-  r.pass(PASS_Y_INV, [&] {
-    return o.strided(r.s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1,
-                     G.D2, 6, isA1, isA2, nb, g, act);
-  });
+  y_inv_pass(r, G, q, act);
 }
 
 // The forward half after the z pass: the y pass from A2, then (x_fwd) the x
@@ -505,10 +544,7 @@ void forward_passes(Runner& r, const Group& G, const GroupPtrs& q, const int* ac
   const int nb = G.B();
   const long isU = 3 * G.C, isA1 = 6 * G.D1, isA2 = 6 * G.D2;
   // y forward: 3 components, y (all N) -> ky (compact)
-  r.pass(PASS_Y_FWD, [&] {
-    return o.strided(r.s, G.variant[PASS_Y_FWD], -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2,
-                     G.D1, 3, isA2, isA1, nb, g, act);
-  });
+  y_fwd_pass(r, G, q, act);
   // x forward: rows x (all N) -> kx (compact), columns (ky, kz)
   if (!x_fwd) return;
   r.pass(PASS_X_FWD, [&] {
@@ -524,7 +560,7 @@ void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, 
                 bool x_fwd = true) {
   if (G.yz < 0) {
     inverse_passes(r, G, q, src, act);
-    r.pass(PASS_Z_CROSS, [&] { return G.ops.z_cross(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act); });
+    z_pass(r, G, q, act);
     forward_passes(r, G, q, act, x_fwd);
     return;
   }
@@ -609,6 +645,37 @@ void state_stats(Runner& r, const hot_plan_s* p, const Group& G, const GroupPtrs
   });
 }
 
+// Branches: when `fork` is set and the plan has several groups, every group
+// runs on its own side stream, forked from and joined back into the calling
+// stream with events.  Under graph capture this gives one branch per size, so
+// the passes of small sizes run beside those of large ones.
+hipError_t fork_groups(hot_plan_s* p, hipStream_t s) {
+  const size_t ng = p->groups.size();
+  hipError_t e = hipSuccess;
+  while (e == hipSuccess && p->side.size() < ng) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);  // default priority
+    if (e == hipSuccess) p->side.push_back(st);
+  }
+  while (e == hipSuccess && p->side_ev.size() < ng + 1) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) p->side_ev.push_back(ev);
+  }
+  if (e == hipSuccess) e = hipEventRecord(p->side_ev[ng], s);
+  for (size_t g = 0; g < ng && e == hipSuccess; ++g) e = hipStreamWaitEvent(p->side[g], p->side_ev[ng], 0);
+  return e;
+}
+
+hipError_t join_groups(hot_plan_s* p, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (size_t g = 0; g < p->groups.size() && e == hipSuccess; ++g) {
+    e = hipEventRecord(p->side_ev[g], p->side[g]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->side_ev[g], 0);
+  }
+  return e;
+}
+
 int check_run_args(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
                    const void* stats) {
   if (!p || !in || !out || nsteps < 0) return HOT_E_INVALID;
@@ -623,7 +690,7 @@ int check_run_args(hot_plan_s* p, void* const* in, void* const* out, void* works
 
 // Enqueue the whole operation (the pointer tables are already in place).
 int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t stream,
-            bool record, StatsRec* stats) {
+            bool record, StatsRec* stats, bool branches = false) {
   Runner r{p, stream, record};
   const size_t e = p->elem;
   if (p->op == HOT_OP_R2C || p->op == HOT_OP_C2R) {
@@ -661,9 +728,20 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
     return r.rc;
   }
   // right-hand side / RK4: group by group (a small group's working set can
-  // stay in the device's last-level cache between its passes)
-  for (const auto& G : p->groups) {
+  // stay in the device's last-level cache between its passes), or one branch
+  // per group
+  const bool br = branches && p->groups.size() > 1;
+  if (br) {
+    const hipError_t e = fork_groups(p, stream);
+    if (e != hipSuccess) {
+      p->last_hip = (int)e;
+      return HOT_E_HIP;
+    }
+  }
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    const Group& G = p->groups[gi];
     if (r.rc != HOT_OK) break;
+    r.s = br ? p->side[gi] : stream;
     const GroupPtrs q = group_ptrs(G, workspace);
     const Ops& o = G.ops;
     const Geo& g = G.g;
@@ -684,6 +762,13 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
     // the state: the input of a right-hand side, the result of RK4 steps
     if (stats) state_stats(r, p, G, q, q.U0, stats, false);
   }
+  if (br) {
+    const hipError_t e = join_groups(p, stream);
+    if (e != hipSuccess && r.rc == HOT_OK) {
+      p->last_hip = (int)e;
+      r.rc = HOT_E_HIP;
+    }
+  }
   return r.rc;
 }
 
@@ -696,11 +781,21 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
 // in Acc and the two increment histories in H1, H2; the three buffers rotate
 // at the end of a step (d becomes the newest history).
 int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t s,
-                 bool record, StatsRec* stats) {
+                 bool record, StatsRec* stats, bool branches = false) {
   Runner r{p, s, record};
   const bool keep = (p->flags & HOT_FLAG_KEEP_HISTORY) && p->hist_ws == workspace;
-  for (auto& G : p->groups) {
+  const bool br = branches && p->groups.size() > 1;
+  if (br) {
+    const hipError_t e = fork_groups(p, s);
+    if (e != hipSuccess) {
+      p->last_hip = (int)e;
+      return HOT_E_HIP;
+    }
+  }
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    Group& G = p->groups[gi];
     if (r.rc != HOT_OK) break;
+    r.s = br ? p->side[gi] : s;
     if (!keep) {
       G.rot = 0;
       G.hist = 0;
@@ -756,6 +851,13 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
     }
     r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.U0, out0, q.out_tab, G.C, isU, nb, g); });
     if (stats) state_stats(r, p, G, q, q.U0, stats, true);
+  }
+  if (br) {
+    const hipError_t e = join_groups(p, s);
+    if (e != hipSuccess && r.rc == HOT_OK) {
+      p->last_hip = (int)e;
+      r.rc = HOT_E_HIP;
+    }
   }
   p->hist_ws = workspace;
   p->cnt_ws = workspace;
@@ -951,8 +1053,8 @@ extern "C" int hot_graph_create(hot_plan_t p, void* const* in, void* const* out,
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     StatsRec* stats = (StatsRec*)stats_dev;
-    rc = p->op == HOT_OP_IMPLICIT ? run_implicit(p, in, out, workspace, nsteps, s, false, stats)
-                                  : enqueue(p, in, out, workspace, nsteps, s, false, stats);
+    rc = p->op == HOT_OP_IMPLICIT ? run_implicit(p, in, out, workspace, nsteps, s, false, stats, p->graph_branches)
+                                  : enqueue(p, in, out, workspace, nsteps, s, false, stats, p->graph_branches);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s, &g);
     G->graph = g;
@@ -1005,8 +1107,11 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
     for (int pid : pass_ids) {
       float best = 1e30f;
       int best_v = 1;
-      for (int v = 0; v < G.ops.strided_variants && rc == HOT_OK; ++v) {
-        if (v != 1 && G.ops.strided_width[v] == G.ops.strided_width[1]) continue;  // same kernel
+      // the packed y forward pass also comes with one output per block (variants 3..5)
+      const int nv = (pid == PASS_Y_FWD && G.zpack) ? 2 * G.ops.strided_variants : G.ops.strided_variants;
+      for (int v = 0; v < nv && rc == HOT_OK; ++v) {
+        const int w = v % G.ops.strided_variants;
+        if (w != 1 && G.ops.strided_width[w] == G.ops.strided_width[1]) continue;  // same kernel
         G.variant[pid] = v;
         float t = 0.f;
         for (int rep = 0; rep <= reps && rc == HOT_OK; ++rep) {
@@ -1019,9 +1124,15 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
           r.pass(pid, [&] {
             if (pid == PASS_X_INV_CURL)
               return G.ops.x_inv_curl(s, v, q.U0, G.C, isU, q.A1, G.D1, isA1, G.B(), g, nullptr);
+            if (pid == PASS_Y_INV && G.zpack)
+              return G.ops.y_inv_pack(s, v, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2, isA1, isA2,
+                                      G.B(), g, nullptr);
             if (pid == PASS_Y_INV)
               return G.ops.strided(s, v, +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2, 6,
                                    isA1, isA2, G.B(), g, nullptr);
+            if (pid == PASS_Y_FWD && G.zpack)
+              return G.ops.y_fwd_unpack(s, v, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1, isA2, isA1,
+                                        G.B(), g, nullptr);
             if (pid == PASS_Y_FWD)
               return G.ops.strided(s, v, -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1, 3,
                                    isA2, isA1, G.B(), g, nullptr);
@@ -1057,17 +1168,9 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
           Runner r{p, s, false};
           if (rep == 1) (void)hipEventRecord(a, s);
           if (yv < 0) {
-            const long N = G.N, M = G.g.M, P = G.g.Mzp;
-            const int nb = G.B();
-            r.pass(PASS_Y_INV, [&] {
-              return G.ops.strided(s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P,
-                                   N * P, G.D1, G.D2, 6, 6 * G.D1, 6 * G.D2, nb, G.g, nullptr);
-            });
-            r.pass(PASS_Z_CROSS, [&] { return G.ops.z_cross(s, q.A2, G.D2, 6 * G.D2, N * N, nb, G.g, nullptr); });
-            r.pass(PASS_Y_FWD, [&] {
-              return G.ops.strided(s, G.variant[PASS_Y_FWD], -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P,
-                                   M * P, G.D2, G.D1, 3, 6 * G.D2, 6 * G.D1, nb, G.g, nullptr);
-            });
+            y_inv_pass(r, G, q, nullptr);
+            z_pass(r, G, q, nullptr);
+            y_fwd_pass(r, G, q, nullptr);
           } else {
             r.pass(PASS_YZ_FUSED, [&] { return G.ops.yz_fused(s, q.A1, G.D1, 6 * G.D1, G.B(), G.g, nullptr); });
           }
@@ -1095,8 +1198,8 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
       float best = 1e30f;
       int best_f = -1;
       for (int f = -1; f < 3 && rc == HOT_OK; ++f) {
-        if (f == 0 && G.ops.strided_width[0] == G.ops.strided_width[1]) continue;  // same kernel as f = 1
-        if (f == 2 && G.ops.fused_quarter_width == G.ops.strided_width[0]) continue;  // same kernel as f = 0
+        if (f == 0 && G.ops.fused_width[0] == G.ops.fused_width[1]) continue;  // same kernel as f = 1
+        if (f == 2 && G.ops.fused_width[2] == G.ops.fused_width[0]) continue;  // same kernel as f = 0
         G.fused = f;
         float t = 0.f;
         for (int rep = 0; rep <= reps && rc == HOT_OK; ++rep) {
@@ -1150,13 +1253,25 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
     for (auto& G : p->groups) G.fused = variant;
     return HOT_OK;
   }
+  if (pass == PASS_GRAPH) {  // 1: one branch per size (default), 0: the sizes one after another
+    if (variant < 0 || variant > 1) return HOT_E_INVALID;
+    p->graph_branches = variant == 1;
+    return HOT_OK;
+  }
+  if (pass == PASS_Z_CROSS) {  // 1: packed pair rows (default), 0: six component rows
+    const bool plain = p->op == HOT_OP_R2C || p->op == HOT_OP_C2R;
+    if (variant < 0 || variant > 1 || plain) return HOT_E_INVALID;
+    for (auto& G : p->groups) G.zpack = variant == 1;
+    return HOT_OK;
+  }
   if (pass == PASS_YZ_FUSED) {  // 0: fused wherever a size has the kernel
     const bool plain = p->op == HOT_OP_R2C || p->op == HOT_OP_C2R;
     if (variant < -1 || variant > 0 || plain || p->nranks > 1) return HOT_E_INVALID;
     for (auto& G : p->groups) G.yz = (variant == 0 && G.ops.yz_fused) ? 0 : -1;
     return HOT_OK;
   }
-  if (!tiled || variant < 0 || variant > 2) return HOT_E_INVALID;
+  // the y forward pass takes 3..5 too: the same widths, one output per block
+  if (!tiled || variant < 0 || variant > (pass == PASS_Y_FWD ? 5 : 2)) return HOT_E_INVALID;
   for (auto& G : p->groups) G.variant[pass] = variant;
   return HOT_OK;
 }
@@ -1166,9 +1281,11 @@ extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
   for (const auto& G : p->groups)
     if (G.N == p->n[instance]) {
       if (pass == PASS_X_FWD_RK)
-        return G.fused < 0 ? 0 : (G.fused == 2 ? G.ops.fused_quarter_width : G.ops.strided_width[G.fused]);
+        return G.fused < 0 ? 0 : G.ops.fused_width[G.fused];
       if (pass == PASS_YZ_FUSED) return G.yz < 0 ? 0 : 1;
-      return G.ops.strided_width[G.variant[pass]];
+      if (pass == PASS_Z_CROSS) return G.zpack ? 1 : 0;
+      if (pass == PASS_GRAPH) return p->graph_branches ? 1 : 0;
+      return G.ops.strided_width[G.variant[pass] % 3];
     }
   return HOT_E_INVALID;
 }
@@ -1261,7 +1378,10 @@ extern "C" int hot_slab_run(hot_plan_t p, int32_t phase, int32_t stage, const vo
       break;
     case HOT_SLAB_CROSS: {
       const long lines = (long)p->nx * G.N, blk = lines * G.g.Mzp;
-      r.pass(PASS_Z_CROSS, [&] { return o.z_cross_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk); });
+      r.pass(PASS_Z_CROSS, [&] {
+        return G.zpack ? o.z_cross_packed_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk)
+                       : o.z_cross_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk);
+      });
       break;
     }
     case HOT_SLAB_FORWARD:

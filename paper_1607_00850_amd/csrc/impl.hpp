@@ -34,6 +34,15 @@ template <> struct LP<36> { using P = LinePlan<36, 6, 6, 6>; };
 template <> struct LP<48> { using P = LinePlan<48, 12, 4, 4, 3>; };
 template <> struct LP<54> { using P = LinePlan<54, 6, 6, 3, 3>; };
 
+// line plans of the x forward pass fused with the stage update: it holds three
+// components per thread, so long lines spread over twice the lanes (half the
+// registers per component, one more exchange)
+template <int N>
+struct LPf {
+  using P = typename LP<N>::P;
+};
+template <> struct LPf<1024> { using P = LinePlan<1024, 8, 8, 8, 4, 4>; };
+
 // line plans of the z passes (one line per Tl lanes; see ZShape)
 template <int N>
 struct LPz {
@@ -84,9 +93,21 @@ struct Ops {
   hipError_t (*x_inv_curl)(hipStream_t, int variant, const void* U, long csU, long isU, void* A, long csA, long isA,
                            int nb, const Geo&, const int* act);
   hipError_t (*z_cross)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&, const int* act);
+  // the y inverse, z and y forward passes on packed pair rows (k_y_inv_pack,
+  // k_z_cross_packed, k_y_fwd_unpack); strided-pass arguments without the
+  // direction, row kinds and component count
+  hipError_t (*y_inv_pack)(hipStream_t, int variant, const void* in, void* out, long ncols, long Qp, long ld_in,
+                           long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, long is_in, long is_out,
+                           int nb, const Geo&, const int* act);
+  hipError_t (*z_cross_packed)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&,
+                               const int* act);
+  hipError_t (*y_fwd_unpack)(hipStream_t, int variant, const void* in, void* out, long ncols, long Qp, long ld_in,
+                             long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, long is_in, long is_out,
+                             int nb, const Geo&, const int* act);
   // z_cross on lines that arrive in chunks of `chunk` coefficients, blocks blk
   // elements apart (the receive buffer of a z-slab all-to-all)
   hipError_t (*z_cross_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk);
+  hipError_t (*z_cross_packed_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk);
   // y inverse, z pass and y forward in one kernel, in place on A1 (NULL where
   // the six planes of an x-plane do not fit in LDS)
   hipError_t (*yz_fused)(hipStream_t, void* A, long csA, long isA, int nb, const Geo&, const int* act);
@@ -109,7 +130,7 @@ struct Ops {
   hipError_t (*imp_advance)(hipStream_t, void* U0, const void* D, long C, long is, int nb, const Geo&);
   int strided_variants;       // number of column widths the autotuner may pick from
   int strided_width[3];       // columns per block of each variant
-  int fused_quarter_width;    // columns per block of x_fwd_rk variant 2
+  int fused_width[3];         // columns per block of the x_fwd_rk variants 0, 1, 2
 };
 
 static inline unsigned grid_1d(long work, int block) {
@@ -177,25 +198,28 @@ struct Impl {
   }
   // short FP32 lines: all six outputs of a tile in one block (k_x_inv_curl6)
   static constexpr bool kCurl6 = std::is_same_v<T, float> && N <= 64;
+  // 1/N^3 of the inverse transform (Eq. ffteq), applied to u and w by the x pass
+  static constexpr double kUsc = 1.0 / (double(N) * N * N);
   template <int WW>
   static hipError_t x_inv_curl_w(hipStream_t s, const void* U, long csU, long isU, void* A, long csA, long isA,
                                  int nb, const Geo& g, const int* act) {
+    const T usc = T(kUsc);
     const long Q = (long)g.M * g.Mzp;
     const int ntiles = (int)((Q + WW - 1) / WW);
     constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
     const unsigned ngrp = (unsigned)((ntiles + 8 * pair - 1) / (8 * pair) * pair);
     if constexpr (kCurl6) {
       hipLaunchKernelGGL((k_x_inv_curl6<T, P, WW>), dim3(8u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
-                         (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
+                         (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
     } else {
       // registers that can hold a retained row: the 2/3-rule count, or all
       constexpr int KL23 = (((N - 1) / 3 + 1) + Tl - 1) / Tl;
       if (g.lo <= KL23 * Tl && g.hi <= KL23 * Tl)
         hipLaunchKernelGGL((k_x_inv_curl3<T, P, WW, KL23>), dim3(8u * 3u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
-                           (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
+                           (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
       else
         hipLaunchKernelGGL((k_x_inv_curl3<T, P, WW, P::R>), dim3(8u * 3u * ngrp, (unsigned)nb), dim3(WW * Tl), 0,
-                           s, (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, act);
+                           s, (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
     }
     return hipGetLastError();
   }
@@ -213,17 +237,15 @@ struct Impl {
   static hipError_t z_cross_za(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
                                const int* act, ZA za) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
-    const double n3 = double(N) * N * N;
-    const T scale = T(1.0 / (n3 * n3));
     const dim3 grid(nblk, (unsigned)nb);
     // coefficients per lane: the 2/3-rule count, or the all-but-Nyquist one
     constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
     if (g.Mz <= KL23 * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, scale,
-                         act, za);
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KL23, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, act,
+                         za);
     else if (g.Mz <= KLall * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g,
-                         scale, act, za);
+      hipLaunchKernelGGL((k_z_cross<T, PZ, KLall, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g, act,
+                         za);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
@@ -232,27 +254,96 @@ struct Impl {
                             const int* act) {
     return z_cross_za(s, A, csA, isA, nlines, nb, g, act, ZContig{});
   }
+  template <class ZA>
+  static hipError_t z_cross_packed_za(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
+                                      const int* act, ZA za) {
+    const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
+    const dim3 grid(nblk, (unsigned)nb);
+    constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
+    if (g.Mz <= KL23 * PZ::Tl)
+      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KL23, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g,
+                         act, za);
+    else if (g.Mz <= KLall * PZ::Tl)
+      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KLall, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g,
+                         act, za);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  static hipError_t z_cross_packed(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
+                                   const int* act) {
+    return z_cross_packed_za(s, A, csA, isA, nlines, nb, g, act, ZContig{});
+  }
+  // the y passes on packed rows: a grid like k_strided's, with blockIdx.y
+  // the component pair (3 for the inverse, 2 for the forward)
+  template <int WW, bool INV>
+  static hipError_t ypack_w(hipStream_t s, const void* in, void* out, long ncols, long Qp, long ld_in, long ld_out,
+                            long bs_in, long bs_out, long cs_in, long cs_out, long is_in, long is_out, int nb,
+                            const Geo& g, const int* act, bool single) {
+    constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
+    const long ntiles = (ncols + WW - 1) / WW;
+    const long group = 8L * pair;
+    if (!INV && single) {  // one output per block, the three blocks of a tile consecutive on one XCD
+      constexpr int KL23 = (((N - 1) / 3 + 1) + Tl - 1) / Tl;
+      const dim3 grid3((unsigned)(3 * ((ntiles + group - 1) / group * group)), (unsigned)nb);
+      if (g.lo <= KL23 * Tl && g.hi <= KL23 * Tl)
+        hipLaunchKernelGGL((k_y_fwd_unpack3<T, P, WW, KL23>), grid3, dim3(WW * Tl), 0, s, (const cx<T>*)in,
+                           (cx<T>*)out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in, is_out, g, act);
+      else
+        hipLaunchKernelGGL((k_y_fwd_unpack3<T, P, WW, P::R>), grid3, dim3(WW * Tl), 0, s, (const cx<T>*)in,
+                           (cx<T>*)out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in, is_out, g, act);
+      return hipGetLastError();
+    }
+    const dim3 grid((unsigned)((ntiles + group - 1) / group * group), INV ? 3u : 2u, (unsigned)nb);
+    constexpr int KL23 = (((N - 1) / 3 + 1) + Tl - 1) / Tl;
+    const bool cut = g.lo <= KL23 * Tl && g.hi <= KL23 * Tl;
+#define HOT_YP(K)                                                                                                  \
+  hipLaunchKernelGGL((INV ? k_y_inv_pack<T, P, WW, K> : k_y_fwd_unpack<T, P, WW, K>), grid, dim3(WW * Tl), 0, s, \
+                     (const cx<T>*)in, (cx<T>*)out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in,  \
+                     is_out, g, act)
+    if (cut) HOT_YP(KL23);
+    else HOT_YP(P::R);
+#undef HOT_YP
+    return hipGetLastError();
+  }
+  template <bool INV>
+  static hipError_t ypack(hipStream_t s, int variant, const void* in, void* out, long ncols, long Qp, long ld_in,
+                          long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, long is_in, long is_out,
+                          int nb, const Geo& g, const int* act) {
+    const bool single = variant >= 3;  // y forward: one output per block
+    switch (variant % 3) {
+      case 0: return ypack_w<WV0, INV>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in,
+                                       is_out, nb, g, act, single);
+      case 2: return ypack_w<WV2, INV>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in,
+                                       is_out, nb, g, act, single);
+      default: return ypack_w<W, INV>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in,
+                                      is_out, nb, g, act, single);
+    }
+  }
   static hipError_t z_cross_blocked(hipStream_t s, void* A, long csA, long nlines, const Geo& g, int chunk,
                                     long blk) {
     if (chunk < 1) return hipErrorInvalidValue;
     return z_cross_za(s, A, csA, 0, nlines, 1, g, nullptr, ZBlocked{chunk, 1.0f / (float)chunk, blk});
   }
+  static hipError_t z_cross_packed_blocked(hipStream_t s, void* A, long csA, long nlines, const Geo& g, int chunk,
+                                           long blk) {
+    if (chunk < 1) return hipErrorInvalidValue;
+    return z_cross_packed_za(s, A, csA, 0, nlines, 1, g, nullptr, ZBlocked{chunk, 1.0f / (float)chunk, blk});
+  }
   static constexpr bool kYz = N <= 64 && YzShape<T, PZ>::kFits;
   static hipError_t yz_fused(hipStream_t s, void* A, long csA, long isA, int nb, const Geo& g, const int* act) {
     if constexpr (kYz) {
-      const double n3 = double(N) * N * N;
-      const T scale = T(1.0 / (n3 * n3));
       const size_t lds = (size_t)YzShape<T, PZ>::lds_bytes(g.Mz);
       const dim3 grid((unsigned)N, (unsigned)nb);
       constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
       if (g.Mz <= KL23 * PZ::Tl) {
         (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KL23>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_yz_fused<T, PZ, KL23>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA, isA, g, scale, act);
+        hipLaunchKernelGGL((k_yz_fused<T, PZ, KL23>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA, isA, g, act);
       } else if (g.Mz <= KLall * PZ::Tl) {
         (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KLall>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_yz_fused<T, PZ, KLall>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA, isA, g, scale, act);
+        hipLaunchKernelGGL((k_yz_fused<T, PZ, KLall>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA, isA, g, act);
       } else {
         return hipErrorInvalidValue;
       }
@@ -279,6 +370,8 @@ struct Impl {
                        (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, is, g, mode, T(nu), T(dt));
     return hipGetLastError();
   }
+  using PF = typename LPf<N>::P;
+  static constexpr int TlF = PF::Tl;
   template <int WW>
   static hipError_t x_fwd_rk_w(hipStream_t s, const void* A, long csA, long isA, void* U0, void* U1, void* Acc,
                                long C, long isU, int nb, const Geo& g, int mode, double nu, double dt) {
@@ -288,23 +381,26 @@ struct Impl {
     const long group = 8L * pair;
     const dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)nb);
     // registers that can hold a retained row: the 2/3-rule count, or all
-    constexpr int KL23 = (((N - 1) / 3 + 1) + Tl - 1) / Tl;
-    if (g.lo <= KL23 * Tl && g.hi <= KL23 * Tl)
-      hipLaunchKernelGGL((k_x_fwd_rk<T, P, WW, KL23>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)A, csA, isA,
+    constexpr int KL23 = (((N - 1) / 3 + 1) + TlF - 1) / TlF;
+    if (g.lo <= KL23 * TlF && g.hi <= KL23 * TlF)
+      hipLaunchKernelGGL((k_x_fwd_rk<T, PF, WW, KL23>), grid, dim3(WW * TlF), 0, s, (const cx<T>*)A, csA, isA,
                          (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
     else
-      hipLaunchKernelGGL((k_x_fwd_rk<T, P, WW, P::R>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)A, csA, isA,
+      hipLaunchKernelGGL((k_x_fwd_rk<T, PF, WW, PF::R>), grid, dim3(WW * TlF), 0, s, (const cx<T>*)A, csA, isA,
                          (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
     return hipGetLastError();
   }
-  // fused variants: W/2, W and W/4 (three components in registers); W/4 only
-  // where it still makes a whole wave
-  static constexpr int WQ = fits(W / 4) ? W / 4 : WV0;
+  // fused variants: W/2, W and W/4 columns per block (three components in
+  // registers), within 1024 threads and at least one wave
+  static constexpr bool fitsF(int w) { return w >= 1 && w * TlF <= 1024 && w * TlF >= 64; }
+  static constexpr int WF = fitsF(W) ? W : W / 2;
+  static constexpr int WF0 = fitsF(WF / 2) ? WF / 2 : WF;
+  static constexpr int WQ = fitsF(WF / 4) ? WF / 4 : WF0;
   static hipError_t x_fwd_rk(hipStream_t s, int variant, const void* A, long csA, long isA, void* U0, void* U1,
                              void* Acc, long C, long isU, int nb, const Geo& g, int mode, double nu, double dt) {
-    if (variant == 0) return x_fwd_rk_w<WV0>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
+    if (variant == 0) return x_fwd_rk_w<WF0>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
     if (variant == 2) return x_fwd_rk_w<WQ>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
-    return x_fwd_rk_w<W>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
+    return x_fwd_rk_w<WF>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
   }
   static hipError_t gather(hipStream_t s, const void* in0, const void* const* in_tab, void* out, long C, long is,
                            int nb, const Geo& g) {
@@ -339,10 +435,10 @@ struct Impl {
     return hipGetLastError();
   }
   static Ops ops() {
-    return Ops{&strided,     &x_inv_curl, &z_cross,    &z_cross_blocked,
+    return Ops{&strided,     &x_inv_curl, &z_cross,    &ypack<true>, &z_cross_packed, &ypack<false>, &z_cross_blocked, &z_cross_packed_blocked,
                kYz ? &yz_fused : nullptr,   &z_c2r,      &z_r2c,      &rk_stage,
                &x_fwd_rk,    &gather,     &scatter,    &imp_predict,
-               &imp_update,  &imp_advance, 3,          {WV0, W, WV2}, WQ};
+               &imp_update,  &imp_advance, 3,          {WV0, W, WV2}, {WF0, WF, WQ}};
   }
 };
 

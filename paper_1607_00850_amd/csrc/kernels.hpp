@@ -234,15 +234,19 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
 // P1: inverse transform along x of the velocity and of the vorticity
 // omega_hat = i k x u_hat (curl fused into the load).  Input compact state
 // U[3][M rows (kx)][Q = M*Mzp cols (ky,kz)], output A[6][N rows (x)][Q] with
-// components (u_x, u_y, u_z, w_x, w_y, w_z).  One block per (tile, output
-// component); the 6 components of a tile go to blocks with equal b mod 8
-// (one XCD) so that their shared input rows are read from HBM once and then
-// served by that XCD's L2.  blockIdx.y is the instance of a batch.
+// components (u_x, u_y, u_z, w_x, w_y, w_z).  Every output carries the factor
+// usc = 1/N^3 of the inverse transform of Eq. ffteq, so the z pass multiplies
+// nothing (u and w enter its cross product already normalised; they share
+// complex lines there, so they must share the scale too).
+// One block per (tile, output component); the 6 components of a tile go to
+// blocks with equal b mod 8 (one XCD) so that their shared input rows are
+// read from HBM once and then served by that XCD's L2.  blockIdx.y is the
+// instance of a batch.
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int W>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restrict__ U, long csU, long isU,
                                                             cx<T>* __restrict__ A, long csA, long isA,
-                                                            int ntiles, Geo g, const int* __restrict__ act) {
+                                                            int ntiles, Geo g, T usc, const int* __restrict__ act) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
       const int p = j + s * Tl;
       const bool kp = valid && kept(p, g);
       const cx<T> x = pa[kp ? (long)crow(p, g) * Q : 0];
-      v[s] = kp ? x : cx<T>{T(0), T(0)};
+      v[s] = kp ? x * usc : cx<T>{T(0), T(0)};
     });
   } else {
     static_for<0, R>([&](auto s) {
@@ -292,8 +296,8 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
       const long off = kp ? (long)crow(p, g) * Q : 0;
       const cx<T> a = pa[off], b = pb[off];
       const T kx = T(kwave(p, N));
-      const T fa = o == 3 ? ky : (o == 4 ? kzf : kx);
-      const T fb = o == 3 ? kzf : (o == 4 ? kx : ky);
+      const T fa = (o == 3 ? ky : (o == 4 ? kzf : kx)) * usc;
+      const T fb = (o == 3 ? kzf : (o == 4 ? kx : ky)) * usc;
       v[s] = kp ? mul_i(a * fa - b * fb) : cx<T>{T(0), T(0)};
     });
   }
@@ -324,7 +328,7 @@ constexpr bool col_live(int s) {
 template <typename T, class Plan, int W, int KL>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl3(const cx<T>* __restrict__ U, long csU, long isU,
                                                              cx<T>* __restrict__ A, long csA, long isA,
-                                                             int ntiles, Geo g, const int* __restrict__ act) {
+                                                             int ntiles, Geo g, T usc, const int* __restrict__ act) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
@@ -363,9 +367,9 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl3(const cx<T>* __rest
       const long off = kp ? (long)crow(p, g) * Q : 0;
       const cx<T> x = pa[off], y = pb[off];
       const T kx = T(kwave(p, N));
-      const T km = m == 0 ? kx : (m == 1 ? ky : kzf);
-      const T kn = m == 0 ? ky : (m == 1 ? kzf : kx);
-      a[s] = kp ? x : cx<T>{T(0), T(0)};
+      const T km = (m == 0 ? kx : (m == 1 ? ky : kzf)) * usc;
+      const T kn = (m == 0 ? ky : (m == 1 ? kzf : kx)) * usc;
+      a[s] = kp ? x * usc : cx<T>{T(0), T(0)};
       v[s] = kp ? mul_i(y * km - x * kn) : cx<T>{T(0), T(0)};
     } else {
       a[s] = cx<T>{T(0), T(0)};
@@ -396,7 +400,7 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl3(const cx<T>* __rest
 template <typename T, class Plan, int W>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __restrict__ U, long csU, long isU,
                                                              cx<T>* __restrict__ A, long csA, long isA,
-                                                             int ntiles, Geo g, const int* __restrict__ act) {
+                                                             int ntiles, Geo g, T usc, const int* __restrict__ act) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
@@ -426,7 +430,7 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __rest
       const int p = j + s * Tl;
       const bool kp = valid && kept(p, g);
       const cx<T> x = U[comp * csU + qq + (kp ? (long)crow(p, g) * Q : 0)];
-      u[comp][s] = kp ? x : cx<T>{T(0), T(0)};
+      u[comp][s] = kp ? x * usc : cx<T>{T(0), T(0)};
     });
   });
   tw.put(tws, tid);
@@ -538,8 +542,9 @@ __device__ __forceinline__ void load_line(cx<T> (&la)[KL], const cx<T>* __restri
 // ---------------------------------------------------------------------------
 // P3: per z-line, inverse real transforms of u and omega (three complex FFTs,
 // two real lines each), the cross product c = u x omega (component formula of
-// Sec. 3.4) scaled by 1/N^6 (the 1/N^3 of Eq. ffteq for each factor), and the
-// forward real transform of c (c0 + i c1 in one FFT, c2 in another).
+// Sec. 3.4; both factors already carry the 1/N^3 of Eq. ffteq, applied by
+// the x pass), and the forward real transform of c (c0 + i c1 in one FFT,
+// c2 in another).
 // In place: reads components 0..5 of the line, writes 0..2.  The loads of the
 // next component pair are issued before the current pair's FFT.  ZA places
 // the coefficients of a line (ZContig: one row; ZBlocked: the chunks of a
@@ -547,7 +552,7 @@ __device__ __forceinline__ void load_line(cx<T> (&la)[KL], const cx<T>* __restri
 // ---------------------------------------------------------------------------
 template <typename T, class Plan, int KL, class ZA>
 __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA, long isA, long nlines, Geo g,
-                                                 T scale, const int* __restrict__ act, ZA za) {
+                                                 const int* __restrict__ act, ZA za) {
   if (act && !act[blockIdx.y]) return;  // instance no longer iterating
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
@@ -591,8 +596,8 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
   static_for<0, R>([&](auto s) {
     const T u0 = ph[0][s].x, u1 = ph[0][s].y, u2 = ph[1][s].x;
     const T w0 = ph[1][s].y, w1 = ph[2][s].x, w2 = ph[2][s].y;
-    z01[s] = {(u1 * w2 - u2 * w1) * scale, (u2 * w0 - u0 * w2) * scale};
-    z2[s] = {(u0 * w1 - u1 * w0) * scale, T(0)};
+    z01[s] = {u1 * w2 - u2 * w1, u2 * w0 - u0 * w2};
+    z2[s] = {u0 * w1 - u1 * w0, T(0)};
   });
   Plan::template fft<T, -1>(z2, j, lds, tw);
   Plan::template fft<T, -1>(z01, j, lds, tw);
@@ -616,6 +621,298 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
       }
     });
   }
+}
+
+// ---------------------------------------------------------------------------
+// Packed pair rows.  A real z line f has the half spectrum f_k, k < Mz; two
+// real lines a, b travel through one complex transform as Z = a + i b, whose
+// spectrum on the full circle is Z_k = a_k + i b_k and Z_{N-k} =
+// conj(a_k) + i conj(b_k).  With packed rows the two halves of that circle
+// are stored as two rows of the same shape as a half spectrum:
+//   row A[k] = Z_k = a_k + i b_k,   row B[k] = Z_{N-k} = conj(a_k) + i conj(b_k),
+// k < Mz (at k = 0 the imaginary parts of a_0 and b_0 are dropped, as in any
+// real inverse transform).  The y inverse pass writes them for the pairs
+// (u_x, u_y), (u_z, w_x), (w_y, w_z) in place of the six components, so the
+// z pass loads each complex line straight into its transform registers, with
+// no Hermitian completion in LDS; after the forward transform of
+// c0 + i c1 the z pass stores the two halves of its circle the same way, and
+// the y forward pass separates c0_k = (A_k + conj B_k)/2 and
+// c1_k = (A_k - conj B_k)/(2i) on load.  The bytes moved are those of six
+// (three) component rows, as before.
+// ---------------------------------------------------------------------------
+
+// y inverse on pairs: component pair P = blockIdx.y (inputs 2P, 2P+1 of the
+// compact-row array), transformed along the columns' rows, written as the
+// packed rows A (component 2P) and B (component 2P + 1).  Arguments as
+// k_strided with IN_C = true, OUT_C = false; KL as col_live.
+template <typename T, class Plan, int W, int KL>
+__global__ __launch_bounds__(W* Plan::Tl) void k_y_inv_pack(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                            long ncols, long Qp, long ld_in, long ld_out, long bs_in,
+                                                            long bs_out, long cs_in, long cs_out, long is_in,
+                                                            long is_out, Geo g, const int* __restrict__ act) {
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+  __shared__ cx<T> sm[N * W];
+  __shared__ cx<T> tws[N];
+  const long tile = tile_of_block<PAIR>(blockIdx.x);
+  if (tile * W >= ncols) return;          // whole block leaves together
+  if (act && !act[blockIdx.z]) return;  // instance no longer iterating
+  const int tid = threadIdx.x;
+  TwStage<T, Plan, W * Tl> tw;
+  tw.fetch(tid);
+  const int c = tid % W, j = tid / W;
+  const long gc = tile * W + c;
+  const long b = gc / Qp;
+  const long q = gc - b * Qp;
+  const int kz = (int)(q % g.Mzp);
+  const bool valid = gc < ncols && kz < g.Mz;
+  const long pc = 2 * (long)blockIdx.y;
+  const long ib = valid ? blockIdx.z * is_in + pc * cs_in + b * bs_in + q : 0;
+  const long ob = valid ? blockIdx.z * is_out + pc * cs_out + b * bs_out + q : 0;
+  cx<T> va[R], vb[R];
+  static_for<0, R>([&](auto s) {
+    if constexpr (col_live<Plan, KL>(s)) {
+      const int p = j + s * Tl;
+      const bool kp = valid && kept(p, g);
+      const long off = ib + (kp ? (long)crow(p, g) * ld_in : 0);
+      const cx<T> x = in[off], y = in[off + cs_in];
+      va[s] = kp ? x : cx<T>{T(0), T(0)};
+      vb[s] = kp ? y : cx<T>{T(0), T(0)};
+    } else {
+      va[s] = cx<T>{T(0), T(0)};
+      vb[s] = cx<T>{T(0), T(0)};
+    }
+  });
+  tw.put(tws, tid);
+  LdsCols<T, N, W> lds{sm, c};
+  Plan::template fft<T, +1>(va, j, lds, TwTab<T>{tws});
+  Plan::template fft<T, +1>(vb, j, lds, TwTab<T>{tws});
+  if (!valid) return;
+  const bool k0 = kz + g.kz0 == 0;  // a real line's k = 0 coefficient is real
+  static_for<0, R>([&](auto s) {
+    cx<T> a = va[s], e = vb[s];
+    if (k0) {
+      a.y = T(0);
+      e.y = T(0);
+    }
+    const long o = ob + (long)(j + s * Tl) * ld_out;
+    store_out<PAIR == 1>(out + o, cx<T>{a.x - e.y, a.y + e.x});
+    store_out<PAIR == 1>(out + o + cs_out, cx<T>{a.x + e.y, e.x - a.y});
+  });
+}
+
+// y forward from packed rows: blockIdx.y = 0 separates c0, c1 from rows A
+// (component 0) and B (component 1) on load and transforms both, into
+// components 0 and 1; blockIdx.y = 1 transforms component 2.  Arguments as
+// k_strided with IN_C = false, OUT_C = true; KL as col_live (output rows).
+template <typename T, class Plan, int W, int KL>
+__global__ __launch_bounds__(W* Plan::Tl) void k_y_fwd_unpack(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                              long ncols, long Qp, long ld_in, long ld_out,
+                                                              long bs_in, long bs_out, long cs_in, long cs_out,
+                                                              long is_in, long is_out, Geo g,
+                                                              const int* __restrict__ act) {
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+  __shared__ cx<T> sm[N * W];
+  __shared__ cx<T> tws[N];
+  const long tile = tile_of_block<PAIR>(blockIdx.x);
+  if (tile * W >= ncols) return;          // whole block leaves together
+  if (act && !act[blockIdx.z]) return;  // instance no longer iterating
+  const int tid = threadIdx.x;
+  TwStage<T, Plan, W * Tl> tw;
+  tw.fetch(tid);
+  const int c = tid % W, j = tid / W;
+  const long gc = tile * W + c;
+  const long b = gc / Qp;
+  const long q = gc - b * Qp;
+  const bool valid = gc < ncols && (int)(q % g.Mzp) < g.Mz;
+  const bool pair = blockIdx.y == 0;
+  const long pc = pair ? 0 : 2;
+  const long ib = valid ? blockIdx.z * is_in + pc * cs_in + b * bs_in + q : 0;
+  const long ob = valid ? blockIdx.z * is_out + pc * cs_out + b * bs_out + q : 0;
+  LdsCols<T, N, W> lds{sm, c};
+  if (pair) {
+    cx<T> va[R], vb[R];
+    static_for<0, R>([&](auto s) {
+      const long off = ib + (valid ? (long)(j + s * Tl) * ld_in : 0);
+      const cx<T> x = in[off], y = in[off + cs_in];
+      // c0 = (A + conj B)/2, c1 = (A - conj B)/(2i)
+      va[s] = valid ? cx<T>{T(0.5) * (x.x + y.x), T(0.5) * (x.y - y.y)} : cx<T>{T(0), T(0)};
+      vb[s] = valid ? cx<T>{T(0.5) * (x.y + y.y), T(0.5) * (y.x - x.x)} : cx<T>{T(0), T(0)};
+    });
+    tw.put(tws, tid);
+    Plan::template fft<T, -1>(va, j, lds, TwTab<T>{tws});
+    Plan::template fft<T, -1>(vb, j, lds, TwTab<T>{tws});
+    if (!valid) return;
+    static_for<0, R>([&](auto s) {
+      if constexpr (col_live<Plan, KL>(s)) {
+        const int p = j + s * Tl;
+        if (kept(p, g)) {
+          const long o = ob + (long)crow(p, g) * ld_out;
+          store_out<false>(out + o, va[s]);
+          store_out<false>(out + o + cs_out, vb[s]);
+        }
+      }
+    });
+  } else {
+    cx<T> v[R];
+    static_for<0, R>([&](auto s) {
+      const cx<T> x = in[ib + (valid ? (long)(j + s * Tl) * ld_in : 0)];
+      v[s] = valid ? x : cx<T>{T(0), T(0)};
+    });
+    tw.put(tws, tid);
+    Plan::template fft<T, -1>(v, j, lds, TwTab<T>{tws});
+    if (!valid) return;
+    static_for<0, R>([&](auto s) {
+      if constexpr (col_live<Plan, KL>(s)) {
+        const int p = j + s * Tl;
+        if (kept(p, g)) store_out<false>(out + ob + (long)crow(p, g) * ld_out, v[s]);
+      }
+    });
+  }
+}
+
+// The same with one output per block: block o of a tile (0: c0, 1: c1 from
+// rows A and B; 2: c2) loads what it needs and runs one transform.  The three
+// blocks of a tile are consecutive on one XCD, so the second read of rows A
+// and B comes from its L2.  blockIdx.y is the instance of a batch.
+template <typename T, class Plan, int W, int KL>
+__global__ __launch_bounds__(W* Plan::Tl) void k_y_fwd_unpack3(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                               long ncols, long Qp, long ld_in, long ld_out,
+                                                               long bs_in, long bs_out, long cs_in, long cs_out,
+                                                               long is_in, long is_out, Geo g,
+                                                               const int* __restrict__ act) {
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+  __shared__ cx<T> sm[N * W];
+  __shared__ cx<T> tws[N];
+  const int blk = blockIdx.x;
+  const int xcd = blk & 7, slot = blk >> 3;
+  const int o = slot % 3;
+  const int rest = slot / 3;
+  const long tile = ((long)(rest / PAIR) * 8 + xcd) * PAIR + rest % PAIR;
+  if (tile * W >= ncols) return;          // whole block leaves together
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
+  const int tid = threadIdx.x;
+  TwStage<T, Plan, W * Tl> tw;
+  tw.fetch(tid);
+  const int c = tid % W, j = tid / W;
+  const long gc = tile * W + c;
+  const long b = gc / Qp;
+  const long q = gc - b * Qp;
+  const bool valid = gc < ncols && (int)(q % g.Mzp) < g.Mz;
+  const long ib = valid ? blockIdx.y * is_in + (o == 2 ? 2 : 0) * cs_in + b * bs_in + q : 0;
+  const long ob = valid ? blockIdx.y * is_out + o * cs_out + b * bs_out + q : 0;
+  cx<T> v[R];
+  if (o == 2) {
+    static_for<0, R>([&](auto s) {
+      const cx<T> x = in[ib + (valid ? (long)(j + s * Tl) * ld_in : 0)];
+      v[s] = valid ? x : cx<T>{T(0), T(0)};
+    });
+  } else {
+    // c0 = (A + conj B)/2, c1 = (A - conj B)/(2i)
+    const T sg = o == 0 ? T(1) : T(-1);
+    static_for<0, R>([&](auto s) {
+      const long off = ib + (valid ? (long)(j + s * Tl) * ld_in : 0);
+      const cx<T> x = in[off], y = in[off + cs_in];
+      const cx<T> e = {T(0.5) * (x.x + sg * y.x), T(0.5) * (x.y - sg * y.y)};  // (A +- conj B)/2
+      v[s] = valid ? (o == 0 ? e : cx<T>{e.y, -e.x}) : cx<T>{T(0), T(0)};
+    });
+  }
+  tw.put(tws, tid);
+  LdsCols<T, N, W> lds{sm, c};
+  Plan::template fft<T, -1>(v, j, lds, TwTab<T>{tws});
+  if (!valid) return;
+  static_for<0, R>([&](auto s) {
+    if constexpr (col_live<Plan, KL>(s)) {
+      const int p = j + s * Tl;
+      if (kept(p, g)) store_out<false>(out + ob + (long)crow(p, g) * ld_out, v[s]);
+    }
+  });
+}
+
+// P3 on packed rows: per z line, the three complex lines (u_x + i u_y,
+// u_z + i w_x, w_y + i w_z) load straight into the registers of their inverse
+// transforms (lane j, register s holds position p = j + s Tl: row A at p < Mz,
+// row B at N - p < Mz, zero between), all nine loads of a lane in flight
+// together; then the cross product c = u x w (component formula of Sec. 3.4;
+// u and w already carry the 1/N^3 of Eq. ffteq, applied by the x pass), and the
+// forward transforms of c0 + i c1 (stored as packed rows A, B in components
+// 0, 1) and of c2 (component 2).  In place.  KL: coefficients per lane; ZA
+// places coefficient k of a row (ZContig, or ZBlocked for the receive buffer
+// of a z-slab all-to-all).  Three waves per SIMD: at 168 VGPRs nothing spills
+// for the 2/3 rule.
+template <typename T, class Plan, int KL, class ZA>
+__global__ __launch_bounds__(256, 3) void k_z_cross_packed(cx<T>* __restrict__ A, long csA, long isA, long nlines, Geo g,
+                                                        const int* __restrict__ act, ZA za) {
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
+  constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
+  constexpr int LPB = ZShape<Plan>::LPB;
+  constexpr int LS = Plan::line_stride;
+  __shared__ cx<T> sm[ZShape<Plan>::SLOTS * LS];
+  __shared__ cx<T> tws[N];
+  TwStage<T, Plan, 256> twst;
+  twst.fetch(threadIdx.x);
+  int li, j;
+  bool live;
+  ZShape<Plan>::place(threadIdx.x, li, j, live);
+  const long line = (long)blockIdx.x * LPB + li;
+  const bool valid = live && line < nlines;
+  const int Mz = g.Mz;  // the launcher guarantees Mz <= KL * Tl
+  LdsLine<T, Plan::SH, ZShape<Plan>::kBlock> lds{sm + li * LS};
+  const TwTab<T> tw{tws};
+  A += blockIdx.y * isA + (valid ? line * g.Mzp : 0);
+  cx<T> ph[3][R];
+  static_for<0, 3>([&](auto pr) {
+    const cx<T>* ra = A + (2 * pr) * csA;
+    const cx<T>* rb = ra + csA;
+    static_for<0, R>([&](auto s) {
+      constexpr bool lo = s * Tl < KL * Tl;         // can hold a k < Mz
+      constexpr bool hi = (s + 1) * Tl > N - KL * Tl;  // can hold an N - k, k < Mz
+      if constexpr (lo || hi) {
+        const int p = j + s * Tl;
+        const bool ina = lo && valid && p < Mz;
+        const bool inb = hi && !ina && valid && p > 0 && N - p < Mz;
+        const cx<T> x = ina ? ra[za(p)] : rb[za(inb ? N - p : 0)];
+        ph[pr][s] = (ina || inb) ? x : cx<T>{T(0), T(0)};
+      } else {
+        ph[pr][s] = cx<T>{T(0), T(0)};
+      }
+    });
+  });
+  // twiddles to LDS while the line loads are in flight
+  twst.put(tws, threadIdx.x);
+  lds_barrier();
+  static_for<0, 3>([&](auto pr) { Plan::template fft<T, +1>(ph[pr], j, lds, tw); });
+  // u = (ph0.x, ph0.y, ph1.x), w = (ph1.y, ph2.x, ph2.y)
+  cx<T> z01[R], z2[R];
+  static_for<0, R>([&](auto s) {
+    const T u0 = ph[0][s].x, u1 = ph[0][s].y, u2 = ph[1][s].x;
+    const T w0 = ph[1][s].y, w1 = ph[2][s].x, w2 = ph[2][s].y;
+    z01[s] = {u1 * w2 - u2 * w1, u2 * w0 - u0 * w2};
+    z2[s] = {u0 * w1 - u1 * w0, T(0)};
+  });
+  Plan::template fft<T, -1>(z2, j, lds, tw);
+  Plan::template fft<T, -1>(z01, j, lds, tw);
+  if (!valid) return;
+  cx<T>* oa = A;
+  cx<T>* ob = A + csA;
+  cx<T>* o2 = A + 2 * csA;
+  static_for<0, R>([&](auto s) {
+    constexpr bool lo = s * Tl < KL * Tl;
+    constexpr bool hi = (s + 1) * Tl > N - KL * Tl;
+    if constexpr (lo || hi) {
+      const int p = j + s * Tl;
+      if (lo && p < Mz) {
+        const long o = za(p);
+        store_stream(oa + o, z01[s]);
+        store_stream(o2 + o, z2[s]);
+        if (p == 0) store_stream(ob + o, z01[s]);  // row B at k = 0 is Z_N = Z_0
+      } else if (hi && N - p < Mz) {
+        store_stream(ob + za(N - p), z01[s]);
+      }
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------

@@ -6,8 +6,8 @@
 //          the rows outside the retained set are read as zeros
 //   y      inverse transform of every (component, kz) column, in place
 //   z      per y line: the z pass of k_z_cross (inverse real transforms of
-//          u and omega, u x omega scaled by 1/N^6, forward real transforms),
-//          components 0..2 of the row written back
+//          u and omega, u x omega, forward real transforms; u and omega
+//          carry the 1/N^3 already), components 0..2 of the row written back
 //   y      forward transform of every (component 0..2, kz) column, in place
 //   store  the retained rows of components 0..2 -> A[3][x][M][Mzp]
 // So the (x, y, kz) intermediate never goes to HBM: per x-plane the block
@@ -54,7 +54,7 @@ struct YzShape {
 };
 
 template <typename T, class Plan, int KL>
-__global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __restrict__ A, long csA, long isA, Geo g, T scale,
+__global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __restrict__ A, long csA, long isA, Geo g,
                                                   const int* __restrict__ act) {
   using S = YzShape<T, Plan>;
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, LS = Plan::line_stride;
@@ -154,8 +154,8 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
       static_for<0, R>([&](auto s) {
         const T u0 = ph[0][s].x, u1 = ph[0][s].y, u2 = ph[1][s].x;
         const T w0 = ph[1][s].y, w1 = ph[2][s].x, w2 = ph[2][s].y;
-        z01[s] = {(u1 * w2 - u2 * w1) * scale, (u2 * w0 - u0 * w2) * scale};
-        z2[s] = {(u0 * w1 - u1 * w0) * scale, T(0)};
+        z01[s] = {u1 * w2 - u2 * w1, u2 * w0 - u0 * w2};
+        z2[s] = {u0 * w1 - u1 * w0, T(0)};
       });
       Plan::template fft<T, -1>(z2, j, lds, tw);
       Plan::template fft<T, -1>(z01, j, lds, tw);

@@ -280,7 +280,11 @@ def test_set_variant_rules_without_the_gpu():
             assert (binding.hot_tuned_width(h, 0, "x_fwd_rk") == 0) == (v < 0)
         assert lib.hot_set_variant(h, names.index("x_fwd_rk"), 3) == binding.HOT_E_INVALID
         assert lib.hot_set_variant(h, names.index("y_inv"), 3) == binding.HOT_E_INVALID
-        assert lib.hot_set_variant(h, names.index("z_cross"), 1) == binding.HOT_E_INVALID
+        assert lib.hot_set_variant(h, names.index("z_cross"), 2) == binding.HOT_E_INVALID
+        assert binding.hot_tuned_width(h, 0, "z_cross") == 1  # packed pair rows by default
+        binding.hot_set_variant(h, "z_cross", 0)
+        assert binding.hot_tuned_width(h, 0, "z_cross") == 0
+        binding.hot_set_variant(h, "z_cross", 1)
         binding.hot_set_variant(h, "y_inv", 0)
         binding.hot_set_variant(h, "x_fwd_rk", -1)
         assert binding.hot_tuned_width(h, 0, "x_fwd_rk") == 0
@@ -299,7 +303,7 @@ def test_fused_yz_variant_rules_without_the_gpu():
     lib = binding.library()
     names = binding.pass_names()
     yz = names.index("yz_fused")
-    assert names[-3:] == ["yz_fused", "tables", "stats"]
+    assert names[-4:] == ["yz_fused", "tables", "stats", "graph"]
     # the fused y-z pass exists for small N only: a batch switches the sizes that have it
     h, _ = binding.hot_plan([16, 64, 128, 1024], "rk4", "f32", nu=0.01, dt=1e-3)
     try:

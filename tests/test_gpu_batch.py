@@ -78,11 +78,13 @@ def test_batched_instance_equals_its_single_run_bitwise():
         assert np.array_equal(batch[i].view(np.uint32), single[0].view(np.uint32)), SIZES[i]
 
 
-def test_graph_replays_equal_eager_run():
+@pytest.mark.parametrize("branches", [1, 0])
+def test_graph_replays_equal_eager_run(branches):
+    # branches = 1: one graph branch per size (the default); 0: one chain
     import torch
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        eager, replays = _plan_run(_fields("f32"), "f32", 1, stream=s, graph_reps=3)
+        eager, replays = _plan_run(_fields("f32"), "f32", 1, stream=s, graph_reps=3, variants={"graph": branches})
     assert len(replays) == 3
     for rep in replays:
         for a, b in zip(rep, eager):

@@ -250,3 +250,25 @@ def test_fused_and_separate_x_pass_agree_on_a_batch():
     for x, y, f in zip(a, b, fields):
         assert rel_l2(y, x) < 1e-6
         assert rel_l2(y, oracle.rk4(round32(f), NU, DT, 1)) < fp32_tol(f.shape[1])
+
+
+# -- the y and z passes on packed pair rows against six component rows -----------
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N", [16, 24, 64, 128])
+def test_packed_and_component_rows_agree(N, dtype):
+    # variant 1 (default): u and w travel as packed pairs of complex lines;
+    # variant 0: six component rows, the z pass building the Hermitian halves
+    print(f"packed rows N={N} {dtype}", flush=True)
+    uh = inputs.rough_random(N, 90 + N)
+    (a,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 1})
+    (b,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 0})
+    # the packed y forward pass with one output per block (variant 4)
+    (c,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 1, "y_fwd": 4})
+    ref = oracle.rk4(ref_input(uh, dtype), NU, DT, 1)
+    for x in (a, b, c):
+        assert rel_l2(x, ref) < tol(dtype, N)
+    assert rel_l2(a, b) < tol(dtype, N)
+    assert rel_l2(a, c) < tol(dtype, N)
+    M = oracle.retained_mask(N)
+    assert np.all(a[:, ~M] == 0) and np.all(b[:, ~M] == 0) and np.all(c[:, ~M] == 0)
