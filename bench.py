@@ -236,6 +236,7 @@ def bench_batch(a):
         try:
             with torch.cuda.stream(s):
                 binding.hot_tune(plan, ws, s)
+                binding.hot_set_variant(plan, "graph", 1 if a.graph_layout == "branches" else 0)
                 g = binding.hot_graph_create(plan, ins, outs, ws, 1, s)
                 binding.hot_graph_launch(g, s)
                 torch.cuda.synchronize()
@@ -267,6 +268,7 @@ def bench_batch(a):
             prof = binding.hot_profile_read(plan)
             binding.hot_profile_enable(plan, False)
             # graph: the whole batch step as one replayed HIP graph
+            binding.hot_set_variant(plan, "graph", 1 if a.graph_layout == "branches" else 0)
             g = binding.hot_graph_create(plan, ins, outs, ws, 1, s)
             binding.hot_graph_launch(g, s)
             torch.cuda.synchronize()
@@ -327,7 +329,7 @@ def bench_batch(a):
         "vs_baseline": None,
         "dtype": a.dtype,
         "data": "synthetic (R1 per instance, seeds 1000+i; sizes log-uniform over [16, 64], seed 0)",
-        "config": {"workload": f"rk4_batch_{B}_uneven_16-64_{a.dtype}", "instances": B,
+        "config": {"workload": f"rk4_batch_{B}_uneven_16-64_{a.dtype}", "instances": B, "graph": a.graph_layout,
                    "sizes": {int(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))},
                    "points": int((sizes.astype(np.int64) ** 3).sum()), "nu": NU, "dt": DT,
                    "launch": "one HIP graph replay per batch step (one launch per pass per size inside)"},
@@ -353,51 +355,12 @@ BF16_PEAK_TFLOPS = 2500.0
 MLP_FLOP_PER_ROW = 2 * (32 * 256 + 2 * 256 * 256 + 256 * 6)  # the six real outputs (not the padded tile)
 
 
-def _implicit_trajectory(binding, torch, N, seed, nsteps, nu, dt):
-    """States u_0 .. u_nsteps of one R1 field (FP64, tol 1e-12) from the
-    GPU implicit solver, one hot_run call per step with the history kept."""
-    from paper_1607_00850_amd import inputs
-
-    u = torch.from_numpy(inputs.smooth_random(N, seed)).to("cuda")
-    h, wsb = binding.hot_plan(N, "implicit", "f64", "two_thirds", nu, dt, 1e-12, 100, keep_history=True)
-    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
-    states = []
-    try:
-        cur = torch.empty_like(u)
-        binding.hot_run(h, [u], [cur], ws, 0)  # projection onto the retained set
-        states.append(cur.clone())
-        for _ in range(nsteps):
-            binding.hot_run(h, [cur], [cur], ws, 1)
-            states.append(cur.clone())
-        torch.cuda.synchronize()
-    finally:
-        binding.hot_destroy(h)
-    return states
-
-
-def _dataset(binding, torch, fields, nu, dt):
-    """Training rows of the third step of each (N, seed) trajectory."""
-    xs, ts, ss = [], [], []
-    for N, sd in fields:
-        N = int(N)
-        rows = binding.hot_mlp_dataset_rows(N)
-        u = _implicit_trajectory(binding, torch, N, sd, 3, nu, dt)
-        d2, d1, d = u[1] - u[0], u[2] - u[1], u[3] - u[2]
-        x = torch.empty((rows, 32), dtype=torch.float32, device="cuda")
-        t = torch.empty((rows, 6), dtype=torch.float32, device="cuda")
-        sc = torch.empty(rows, dtype=torch.float32, device="cuda")
-        binding.hot_mlp_dataset(N, "f64", u[2], d1, d2, d, nu, dt, x, t, sc)
-        xs.append(x)
-        ts.append(t)
-        ss.append(sc / torch.linalg.vector_norm(sc))  # each field weighs the same (coefficients scale as N^3)
-    torch.cuda.synchronize()
-    return torch.cat(xs), torch.cat(ts), torch.cat(ss)
-
-
 def bench_surrogate(a):
-    """MLP surrogate for the implicit step: train it on GPU trajectories at
-    N = 64, then compare plain and surrogate-assisted implicit steps on a
-    batch of uneven instances at the same tolerance."""
+    """MLP surrogate for the implicit step: train it on input/output pairs
+    of FP64 oracle trajectories at N = 64 (a file written beforehand by
+    `python -m oracle.surrogate_data`; this script does not run the oracle),
+    then compare plain and surrogate-assisted implicit steps on a batch of
+    uneven instances at the same tolerance."""
     import numpy as np
     import torch
 
@@ -406,23 +369,22 @@ def bench_surrogate(a):
     nu, dt, tol = NU, IMP_DT, 1e-5
     sizes = inputs.batch_sizes(a.surrogate_batch, 0)
     modes = batch_modes(sizes)  # host work first: the pool forks before any GPU call
-    # ---- training data: trajectories of the batch's size law (sizes drawn
-    # with seed 1, fields seeds 10000+i) or N = 64 only; held out: sizes
-    # drawn with seed 2 (fields 20000+i) and two N = 64 fields
+    # ---- training data: input/output pairs of FP64 oracle trajectories at
+    # N = 64, written beforehand by `python -m oracle.surrogate_data` (rows
+    # drawn with probability ~ s^2 within each field); held out: every
+    # retained mode of other oracle trajectories
     t0 = time.perf_counter()
-    if a.train_sizes == "batch":
-        train = list(zip(inputs.batch_sizes(a.train_fields, 1), range(10000, 10000 + a.train_fields)))
-    else:
-        train = [(64, 10000 + i) for i in range(a.train_fields)]
-    X, T, S = _dataset(binding, torch, train, nu, dt)
-    held = list(zip(inputs.batch_sizes(20, 2), range(20000, 20020)))
-    Xv, Tv, Sv = _dataset(binding, torch, held, nu, dt)
-    Xv64, Tv64, Sv64 = _dataset(binding, torch, [(64, 20100), (64, 20101)], nu, dt)
-    # rows are drawn with probability proportional to s^2: the stopping test
-    # measures the increment's error in the field's L2 norm, where a mode's
-    # error counts as s * |y - t|
-    cdf = torch.cumsum(S.double() ** 2, 0)
-    cdf /= cdf[-1].clone()
+    if not a.train_data or not a.val_data:
+        raise SystemExit("--workload surrogate needs --train-data and --val-data (files written by "
+                         "`python -m oracle.surrogate_data`)")
+    tr = np.load(a.train_data)
+    va = np.load(a.val_data)
+    X = torch.from_numpy(tr["x"]).cuda()
+    T = torch.from_numpy(tr["t"]).cuda()
+    Xv = torch.from_numpy(va["x"]).cuda()
+    Tv = torch.from_numpy(va["t"]).cuda()
+    Sv = torch.from_numpy(va["s"].astype(np.float32)).cuda()
+    train = [int(v) for v in tr["seeds"]]
     t_data = time.perf_counter() - t0
     rows = X.shape[0]
     # ---- training (FP32 master weights, BF16 MFMA products, Adam)
@@ -449,8 +411,7 @@ def bench_surrogate(a):
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     grad_ms = 0.0
     for step in range(1, a.train_steps + 1):
-        u = torch.rand(mb, dtype=torch.float64, device="cuda", generator=gen)
-        idx = torch.clamp(torch.searchsorted(cdf, u), max=rows - 1)
+        idx = torch.randint(0, rows, (mb,), device="cuda", generator=gen)
         torch.index_select(X, 0, idx, out=xb)
         torch.index_select(T, 0, idx, out=tb)
         lr = 1e-3 * (0.5 * (1 + np.cos(np.pi * (step - 1) / a.train_steps)))  # cosine decay
@@ -472,7 +433,7 @@ def bench_surrogate(a):
     # extrapolation's error (1.0 = no better than the extrapolation)
     val = {"note": "||s (y - t)|| / ||s t||: the increment error of the warm start relative to that of the "
                    "plain extrapolation (1.0 = no better), over the held-out rows"}
-    for name, xv, tv, sv in (("held_out_batch_sizes", Xv, Tv, Sv), ("held_out_N64", Xv64, Tv64, Sv64)):
+    for name, xv, tv, sv in (("held_out_oracle_N64", Xv, Tv, Sv),):
         yv = torch.empty_like(tv)
         binding.hot_mlp_forward(pk, xv, yv, xv.shape[0])
         torch.cuda.synchronize()
@@ -549,7 +510,8 @@ def bench_surrogate(a):
         "roofline": {"bound": "mfma", "kernel": "mlp_fused (imp_predict)", "achieved": mlp_tflops,
                      "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": (mlp_tflops / BF16_PEAK_TFLOPS) if mlp_tflops else None, "traffic": None},
-        "training": {"sizes": a.train_sizes, "fields": len(train), "train_rows": rows, "steps": a.train_steps,
+        "training": {"data": "FP64 oracle implicit-midpoint trajectories at N = 64 (oracle.surrogate_data)",
+                     "fields": len(train), "train_rows": rows, "steps": a.train_steps,
                      "minibatch": mb, "seconds": t_train, "data_seconds": t_data, "loss_trace": losses,
                      "grad_call_ms": grad_ms, "grad_gemm_tflops": grad_tflops,
                      "grad_mfma_frac": (grad_tflops / BF16_PEAK_TFLOPS) if grad_tflops else None},
@@ -825,9 +787,8 @@ def main():
     ap.add_argument("--gen-workers", type=int, default=16, help="batch workloads: field generation processes")
     ap.add_argument("--tg-n", type=int, default=256, help="tg: points per axis")
     ap.add_argument("--tg-steps", type=int, default=20000, help="tg: RK4 steps (dt = 1e-3)")
-    ap.add_argument("--train-fields", type=int, default=200, help="surrogate: training trajectories")
-    ap.add_argument("--train-sizes", default="batch", choices=["batch", "n64"],
-                    help="surrogate: training sizes drawn like the batch's, or N = 64 only")
+    ap.add_argument("--train-data", default="", help="surrogate: training pairs (python -m oracle.surrogate_data)")
+    ap.add_argument("--val-data", default="", help="surrogate: held-out pairs (python -m oracle.surrogate_data)")
     ap.add_argument("--train-steps", type=int, default=3000, help="surrogate: Adam steps")
     ap.add_argument("--minibatch", type=int, default=4096, help="surrogate: rows per Adam step")
     ap.add_argument("--surrogate-batch", type=int, default=16384, help="surrogate: instances compared")
@@ -837,6 +798,8 @@ def main():
     ap.add_argument("--ranks", type=int, default=8, help="slab: shares of the field")
     ap.add_argument("--rank", type=int, default=0, help="slab: the share timed")
     ap.add_argument("--batch", type=int, default=4096, help="instances of the batch workload")
+    ap.add_argument("--graph-layout", default="branches", choices=["branches", "chain"],
+                    help="batch: one graph branch per size (default) or the sizes one after another")
     ap.add_argument("--replays-only", type=int, default=0, metavar="K",
                     help="batch: tune, capture, pause 0.5 s, replay the graph K times and print only that "
                          "(for kernel traces of the replays)")

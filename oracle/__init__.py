@@ -7,9 +7,11 @@ from .spectral_ns import *  # noqa: F401,F403
 from .implicit_midpoint import *  # noqa: F401,F403
 from .mlp import *  # noqa: F401,F403
 from .triads import *  # noqa: F401,F403
+from .surrogate_data import *  # noqa: F401,F403
 from .spectral_ns import __all__ as _a
 from .implicit_midpoint import __all__ as _b
 from .mlp import __all__ as _c
 from .triads import __all__ as _d
+from .surrogate_data import __all__ as _e
 
-__all__ = list(_a) + list(_b) + list(_c) + list(_d)
+__all__ = list(_a) + list(_b) + list(_c) + list(_d) + list(_e)
