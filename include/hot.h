@@ -221,8 +221,10 @@ int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
  * for x_fwd_rk -1 (separate x_fwd and rk_stage passes), 0, 1 or 2 (fused,
  * at half, the default or a quarter of the default width); for z_cross 1
  * (the default: the y and z passes carry u and w as packed pairs of complex
- * lines) or 0 (six separate component rows, the z pass completing the
- * Hermitian halves itself); for "graph" (no kernel of its own) the layout of
+ * lines), 2 (packed pairs into the z pass, which stores c0, c1, c2 as three
+ * component rows for the y forward pass; hot_tune chooses between 1 and 2) or
+ * 0 (six separate component rows, the z pass completing the Hermitian halves
+ * itself); for "graph" (no kernel of its own) the layout of
  * graphs hot_graph_create captures from then on: 1 (the default) one branch
  * per distinct N, forked from and joined back into the capturing stream, so
  * the passes of small sizes run beside those of large ones; 0 the sizes one

@@ -121,7 +121,7 @@ struct Group {
   int rot = 0, hist = 0;                      // implicit step: buffer rotation, history depth
   int fused = -1;  // RK4/RHS: x_fwd_rk variant fusing the x pass with the stage update, -1 = separate passes
   int yz = -1;     // 0: the y and z passes fused (k_yz_fused), -1: y_inv, z_cross, y_fwd
-  bool zpack = false;  // the y and z passes on packed pair rows (hot_set_variant z_cross 1, the default)
+  int zpack = 0;  // z pass rows: 0 six component rows; 1 packed pairs in and out (default); 2 packed in, c0 c1 c2 out
   size_t bytes = 0;
   int variant[NUM_PASSES];  // strided column-width variant per pass (autotuned)
   int B() const { return (int)members.size(); }
@@ -297,7 +297,7 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
         return HOT_E_UNSUPPORTED;
       }
       G.g = make_geo(N, plain ? 2 : d->dealias, (int)p->elem);
-      G.zpack = !plain;
+      G.zpack = plain ? 0 : 1;
       for (int k = 0; k < NUM_PASSES; ++k) G.variant[k] = 1;
       p->groups.push_back(G);
       gp = &p->groups.back();
@@ -494,7 +494,7 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
 void y_inv_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
   const long N = G.N, M = G.g.M, P = G.g.Mzp;
   r.pass(PASS_Y_INV, [&] {
-    if (G.zpack)
+    if (G.zpack > 0)
       return G.ops.y_inv_pack(r.s, G.variant[PASS_Y_INV], q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2,
                               6 * G.D1, 6 * G.D2, G.B(), G.g, act);
     return G.ops.strided(r.s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1,
@@ -504,18 +504,19 @@ void y_inv_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
 
 void z_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
   r.pass(PASS_Z_CROSS, [&] {
-    return G.zpack ? G.ops.z_cross_packed(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act)
-                   : G.ops.z_cross(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act);
+    return G.zpack > 0
+               ? G.ops.z_cross_packed(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act, G.zpack == 2)
+               : G.ops.z_cross(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act);
   });
 }
 
 void y_fwd_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
   const long N = G.N, M = G.g.M, P = G.g.Mzp;
   r.pass(PASS_Y_FWD, [&] {
-    if (G.zpack)
+    if (G.zpack == 1)
       return G.ops.y_fwd_unpack(r.s, G.variant[PASS_Y_FWD], q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1,
                                 6 * G.D2, 6 * G.D1, G.B(), G.g, act);
-    return G.ops.strided(r.s, G.variant[PASS_Y_FWD], -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2,
+    return G.ops.strided(r.s, G.variant[PASS_Y_FWD] % 3, -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2,
                          G.D1, 3, 6 * G.D2, 6 * G.D1, G.B(), G.g, act);
   });
 }
@@ -1108,7 +1109,7 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
       float best = 1e30f;
       int best_v = 1;
       // the packed y forward pass also comes with one output per block (variants 3..5)
-      const int nv = (pid == PASS_Y_FWD && G.zpack) ? 2 * G.ops.strided_variants : G.ops.strided_variants;
+      const int nv = (pid == PASS_Y_FWD && G.zpack == 1) ? 2 * G.ops.strided_variants : G.ops.strided_variants;
       for (int v = 0; v < nv && rc == HOT_OK; ++v) {
         const int w = v % G.ops.strided_variants;
         if (w != 1 && G.ops.strided_width[w] == G.ops.strided_width[1]) continue;  // same kernel
@@ -1124,13 +1125,13 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
           r.pass(pid, [&] {
             if (pid == PASS_X_INV_CURL)
               return G.ops.x_inv_curl(s, v, q.U0, G.C, isU, q.A1, G.D1, isA1, G.B(), g, nullptr);
-            if (pid == PASS_Y_INV && G.zpack)
+            if (pid == PASS_Y_INV && G.zpack > 0)
               return G.ops.y_inv_pack(s, v, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2, isA1, isA2,
                                       G.B(), g, nullptr);
             if (pid == PASS_Y_INV)
               return G.ops.strided(s, v, +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2, 6,
                                    isA1, isA2, G.B(), g, nullptr);
-            if (pid == PASS_Y_FWD && G.zpack)
+            if (pid == PASS_Y_FWD && G.zpack == 1)
               return G.ops.y_fwd_unpack(s, v, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1, isA2, isA1,
                                         G.B(), g, nullptr);
             if (pid == PASS_Y_FWD)
@@ -1191,6 +1192,38 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
         }
       }
       G.yz = best_y;
+    }
+    // the z pass storing packed halves (y forward separating c0 and c1) or
+    // separating them itself (component-row y forward); groups whose y and z
+    // passes are not fused
+    if (rc == HOT_OK && G.yz < 0 && G.zpack > 0) {
+      float best = 1e30f;
+      int best_z = 1;
+      for (int zv = 1; zv <= 2 && rc == HOT_OK; ++zv) {
+        G.zpack = zv;
+        float t = 0.f;
+        for (int rep = 0; rep <= reps && rc == HOT_OK; ++rep) {
+          Runner r{p, s, false};
+          if (rep == 1) (void)hipEventRecord(a, s);
+          z_pass(r, G, q, nullptr);
+          y_fwd_pass(r, G, q, nullptr);
+          rc = r.rc;
+        }
+        if (rc != HOT_OK) break;
+        hipError_t e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+        if (e != hipSuccess) {
+          p->last_hip = (int)e;
+          rc = HOT_E_HIP;
+          break;
+        }
+        if (t < best) {
+          best = t;
+          best_z = zv;
+        }
+      }
+      G.zpack = best_z;
     }
     // RK4 / RHS: the x pass with the stage update fused, or the two passes
     // (one stage-1 update on the workspace; every variant computes the same)
@@ -1258,10 +1291,10 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
     p->graph_branches = variant == 1;
     return HOT_OK;
   }
-  if (pass == PASS_Z_CROSS) {  // 1: packed pair rows (default), 0: six component rows
+  if (pass == PASS_Z_CROSS) {  // 1: packed pair rows (default), 0: six component rows, 2: packed in, split out
     const bool plain = p->op == HOT_OP_R2C || p->op == HOT_OP_C2R;
-    if (variant < 0 || variant > 1 || plain) return HOT_E_INVALID;
-    for (auto& G : p->groups) G.zpack = variant == 1;
+    if (variant < 0 || variant > 2 || plain) return HOT_E_INVALID;
+    for (auto& G : p->groups) G.zpack = variant;
     return HOT_OK;
   }
   if (pass == PASS_YZ_FUSED) {  // 0: fused wherever a size has the kernel
@@ -1283,7 +1316,7 @@ extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
       if (pass == PASS_X_FWD_RK)
         return G.fused < 0 ? 0 : G.ops.fused_width[G.fused];
       if (pass == PASS_YZ_FUSED) return G.yz < 0 ? 0 : 1;
-      if (pass == PASS_Z_CROSS) return G.zpack ? 1 : 0;
+      if (pass == PASS_Z_CROSS) return G.zpack;
       if (pass == PASS_GRAPH) return p->graph_branches ? 1 : 0;
       return G.ops.strided_width[G.variant[pass] % 3];
     }
@@ -1379,8 +1412,8 @@ extern "C" int hot_slab_run(hot_plan_t p, int32_t phase, int32_t stage, const vo
     case HOT_SLAB_CROSS: {
       const long lines = (long)p->nx * G.N, blk = lines * G.g.Mzp;
       r.pass(PASS_Z_CROSS, [&] {
-        return G.zpack ? o.z_cross_packed_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk)
-                       : o.z_cross_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk);
+        return G.zpack > 0 ? o.z_cross_packed_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk, G.zpack == 2)
+                           : o.z_cross_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk);
       });
       break;
     }

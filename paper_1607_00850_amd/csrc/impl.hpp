@@ -100,14 +100,15 @@ struct Ops {
                            long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, long is_in, long is_out,
                            int nb, const Geo&, const int* act);
   hipError_t (*z_cross_packed)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&,
-                               const int* act);
+                               const int* act, bool split);
   hipError_t (*y_fwd_unpack)(hipStream_t, int variant, const void* in, void* out, long ncols, long Qp, long ld_in,
                              long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, long is_in, long is_out,
                              int nb, const Geo&, const int* act);
   // z_cross on lines that arrive in chunks of `chunk` coefficients, blocks blk
   // elements apart (the receive buffer of a z-slab all-to-all)
   hipError_t (*z_cross_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk);
-  hipError_t (*z_cross_packed_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk);
+  hipError_t (*z_cross_packed_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk,
+                                       bool split);
   // y inverse, z pass and y forward in one kernel, in place on A1 (NULL where
   // the six planes of an x-plane do not fit in LDS)
   hipError_t (*yz_fused)(hipStream_t, void* A, long csA, long isA, int nb, const Geo&, const int* act);
@@ -254,25 +255,27 @@ struct Impl {
                             const int* act) {
     return z_cross_za(s, A, csA, isA, nlines, nb, g, act, ZContig{});
   }
-  template <class ZA>
+  template <class ZA, bool SPLIT>
   static hipError_t z_cross_packed_za(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
                                       const int* act, ZA za) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const dim3 grid(nblk, (unsigned)nb);
     constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
     if (g.Mz <= KL23 * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KL23, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g,
-                         act, za);
+      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KL23, ZA, SPLIT>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA,
+                         nlines, g, act, za);
     else if (g.Mz <= KLall * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KLall, ZA>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA, nlines, g,
-                         act, za);
+      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KLall, ZA, SPLIT>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA,
+                         nlines, g, act, za);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
+  // split: c0, c1, c2 stored as half-spectrum rows (for the component-row y forward pass)
   static hipError_t z_cross_packed(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
-                                   const int* act) {
-    return z_cross_packed_za(s, A, csA, isA, nlines, nb, g, act, ZContig{});
+                                   const int* act, bool split) {
+    return split ? z_cross_packed_za<ZContig, true>(s, A, csA, isA, nlines, nb, g, act, ZContig{})
+                 : z_cross_packed_za<ZContig, false>(s, A, csA, isA, nlines, nb, g, act, ZContig{});
   }
   // the y passes on packed rows: a grid like k_strided's, with blockIdx.y
   // the component pair (3 for the inverse, 2 for the forward)
@@ -326,9 +329,11 @@ struct Impl {
     return z_cross_za(s, A, csA, 0, nlines, 1, g, nullptr, ZBlocked{chunk, 1.0f / (float)chunk, blk});
   }
   static hipError_t z_cross_packed_blocked(hipStream_t s, void* A, long csA, long nlines, const Geo& g, int chunk,
-                                           long blk) {
+                                           long blk, bool split) {
     if (chunk < 1) return hipErrorInvalidValue;
-    return z_cross_packed_za(s, A, csA, 0, nlines, 1, g, nullptr, ZBlocked{chunk, 1.0f / (float)chunk, blk});
+    const ZBlocked za{chunk, 1.0f / (float)chunk, blk};
+    return split ? z_cross_packed_za<ZBlocked, true>(s, A, csA, 0, nlines, 1, g, nullptr, za)
+                 : z_cross_packed_za<ZBlocked, false>(s, A, csA, 0, nlines, 1, g, nullptr, za);
   }
   static constexpr bool kYz = N <= 64 && YzShape<T, PZ>::kFits;
   static hipError_t yz_fused(hipStream_t s, void* A, long csA, long isA, int nb, const Geo& g, const int* act) {

@@ -841,8 +841,10 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_y_fwd_unpack3(const cx<T>* __re
 // 0, 1) and of c2 (component 2).  In place.  KL: coefficients per lane; ZA
 // places coefficient k of a row (ZContig, or ZBlocked for the receive buffer
 // of a z-slab all-to-all).  Three waves per SIMD: at 168 VGPRs nothing spills
-// for the 2/3 rule.
-template <typename T, class Plan, int KL, class ZA>
+// for the 2/3 rule.  SPLIT: store c0, c1 and c2 as three half-spectrum rows
+// instead (the two real transforms packed in c0 + i c1 separated here, through
+// the line's LDS region), for the component-row y forward pass.
+template <typename T, class Plan, int KL, class ZA, bool SPLIT>
 __global__ __launch_bounds__(256, 3) void k_z_cross_packed(cx<T>* __restrict__ A, long csA, long isA, long nlines, Geo g,
                                                         const int* __restrict__ act, ZA za) {
   if (act && !act[blockIdx.y]) return;  // instance no longer iterating
@@ -894,10 +896,30 @@ __global__ __launch_bounds__(256, 3) void k_z_cross_packed(cx<T>* __restrict__ A
   });
   Plan::template fft<T, -1>(z2, j, lds, tw);
   Plan::template fft<T, -1>(z01, j, lds, tw);
-  if (!valid) return;
   cx<T>* oa = A;
   cx<T>* ob = A + csA;
   cx<T>* o2 = A + 2 * csA;
+  if constexpr (SPLIT) {
+    // C0_k = (Z_k + conj Z_{N-k})/2, C1_k = (Z_k - conj Z_{N-k})/(2i)
+    static_for<0, R>([&](auto s) { lds.put(j + s * Tl, z01[s]); });
+    lds.sync();
+    if (!valid) return;
+    static_for<0, R>([&](auto s) {
+      if constexpr (s < KL) {
+        const int k = j + s * Tl;
+        if (k < Mz) {
+          const cx<T> zk = lds.get(k);
+          const cx<T> zm = lds.get((N - k) % N);
+          const long o = za(k);
+          store_stream(oa + o, cx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)});
+          store_stream(ob + o, cx<T>{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)});
+          store_stream(o2 + o, z2[s]);
+        }
+      }
+    });
+    return;
+  }
+  if (!valid) return;
   static_for<0, R>([&](auto s) {
     constexpr bool lo = s * Tl < KL * Tl;
     constexpr bool hi = (s + 1) * Tl > N - KL * Tl;

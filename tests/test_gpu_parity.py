@@ -265,10 +265,12 @@ def test_packed_and_component_rows_agree(N, dtype):
     (b,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 0})
     # the packed y forward pass with one output per block (variant 4)
     (c,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 1, "y_fwd": 4})
+    # packed rows into the z pass, c0 c1 c2 component rows out of it (variant 2)
+    (d,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 2})
     ref = oracle.rk4(ref_input(uh, dtype), NU, DT, 1)
-    for x in (a, b, c):
+    for x in (a, b, c, d):
         assert rel_l2(x, ref) < tol(dtype, N)
-    assert rel_l2(a, b) < tol(dtype, N)
-    assert rel_l2(a, c) < tol(dtype, N)
+        assert rel_l2(a, x) < tol(dtype, N)
     M = oracle.retained_mask(N)
-    assert np.all(a[:, ~M] == 0) and np.all(b[:, ~M] == 0) and np.all(c[:, ~M] == 0)
+    for x in (a, b, c, d):
+        assert np.all(x[:, ~M] == 0)
