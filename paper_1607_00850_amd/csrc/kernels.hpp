@@ -325,8 +325,19 @@ constexpr bool col_live(int s) {
 // tile instead of nine, and half as many blocks as k_x_inv_curl.  The three
 // blocks of a tile go to one XCD, so each input row comes from HBM once.
 // KL: retained rows reach at most KL registers from either end (col_live).
+// Waves per SIMD at which a column-tiled block of W columns (an N x W tile
+// of LDS plus N twiddles) still fits twice on a CU, or 1 when the LDS allows
+// one block only.  Used as the second launch bound of column kernels whose
+// registers would otherwise leave one block per CU although the LDS holds two.
+template <typename T, class Plan, int W>
+constexpr int two_block_waves() {
+  constexpr long lds = (long)sizeof(cx<T>) * ((long)Plan::N * W + Plan::N);
+  constexpr int waves = W * Plan::Tl / 64;
+  return (2 * lds <= 163840 && waves <= 8) ? (2 * waves + 3) / 4 : 1;
+}
+
 template <typename T, class Plan, int W, int KL>
-__global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl3(const cx<T>* __restrict__ U, long csU, long isU,
+__global__ __launch_bounds__(W* Plan::Tl, (two_block_waves<T, Plan, W>())) void k_x_inv_curl3(const cx<T>* __restrict__ U, long csU, long isU,
                                                              cx<T>* __restrict__ A, long csA, long isA,
                                                              int ntiles, Geo g, T usc, const int* __restrict__ act) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
@@ -646,7 +657,7 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
 // packed rows A (component 2P) and B (component 2P + 1).  Arguments as
 // k_strided with IN_C = true, OUT_C = false; KL as col_live.
 template <typename T, class Plan, int W, int KL>
-__global__ __launch_bounds__(W* Plan::Tl) void k_y_inv_pack(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+__global__ __launch_bounds__(W* Plan::Tl, (two_block_waves<T, Plan, W>())) void k_y_inv_pack(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                             long ncols, long Qp, long ld_in, long ld_out, long bs_in,
                                                             long bs_out, long cs_in, long cs_out, long is_in,
                                                             long is_out, Geo g, const int* __restrict__ act) {
@@ -1012,53 +1023,85 @@ __global__ __launch_bounds__(256) void k_z_r2c(const T* __restrict__ in, cx<T>* 
 //   s=3: U0 = Acc + dt/6 du
 // mode 4: plain right-hand side, Acc = du (stage input U0).
 // ---------------------------------------------------------------------------
-// One mode of the stage update: n0..n2 the dealiased nonlinear term at compact
-// element e (component stride C) with integer wavenumbers kxi, kyi, kz.
+// The stage update in two halves, so that a caller can have the loads of
+// several elements in flight before it uses any of them.  RkIn holds what
+// stage MODE reads at compact element e (component stride C): the state the
+// viscous term acts on (U0 at stages 0 and 4, U1 at 1..3), U0 (stages 1, 2;
+// at stage 0 it is the same array as the first) and Acc (stages 1..3).
 template <typename T>
-__device__ __forceinline__ void rk_update(long e, cx<T> n0, cx<T> n1, cx<T> n2, int kxi, int kyi, int kz,
-                                          cx<T>* __restrict__ U0, cx<T>* __restrict__ U1, cx<T>* __restrict__ Acc,
-                                          long C, int mode, T nu, T dt) {
+struct RkIn {
+  cx<T> s[3], a[3], acc[3];
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void rk_load(long e, const cx<T>* __restrict__ U0, const cx<T>* __restrict__ U1,
+                                        const cx<T>* __restrict__ Acc, long C, RkIn<T>& r) {
+  static_for<0, 3>([&](auto c) {
+    r.s[c] = ((MODE == 0 || MODE == 4) ? U0 : U1)[c * C + e];
+    if constexpr (MODE == 1 || MODE == 2) r.a[c] = U0[c * C + e];
+    if constexpr (MODE >= 1 && MODE <= 3) r.acc[c] = Acc[c * C + e];
+  });
+}
+
+// n0..n2: the dealiased nonlinear term at element e, with integer
+// wavenumbers kxi, kyi, kz; r: what rk_load read there.
+template <typename T, int MODE>
+__device__ __forceinline__ void rk_apply(long e, cx<T> n0, cx<T> n1, cx<T> n2, int kxi, int kyi, int kz,
+                                         const RkIn<T>& r, cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
+                                         cx<T>* __restrict__ Acc, long C, T nu, T dt) {
   const int k2i = kxi * kxi + kyi * kyi + kz * kz;
   const T kx = T(kxi), ky = T(kyi), kzf = T(kz), k2 = T(k2i);
-  const cx<T>* us = (mode == 0 || mode == 4) ? U0 : U1;
-  const cx<T> s0 = us[e], s1 = us[C + e], s2 = us[2 * C + e];
   cx<T> kn = {T(0), T(0)};
   if (k2i != 0) {
     const T inv = T(1) / k2;
     kn = (n0 * kx + n1 * ky + n2 * kzf) * inv;
   }
   const T vk = nu * k2;
-  const cx<T> d0 = n0 - kn * kx - s0 * vk;
-  const cx<T> d1 = n1 - kn * ky - s1 * vk;
-  const cx<T> d2 = n2 - kn * kzf - s2 * vk;
-  if (mode == 4) {
-    store_stream(Acc + e, d0);
-    store_stream(Acc + C + e, d1);
-    store_stream(Acc + 2 * C + e, d2);
-    return;
-  }
-  if (mode == 3) {
+  const cx<T> d[3] = {n0 - kn * kx - r.s[0] * vk, n1 - kn * ky - r.s[1] * vk, n2 - kn * kzf - r.s[2] * vk};
+  if constexpr (MODE == 4) {
+    static_for<0, 3>([&](auto c) { store_stream(Acc + c * C + e, d[c]); });
+  } else if constexpr (MODE == 3) {
     const T h = dt / T(6);
-    store_stream(U0 + e, Acc[e] + d0 * h);
-    store_stream(U0 + C + e, Acc[C + e] + d1 * h);
-    store_stream(U0 + 2 * C + e, Acc[2 * C + e] + d2 * h);
-    return;
-  }
-  const cx<T> a0 = U0[e], a1 = U0[C + e], a2 = U0[2 * C + e];
-  const T ha = (mode == 0) ? dt / T(6) : dt / T(3);
-  const T hu = (mode == 2) ? dt : dt / T(2);
-  if (mode == 0) {
-    store_stream(Acc + e, a0 + d0 * ha);
-    store_stream(Acc + C + e, a1 + d1 * ha);
-    store_stream(Acc + 2 * C + e, a2 + d2 * ha);
+    static_for<0, 3>([&](auto c) { store_stream(U0 + c * C + e, r.acc[c] + d[c] * h); });
   } else {
-    store_stream(Acc + e, Acc[e] + d0 * ha);
-    store_stream(Acc + C + e, Acc[C + e] + d1 * ha);
-    store_stream(Acc + 2 * C + e, Acc[2 * C + e] + d2 * ha);
+    const T ha = (MODE == 0) ? dt / T(6) : dt / T(3);
+    const T hu = (MODE == 2) ? dt : dt / T(2);
+    static_for<0, 3>([&](auto c) {
+      const cx<T> a = (MODE == 0) ? r.s[c] : r.a[c];
+      store_stream(Acc + c * C + e, ((MODE == 0) ? a : r.acc[c]) + d[c] * ha);
+      store_stream(U1 + c * C + e, a + d[c] * hu);
+    });
   }
-  store_stream(U1 + e, a0 + d0 * hu);
-  store_stream(U1 + C + e, a1 + d1 * hu);
-  store_stream(U1 + 2 * C + e, a2 + d2 * hu);
+}
+
+// One mode of the stage update (runtime mode) at compact element e.
+template <typename T>
+__device__ __forceinline__ void rk_update(long e, cx<T> n0, cx<T> n1, cx<T> n2, int kxi, int kyi, int kz,
+                                          cx<T>* __restrict__ U0, cx<T>* __restrict__ U1, cx<T>* __restrict__ Acc,
+                                          long C, int mode, T nu, T dt) {
+  RkIn<T> r;
+  switch (mode) {
+    case 0:
+      rk_load<T, 0>(e, U0, U1, Acc, C, r);
+      rk_apply<T, 0>(e, n0, n1, n2, kxi, kyi, kz, r, U0, U1, Acc, C, nu, dt);
+      break;
+    case 1:
+      rk_load<T, 1>(e, U0, U1, Acc, C, r);
+      rk_apply<T, 1>(e, n0, n1, n2, kxi, kyi, kz, r, U0, U1, Acc, C, nu, dt);
+      break;
+    case 2:
+      rk_load<T, 2>(e, U0, U1, Acc, C, r);
+      rk_apply<T, 2>(e, n0, n1, n2, kxi, kyi, kz, r, U0, U1, Acc, C, nu, dt);
+      break;
+    case 3:
+      rk_load<T, 3>(e, U0, U1, Acc, C, r);
+      rk_apply<T, 3>(e, n0, n1, n2, kxi, kyi, kz, r, U0, U1, Acc, C, nu, dt);
+      break;
+    default:
+      rk_load<T, 4>(e, U0, U1, Acc, C, r);
+      rk_apply<T, 4>(e, n0, n1, n2, kxi, kyi, kz, r, U0, U1, Acc, C, nu, dt);
+      break;
+  }
 }
 
 template <typename T>
@@ -1081,6 +1124,54 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
     rk_update(e, Nh[e], Nh[C + e], Nh[2 * C + e], kwave(cpos(ix, g), g.N), kwave(cpos(iy, g), g.N), kz + g.kz0, U0,
               U1, Acc, C, mode, nu, dt);
   }
+}
+
+// Register s of the k-th live row of a column (col_live): the first KL and
+// the last KL registers, or all of them when those overlap.
+template <class Plan, int KL>
+constexpr int live_reg(int k) {
+  return 2 * KL >= Plan::R ? k : (k < KL ? k : Plan::R - 2 * KL + k);
+}
+template <class Plan, int KL>
+constexpr int live_regs() {
+  return 2 * KL >= Plan::R ? Plan::R : 2 * KL;
+}
+
+// The stage update of one column of k_x_fwd_rk: v[c][s] holds component c of
+// row j + s Tl.  Rows reach at most KL registers from either end (col_live):
+// the others are never kept, and their outputs are not computed.  The live
+// rows go in groups of GL, the loads of a whole group issued before any of its
+// updates, so that a thread waits on memory once per group rather than once
+// per row; a row outside the retained set loads from row 0 of its column
+// (always valid) and stores nothing.
+template <typename T, class Plan, int KL, int MODE, int GL = 2>
+__device__ __forceinline__ void x_rk_tail(const cx<T> (&v)[3][Plan::R], int j, long q, long Q, int kyi, int kz,
+                                          const Geo& g, cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
+                                          cx<T>* __restrict__ Acc, long C, T nu, T dt) {
+  constexpr int Tl = Plan::Tl, NL = live_regs<Plan, KL>();
+  static_for<0, (NL + GL - 1) / GL>([&](auto gi) {
+    RkIn<T> in[GL];
+    long e[GL];
+    bool kp[GL];
+    static_for<0, GL>([&](auto i) {
+      constexpr int k = decltype(gi)::value * GL + decltype(i)::value;
+      if constexpr (k < NL) {
+        const int p = j + live_reg<Plan, KL>(k) * Tl;
+        kp[i] = kept(p, g);
+        e[i] = (long)(kp[i] ? crow(p, g) : 0) * Q + q;
+        rk_load<T, MODE>(e[i], U0, U1, Acc, C, in[i]);
+      }
+    });
+    static_for<0, GL>([&](auto i) {
+      constexpr int k = decltype(gi)::value * GL + decltype(i)::value;
+      if constexpr (k < NL) {
+        constexpr int s = live_reg<Plan, KL>(k);
+        if (kp[i])
+          rk_apply<T, MODE>(e[i], v[0][s], v[1][s], v[2][s], kwave(j + s * Tl, Plan::N), kyi, kz + g.kz0, in[i], U0,
+                            U1, Acc, C, nu, dt);
+      }
+    });
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1133,16 +1224,13 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restric
   });
   if (!valid) return;
   const int kyi = kwave(cpos(iy, g), N);
-  // rows reach at most KL registers from either end (col_live): the others
-  // are never kept, and their outputs are not computed
-  static_for<0, R>([&](auto s) {
-    if constexpr (col_live<Plan, KL>(s)) {
-      const int p = j + s * Tl;
-      if (kept(p, g))
-        rk_update((long)crow(p, g) * Q + q, v[0][s], v[1][s], v[2][s], kwave(p, N), kyi, kz + g.kz0, U0, U1, Acc,
-                  C, mode, nu, dt);
-    }
-  });
+  switch (mode) {
+    case 0: x_rk_tail<T, Plan, KL, 0>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 1: x_rk_tail<T, Plan, KL, 1>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 2: x_rk_tail<T, Plan, KL, 2>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 3: x_rk_tail<T, Plan, KL, 3>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    default: x_rk_tail<T, Plan, KL, 4>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
