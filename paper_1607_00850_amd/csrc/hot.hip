@@ -66,6 +66,14 @@ static bool ops_for(int N, Ops* o) {
 // mode: 0 = 2/3 rule, 1 = all but Nyquist, 2 = every mode (plain transforms).
 // elem: bytes per complex value; the z pitch is padded to whole 128-byte rows
 // once rows are long enough for the padding to be cheap.
+// Column tile of the compact state arrays (cbase in kernels.hpp): 64 bytes of
+// a row where the z pitch is a multiple of it and holds whole 128-byte rows,
+// else one tile of all M*Mzp columns (row-major).
+static int state_tile(const Geo& g, int elem) {
+  const int tw = 64 / elem, seg = 128 / elem;
+  return (g.Mzp % seg == 0 && g.Mzp >= 4 * seg) ? tw : g.M * g.Mzp;
+}
+
 static Geo make_geo(int N, int mode, int elem) {
   Geo g{};
   g.N = N;
@@ -88,6 +96,7 @@ static Geo make_geo(int N, int mode, int elem) {
   g.Mzp = (mode != 2 && g.Mz >= 4 * seg) ? (g.Mz + seg - 1) / seg * seg : g.Mz;
   g.kz0 = 0;
   g.czp = N / 2 + 1;
+  g.tw = state_tile(g, elem);
   return g;
 }
 
@@ -498,7 +507,7 @@ void y_inv_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
       return G.ops.y_inv_pack(r.s, G.variant[PASS_Y_INV], q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2,
                               6 * G.D1, 6 * G.D2, G.B(), G.g, act);
     return G.ops.strided(r.s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1,
-                         G.D2, 6, 6 * G.D1, 6 * G.D2, G.B(), G.g, act);
+                         G.D2, 6, 6 * G.D1, 6 * G.D2, 0, G.B(), G.g, act);
   });
 }
 
@@ -517,7 +526,7 @@ void y_fwd_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
       return G.ops.y_fwd_unpack(r.s, G.variant[PASS_Y_FWD], q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1,
                                 6 * G.D2, 6 * G.D1, G.B(), G.g, act);
     return G.ops.strided(r.s, G.variant[PASS_Y_FWD] % 3, -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2,
-                         G.D1, 3, 6 * G.D2, 6 * G.D1, G.B(), G.g, act);
+                         G.D1, 3, 6 * G.D2, 6 * G.D1, 0, G.B(), G.g, act);
   });
 }
 
@@ -550,8 +559,8 @@ void forward_passes(Runner& r, const Group& G, const GroupPtrs& q, const int* ac
   if (!x_fwd) return;
   r.pass(PASS_X_FWD, [&] {
     const long Q = M * P;
-    return o.strided(r.s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3, isA1,
-                     isU, nb, g, act);
+    return o.strided(r.s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, g.tw, 0, 0, G.D1, G.C, 3,
+                     isA1, isU, g.tw, nb, g, act);
   });
 }
 
@@ -574,8 +583,8 @@ void rhs_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src, 
   if (!x_fwd) return;
   r.pass(PASS_X_FWD, [&] {
     const long Q = (long)G.g.M * G.g.Mzp;
-    return G.ops.strided(r.s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3,
-                         6 * G.D1, 3 * G.C, nb, G.g, act);
+    return G.ops.strided(r.s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, G.g.tw, 0, 0, G.D1, G.C,
+                         3, 6 * G.D1, 3 * G.C, G.g.tw, nb, G.g, act);
   });
 }
 
@@ -707,20 +716,20 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
           r.pass(PASS_Z_R2C, [&] { return o.z_r2c(r.s, in[i], Z1, 3 * N * N, g); });
           r.pass(PASS_Y_FWD, [&] {
             return o.strided(r.s, 1, -1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, 0, 0,
-                             1, g, nullptr);
+                             0, 1, g, nullptr);
           });
           r.pass(PASS_X_FWD, [&] {
             const long Q = N * Nh;
-            return o.strided(r.s, 1, -1, false, false, Z2, out[i], Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 1, g, nullptr);
+            return o.strided(r.s, 1, -1, false, false, Z2, out[i], Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 0, 1, g, nullptr);
           });
         } else {
           r.pass(PASS_X_INV, [&] {
             const long Q = N * Nh;
-            return o.strided(r.s, 1, +1, false, false, in[i], Z1, Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 1, g, nullptr);
+            return o.strided(r.s, 1, +1, false, false, in[i], Z1, Q, Q, Q, Q, 0, 0, D2, D2, 3, 0, 0, 0, 1, g, nullptr);
           });
           r.pass(PASS_Y_INV, [&] {
             return o.strided(r.s, 1, +1, false, false, Z1, Z2, N * Nh, Nh, Nh, Nh, N * Nh, N * Nh, D2, D2, 3, 0, 0,
-                             1, g, nullptr);
+                             0, 1, g, nullptr);
           });
           r.pass(PASS_Z_C2R, [&] { return o.z_c2r(r.s, Z2, out[i], 3 * N * N, g); });
         }
@@ -1130,16 +1139,16 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
                                       G.B(), g, nullptr);
             if (pid == PASS_Y_INV)
               return G.ops.strided(s, v, +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2, 6,
-                                   isA1, isA2, G.B(), g, nullptr);
+                                   isA1, isA2, 0, G.B(), g, nullptr);
             if (pid == PASS_Y_FWD && G.zpack == 1)
               return G.ops.y_fwd_unpack(s, v, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1, isA2, isA1,
                                         G.B(), g, nullptr);
             if (pid == PASS_Y_FWD)
               return G.ops.strided(s, v, -1, false, true, q.A2, q.A1, N * P, P, P, P, N * P, M * P, G.D2, G.D1, 3,
-                                   isA2, isA1, G.B(), g, nullptr);
+                                   isA2, isA1, 0, G.B(), g, nullptr);
             const long Q = M * P;
-            return G.ops.strided(s, v, -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C, 3, isA1, isU, G.B(),
-                                 g, nullptr);
+            return G.ops.strided(s, v, -1, false, true, q.A1, q.Nh, Q, Q, Q, g.tw, 0, 0, G.D1, G.C, 3, isA1, isU,
+                                 g.tw, G.B(), g, nullptr);
           });
           rc = r.rc;
         }
@@ -1241,8 +1250,8 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
           if (f < 0) {
             const long Q = G.g.M * (long)G.g.Mzp;
             r.pass(PASS_X_FWD, [&] {
-              return G.ops.strided(s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, Q, 0, 0, G.D1, G.C,
-                                   3, 6 * G.D1, 3 * G.C, G.B(), G.g, nullptr);
+              return G.ops.strided(s, G.variant[PASS_X_FWD], -1, false, true, q.A1, q.Nh, Q, Q, Q, G.g.tw, 0, 0, G.D1,
+                                   G.C, 3, 6 * G.D1, 3 * G.C, G.g.tw, G.B(), G.g, nullptr);
             });
             r.pass(PASS_RK_STAGE, [&] {
               return G.ops.rk_stage(s, q.Nh, q.U0, q.U1, q.Acc, G.C, 3 * G.C, G.B(), G.g, 1, p->nu, p->dt);
@@ -1353,6 +1362,7 @@ extern "C" int hot_plan_slab(const hot_desc* d, int32_t nranks, int32_t rank, ho
   G.g.Mz = full.Mz - kz0 < chunk ? full.Mz - kz0 : chunk;
   G.g.Mzp = pitch;
   G.g.czp = rank == nranks - 1 ? N / 2 + 1 - kz0 : chunk;
+  G.g.tw = state_tile(G.g, (int)p->elem);
   p->slab = true;
   p->nranks = nranks;
   p->rank = rank;

@@ -89,7 +89,8 @@ struct Ops {
   // act: per-instance flags of an implicit step (NULL: every instance runs)
   hipError_t (*strided)(hipStream_t, int variant, int dir, bool inc, bool outc, const void* in, void* out,
                         long ncols, long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in,
-                        long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo&, const int* act);
+                        long cs_out, int ncomp, long is_in, long is_out, long otw, int nb, const Geo&,
+                        const int* act);
   hipError_t (*x_inv_curl)(hipStream_t, int variant, const void* U, long csU, long isU, void* A, long csA, long isA,
                            int nb, const Geo&, const int* act);
   hipError_t (*z_cross)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&, const int* act);
@@ -158,21 +159,22 @@ struct Impl {
 
   template <int WW, int DIR, bool IC, bool OC>
   static void go(hipStream_t s, const void* in, void* out, long ncols, long Qp, long ld_in, long ld_out, long bs_in,
-                 long bs_out, long cs_in, long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo& g,
-                 const int* act) {
+                 long bs_out, long cs_in, long cs_out, int ncomp, long is_in, long is_out, long otw, int nb,
+                 const Geo& g, const int* act) {
     constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
     const long ntiles = (ncols + WW - 1) / WW;
     const long group = 8L * pair;
     dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)ncomp, (unsigned)nb);
     hipLaunchKernelGGL((k_strided<T, P, DIR, WW, IC, OC>), grid, dim3(WW * Tl), 0, s, (const cx<T>*)in, (cx<T>*)out,
-                       ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in, is_out, g, act);
+                       ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, is_in, is_out, otw, g, act);
   }
   template <int WW>
   static hipError_t strided_w(hipStream_t s, int dir, bool inc, bool outc, const void* in, void* out, long ncols,
                               long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in, long cs_out,
-                              int ncomp, long is_in, long is_out, int nb, const Geo& g, const int* act) {
-#define HOT_GO(D, I, O) \
-  go<WW, D, I, O>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, is_in, is_out, nb, g, act)
+                              int ncomp, long is_in, long is_out, long otw, int nb, const Geo& g, const int* act) {
+#define HOT_GO(D, I, O)                                                                                          \
+  go<WW, D, I, O>(s, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in, cs_out, ncomp, is_in, is_out, otw, nb, g, \
+                  act)
     if (dir > 0) {
       if (inc && !outc) HOT_GO(+1, true, false);
       else if (!inc && !outc) HOT_GO(+1, false, false);
@@ -187,14 +189,15 @@ struct Impl {
   }
   static hipError_t strided(hipStream_t s, int variant, int dir, bool inc, bool outc, const void* in, void* out,
                             long ncols, long Qp, long ld_in, long ld_out, long bs_in, long bs_out, long cs_in,
-                            long cs_out, int ncomp, long is_in, long is_out, int nb, const Geo& g, const int* act) {
+                            long cs_out, int ncomp, long is_in, long is_out, long otw, int nb, const Geo& g,
+                            const int* act) {
     switch (variant) {
       case 0: return strided_w<WV0>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
-                                    cs_out, ncomp, is_in, is_out, nb, g, act);
+                                    cs_out, ncomp, is_in, is_out, otw, nb, g, act);
       case 2: return strided_w<WV2>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
-                                    cs_out, ncomp, is_in, is_out, nb, g, act);
+                                    cs_out, ncomp, is_in, is_out, otw, nb, g, act);
       default: return strided_w<W>(s, dir, inc, outc, in, out, ncols, Qp, ld_in, ld_out, bs_in, bs_out, cs_in,
-                                   cs_out, ncomp, is_in, is_out, nb, g, act);
+                                   cs_out, ncomp, is_in, is_out, otw, nb, g, act);
     }
   }
   // short FP32 lines: all six outputs of a tile in one block (k_x_inv_curl6)
@@ -407,11 +410,16 @@ struct Impl {
     if (variant == 2) return x_fwd_rk_w<WQ>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
     return x_fwd_rk_w<WF>(s, A, csA, isA, U0, U1, Acc, C, isU, nb, g, mode, nu, dt);
   }
+  // the grid stride of k_gather in the digits of its loop
+  static Pos4 gather_step(long stride, const Geo& g) {
+    if (g.tw == g.M * g.Mzp) return pos4_of(stride, g.M, g.M, g.Mzp);
+    return pos4_of(stride, g.M * (g.Mzp / g.tw), g.M, g.tw);
+  }
   static hipError_t gather(hipStream_t s, const void* in0, const void* const* in_tab, void* out, long C, long is,
                            int nb, const Geo& g) {
     const unsigned grid = grid_1d((3 * C + 3) / 4, 256);  // a few elements per thread
     hipLaunchKernelGGL((k_gather<T>), dim3(grid, (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in0,
-                       (const cx<T>* const*)in_tab, (cx<T>*)out, C, is, g, pos4_of(256L * grid, g.M, g.M, g.Mzp));
+                       (const cx<T>* const*)in_tab, (cx<T>*)out, C, is, g, gather_step(256L * grid, g));
     return hipGetLastError();
   }
   static hipError_t scatter(hipStream_t s, const void* in, void* out0, void* const* out_tab, long C, long is, int nb,

@@ -30,6 +30,7 @@ struct Geo {
   int Mzp;        // z pitch of compact arrays (>= Mz)
   int kz0;        // kz of local column 0: 0, or the first kz of a z-slab share
   int czp;        // z extent of the canonical in/out arrays: N/2+1, or a slab share's
+  int tw;         // column tile of compact state arrays (cbase)
 };
 
 __device__ __forceinline__ bool kept(int p, const Geo& g) { return p < g.lo || p >= g.N - g.hi; }
@@ -39,6 +40,41 @@ __device__ __forceinline__ int crow(int p, const Geo& g) { return p < g.lo ? p :
 __device__ __forceinline__ int cpos(int i, const Geo& g) { return i < g.lo ? i : i + (g.N - g.M); }
 // signed wavenumber (Eq. wavemesh) of FFT position p
 __device__ __forceinline__ int kwave(int p, int N) { return 2 * p <= N ? p : p - N; }
+
+// Compact state arrays (per instance [3][C]: the state, the stage arrays, the
+// nonlinear term and the implicit step's buffers) hold a component as column
+// tiles: column q = (compact ky row) * Mzp + kz of compact kx row ix sits at
+// cbase(q) + ix * tw, where cbase(q) = (q / tw) * M * tw + q mod tw.  With
+// tw = 8 (FP32) or 4 (FP64) a tile's M rows are 64 bytes each and contiguous,
+// so a pass along x over tw or more adjacent columns reads and writes whole
+// runs of memory.  tw = M * Mzp (one tile) is the row-major [M][M][Mzp]
+// layout, kept where Mzp is not a multiple of the tile.  Indices fit 32 bits
+// (C < 2^32 for every planned size).
+__device__ __forceinline__ long cbase(long q, const Geo& g) {
+  const unsigned t = (unsigned)q / (unsigned)g.tw;
+  return (long)t * ((long)g.M * g.tw) + (long)((unsigned)q - t * (unsigned)g.tw);
+}
+
+// Compact element e of one component: its wavenumbers, or false for row
+// padding.
+struct ModeK {
+  int kx, ky, kz;
+};
+__device__ __forceinline__ bool mode_of(long e, const Geo& g, ModeK& m) {
+  const unsigned tw = (unsigned)g.tw, MT = (unsigned)g.M * tw;
+  const unsigned ue = (unsigned)e;
+  const unsigned tile = ue / MT;
+  const unsigned r = ue - tile * MT;
+  const unsigned ix = r / tw;
+  const unsigned q = tile * tw + (r - ix * tw);
+  const unsigned iy = q / (unsigned)g.Mzp;
+  m.kz = (int)(q - iy * (unsigned)g.Mzp);
+  if (m.kz >= g.Mz) return false;
+  m.kz += g.kz0;
+  m.kx = kwave(cpos((int)ix, g), g.N);
+  m.ky = kwave(cpos((int)iy, g), g.N);
+  return true;
+}
 
 // Stores of pass outputs: streamed (non-temporal), since no kernel re-reads
 // them while they could still sit in a cache.  (Measured on MI355X: faster
@@ -176,6 +212,8 @@ __device__ __forceinline__ long tile_of_block(long b) {
 // The array is a batch of [rows][Qp] blocks (global column gc = b*Qp + q);
 // a column is live iff (q mod Mzp) < Mz (the rest is row padding).
 // IN_C / OUT_C: rows are compact (retained positions only) or all N.
+// otw > 0 (with OUT_C): the output is a compact state array (cbase), its
+// columns in tiles of otw and its rows otw apart (ld_out = otw).
 // blockIdx.y selects the component (stride cs_*), blockIdx.z the instance of
 // a batch of equal-size instances (stride is_*).
 // ---------------------------------------------------------------------------
@@ -183,7 +221,7 @@ template <typename T, class Plan, int DIR, int W, bool IN_C, bool OUT_C>
 __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                          long ncols, long Qp, long ld_in, long ld_out, long bs_in,
                                                          long bs_out, long cs_in, long cs_out, long is_in,
-                                                         long is_out, Geo g, const int* __restrict__ act) {
+                                                         long is_out, long otw, Geo g, const int* __restrict__ act) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
@@ -203,7 +241,10 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_strided(const cx<T>* __restrict
   const bool valid = gc < ncols && (int)(q % g.Mzp) < g.Mz;
   // blockIdx.y: component, blockIdx.z: instance of a batch
   const long ib = valid ? blockIdx.z * is_in + blockIdx.y * cs_in + b * bs_in + q : 0;
-  const long ob = valid ? blockIdx.z * is_out + blockIdx.y * cs_out + b * bs_out + q : 0;
+  // otw > 0: the output is a compact state array, its columns in tiles of otw
+  // (cbase; ld_out is then otw)
+  const long oq = otw > 0 ? (q / otw) * ((long)g.M * otw) + q % otw : q;
+  const long ob = valid ? blockIdx.z * is_out + blockIdx.y * cs_out + b * bs_out + oq : 0;
   cx<T> v[R];
   static_for<0, R>([&](auto s) {
     const int p = j + s * Tl;
@@ -279,21 +320,22 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl(const cx<T>* __restr
   // are all in flight together.
   const int ca = o < 3 ? o : (o == 3 ? 2 : (o == 4 ? 0 : 1));
   const int cb = o == 3 ? 1 : (o == 4 ? 2 : 0);
-  const cx<T>* pa = U + ca * csU + qq;
-  const cx<T>* pb = U + cb * csU + qq;
+  const long ub = cbase(qq, g);
+  const cx<T>* pa = U + ca * csU + ub;
+  const cx<T>* pb = U + cb * csU + ub;
   cx<T> v[R];
   if (o < 3) {
     static_for<0, R>([&](auto s) {
       const int p = j + s * Tl;
       const bool kp = valid && kept(p, g);
-      const cx<T> x = pa[kp ? (long)crow(p, g) * Q : 0];
+      const cx<T> x = pa[kp ? (long)crow(p, g) * g.tw : 0];
       v[s] = kp ? x * usc : cx<T>{T(0), T(0)};
     });
   } else {
     static_for<0, R>([&](auto s) {
       const int p = j + s * Tl;
       const bool kp = valid && kept(p, g);
-      const long off = kp ? (long)crow(p, g) * Q : 0;
+      const long off = kp ? (long)crow(p, g) * g.tw : 0;
       const cx<T> a = pa[off], b = pb[off];
       const T kx = T(kwave(p, N));
       const T fa = (o == 3 ? ky : (o == 4 ? kzf : kx)) * usc;
@@ -325,19 +367,8 @@ constexpr bool col_live(int s) {
 // tile instead of nine, and half as many blocks as k_x_inv_curl.  The three
 // blocks of a tile go to one XCD, so each input row comes from HBM once.
 // KL: retained rows reach at most KL registers from either end (col_live).
-// Waves per SIMD at which a column-tiled block of W columns (an N x W tile
-// of LDS plus N twiddles) still fits twice on a CU, or 1 when the LDS allows
-// one block only.  Used as the second launch bound of column kernels whose
-// registers would otherwise leave one block per CU although the LDS holds two.
-template <typename T, class Plan, int W>
-constexpr int two_block_waves() {
-  constexpr long lds = (long)sizeof(cx<T>) * ((long)Plan::N * W + Plan::N);
-  constexpr int waves = W * Plan::Tl / 64;
-  return (2 * lds <= 163840 && waves <= 8) ? (2 * waves + 3) / 4 : 1;
-}
-
 template <typename T, class Plan, int W, int KL>
-__global__ __launch_bounds__(W* Plan::Tl, (two_block_waves<T, Plan, W>())) void k_x_inv_curl3(const cx<T>* __restrict__ U, long csU, long isU,
+__global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl3(const cx<T>* __restrict__ U, long csU, long isU,
                                                              cx<T>* __restrict__ A, long csA, long isA,
                                                              int ntiles, Geo g, T usc, const int* __restrict__ act) {
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
@@ -366,8 +397,9 @@ __global__ __launch_bounds__(W* Plan::Tl, (two_block_waves<T, Plan, W>())) void 
   U += blockIdx.y * isU;  // instance of a batch
   A += blockIdx.y * isA;
   const int m1 = m == 2 ? 0 : m + 1;
-  const cx<T>* pa = U + m * csU + qq;
-  const cx<T>* pb = U + m1 * csU + qq;
+  const long ub = cbase(qq, g);
+  const cx<T>* pa = U + m * csU + ub;
+  const cx<T>* pb = U + m1 * csU + ub;
   // every lane loads from a valid address (row 0 when the position is not
   // retained) and selects afterwards: no branches around the loads
   cx<T> a[R], v[R];
@@ -375,7 +407,7 @@ __global__ __launch_bounds__(W* Plan::Tl, (two_block_waves<T, Plan, W>())) void 
     if constexpr (col_live<Plan, KL>(s)) {
       const int p = j + s * Tl;
       const bool kp = valid && kept(p, g);
-      const long off = kp ? (long)crow(p, g) * Q : 0;
+      const long off = kp ? (long)crow(p, g) * g.tw : 0;
       const cx<T> x = pa[off], y = pb[off];
       const T kx = T(kwave(p, N));
       const T km = (m == 0 ? kx : (m == 1 ? ky : kzf)) * usc;
@@ -435,12 +467,13 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __rest
   const long qq = valid ? q : 0;
   U += blockIdx.y * isU;
   A += blockIdx.y * isA;
+  const long ub = cbase(qq, g);
   cx<T> u[3][R];
   static_for<0, 3>([&](auto comp) {
     static_for<0, R>([&](auto s) {
       const int p = j + s * Tl;
       const bool kp = valid && kept(p, g);
-      const cx<T> x = U[comp * csU + qq + (kp ? (long)crow(p, g) * Q : 0)];
+      const cx<T> x = U[comp * csU + ub + (kp ? (long)crow(p, g) * g.tw : 0)];
       u[comp][s] = kp ? x * usc : cx<T>{T(0), T(0)};
     });
   });
@@ -657,7 +690,7 @@ __global__ __launch_bounds__(256) void k_z_cross(cx<T>* __restrict__ A, long csA
 // packed rows A (component 2P) and B (component 2P + 1).  Arguments as
 // k_strided with IN_C = true, OUT_C = false; KL as col_live.
 template <typename T, class Plan, int W, int KL>
-__global__ __launch_bounds__(W* Plan::Tl, (two_block_waves<T, Plan, W>())) void k_y_inv_pack(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+__global__ __launch_bounds__(W* Plan::Tl) void k_y_inv_pack(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                             long ncols, long Qp, long ld_in, long ld_out, long bs_in,
                                                             long bs_out, long cs_in, long cs_out, long is_in,
                                                             long is_out, Geo g, const int* __restrict__ act) {
@@ -1114,15 +1147,10 @@ __global__ __launch_bounds__(256) void k_rk_stage(const cx<T>* __restrict__ Nh, 
   U0 += ib;
   U1 += ib;
   Acc += ib;
-  const long MMz = (long)g.M * g.Mzp;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < C; e += stride) {
-    const int ix = (int)(e / MMz);
-    const long r = e - ix * MMz;
-    const int iy = (int)(r / g.Mzp);
-    const int kz = (int)(r - (long)iy * g.Mzp);
-    if (kz >= g.Mz) continue;  // row padding
-    rk_update(e, Nh[e], Nh[C + e], Nh[2 * C + e], kwave(cpos(ix, g), g.N), kwave(cpos(iy, g), g.N), kz + g.kz0, U0,
-              U1, Acc, C, mode, nu, dt);
+    ModeK m;
+    if (!mode_of(e, g, m)) continue;  // row padding
+    rk_update(e, Nh[e], Nh[C + e], Nh[2 * C + e], m.kx, m.ky, m.kz, U0, U1, Acc, C, mode, nu, dt);
   }
 }
 
@@ -1143,9 +1171,10 @@ constexpr int live_regs() {
 // rows go in groups of GL, the loads of a whole group issued before any of its
 // updates, so that a thread waits on memory once per group rather than once
 // per row; a row outside the retained set loads from row 0 of its column
-// (always valid) and stores nothing.
+// (always valid) and stores nothing.  cb: the column's row 0 in the compact
+// state arrays (cbase).
 template <typename T, class Plan, int KL, int MODE, int GL = 2>
-__device__ __forceinline__ void x_rk_tail(const cx<T> (&v)[3][Plan::R], int j, long q, long Q, int kyi, int kz,
+__device__ __forceinline__ void x_rk_tail(const cx<T> (&v)[3][Plan::R], int j, long cb, int kyi, int kz,
                                           const Geo& g, cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
                                           cx<T>* __restrict__ Acc, long C, T nu, T dt) {
   constexpr int Tl = Plan::Tl, NL = live_regs<Plan, KL>();
@@ -1158,7 +1187,7 @@ __device__ __forceinline__ void x_rk_tail(const cx<T> (&v)[3][Plan::R], int j, l
       if constexpr (k < NL) {
         const int p = j + live_reg<Plan, KL>(k) * Tl;
         kp[i] = kept(p, g);
-        e[i] = (long)(kp[i] ? crow(p, g) : 0) * Q + q;
+        e[i] = cb + (long)(kp[i] ? crow(p, g) : 0) * g.tw;
         rk_load<T, MODE>(e[i], U0, U1, Acc, C, in[i]);
       }
     });
@@ -1224,12 +1253,13 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restric
   });
   if (!valid) return;
   const int kyi = kwave(cpos(iy, g), N);
+  const long cb = cbase(q, g);
   switch (mode) {
-    case 0: x_rk_tail<T, Plan, KL, 0>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
-    case 1: x_rk_tail<T, Plan, KL, 1>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
-    case 2: x_rk_tail<T, Plan, KL, 2>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
-    case 3: x_rk_tail<T, Plan, KL, 3>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
-    default: x_rk_tail<T, Plan, KL, 4>(v, j, q, Q, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 0: x_rk_tail<T, Plan, KL, 0>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 1: x_rk_tail<T, Plan, KL, 1>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 2: x_rk_tail<T, Plan, KL, 2>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 3: x_rk_tail<T, Plan, KL, 3>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    default: x_rk_tail<T, Plan, KL, 4>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
   }
 }
 
@@ -1247,23 +1277,6 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restric
 // kernel leaves such an instance alone.
 // ---------------------------------------------------------------------------
 
-// Compact element e of a [M][M][Mzp] component: its wavenumbers, or false for
-// row padding.
-struct ModeK {
-  int kx, ky, kz;
-};
-__device__ __forceinline__ bool mode_of(long e, const Geo& g, ModeK& m) {
-  const long MMz = (long)g.M * g.Mzp;
-  const int ix = (int)(e / MMz);
-  const long r = e - ix * MMz;
-  const int iy = (int)(r / g.Mzp);
-  m.kz = (int)(r - (long)iy * g.Mzp);
-  if (m.kz >= g.Mz) return false;
-  m.kz += g.kz0;
-  m.kx = kwave(cpos(ix, g), g.N);
-  m.ky = kwave(cpos(iy, g), g.N);
-  return true;
-}
 
 // Predictor from the increments of earlier steps (H1 newest): hist = 0: d = 0;
 // 1: d = H1; 2: d = 2 H1 - H2.  Writes d and the midpoint U1 = U0 + d/2, and
@@ -1527,8 +1540,8 @@ __global__ __launch_bounds__(64) void k_state_final(const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// Canonical <-> compact.  Canonical: [3][N][N][N/2+1].  Compact:
-// [3][M][M][Mzp].  Gather drops the modes outside the retained set
+// Canonical <-> compact.  Canonical: [3][N][N][N/2+1].  Compact: the state
+// layout of cbase.  Gather drops the modes outside the retained set
 // (projection onto the Galerkin space); scatter writes zeros there.
 // blockIdx.y is the instance of a batch; the canonical array of instance b
 // is tab[b] when a device pointer table is given.
@@ -1602,12 +1615,26 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in0, c
   const long stride = (long)gridDim.x * blockDim.x;
   const long Nh = g.czp;  // canonical z extent; its kz 0 is local column 0
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  // compact [3][M][M][Mzp]; st: the grid stride in the same digits
-  Pos4 p = pos4_first((unsigned)e, g.M, g.M, g.Mzp);
-  for (; p.c < 3; e += stride, pos4_add(p, st, g.M, g.M, g.Mzp)) {
-    if (p.z >= g.Mz) continue;
-    const long src = (((long)p.c * g.N + cpos(p.a, g)) * g.N + cpos(p.b, g)) * Nh + p.z;
-    store_stream(out + e, in[src]);
+  if (g.tw == g.M * g.Mzp) {
+    // row-major compact [3][M][M][Mzp]; st: the grid stride in the same digits
+    Pos4 p = pos4_first((unsigned)e, g.M, g.M, g.Mzp);
+    for (; p.c < 3; e += stride, pos4_add(p, st, g.M, g.M, g.Mzp)) {
+      if (p.z >= g.Mz) continue;
+      const long src = (((long)p.c * g.N + cpos(p.a, g)) * g.N + cpos(p.b, g)) * Nh + p.z;
+      store_stream(out + e, in[src]);
+    }
+  } else {
+    // column tiles [3][Q/tw][M][tw] (cbase); st in the same digits
+    const int nt = g.M * (g.Mzp / g.tw);
+    Pos4 p = pos4_first((unsigned)e, nt, g.M, g.tw);
+    for (; p.c < 3; e += stride, pos4_add(p, st, nt, g.M, g.tw)) {
+      const unsigned q = (unsigned)p.a * g.tw + p.z;
+      const unsigned iy = q / (unsigned)g.Mzp;
+      const int kz = (int)(q - iy * (unsigned)g.Mzp);
+      if (kz >= g.Mz) continue;
+      const long src = (((long)p.c * g.N + cpos(p.b, g)) * g.N + cpos((int)iy, g)) * Nh + kz;
+      store_stream(out + e, in[src]);
+    }
   }
 }
 
@@ -1624,7 +1651,7 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, c
   for (; p.c < 3; e += stride, pos4_add(p, st, g.N, g.N, Nh)) {
     cx<T> v = {T(0), T(0)};
     if (p.z < g.Mz && kept(p.a, g) && kept(p.b, g))
-      v = in[(long)p.c * C + ((long)crow(p.a, g) * g.M + crow(p.b, g)) * g.Mzp + p.z];
+      v = in[(long)p.c * C + cbase((long)crow(p.b, g) * g.Mzp + p.z, g) + (long)crow(p.a, g) * g.tw];
     store_stream(out + e, v);
   }
 }

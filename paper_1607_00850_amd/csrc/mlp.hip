@@ -190,6 +190,7 @@ int hot_mlp_dataset(int32_t N, int32_t dtype, const void* u, const void* d1, con
   g.M = 2 * K + 1;
   g.Mz = g.Mzp = K + 1;
   g.czp = N / 2 + 1;
+  g.tw = g.M * g.Mzp;
   const long rows = (long)g.M * g.M * g.Mz;
   long blocks = (rows + 255) / 256;
   if (blocks > 16384) blocks = 16384;
