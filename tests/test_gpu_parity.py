@@ -221,6 +221,26 @@ def test_radix3_sizes_match_oracle(N, dtype):
     assert rel_l2(got, oracle.rk4(ref_input(uh, dtype), NU, DT, 1)) < tol(dtype, N)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N", [16, 64])
+def test_row_forms_drop_the_imaginary_part_at_kz0(N, dtype):
+    # a kz = 0 plane that is not Hermitian: the real inverse transform along z
+    # (Eq. ffteq with a real field) uses only the real part of each (x, y)
+    # line's k = 0 coefficient, as numpy's irfftn does in the oracle: each
+    # row form of the y and z passes, and the fused y-z pass, must drop the
+    # imaginary part there.
+    print(f"kz0 plane N={N} {dtype}", flush=True)
+    uh = inputs.rough_random(N, 400 + N)
+    rng = np.random.default_rng(N)
+    M = oracle.retained_mask(N)
+    pert = (rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))) * np.abs(uh).max()
+    uh[:, :, :, 0] += np.where(M[:, :, 0], pert, 0)
+    ref = oracle.rhs(ref_input(uh, dtype), NU)
+    for v in ({"z_cross": 1}, {"z_cross": 2}, {"z_cross": 0}, {"z_cross": 1, "y_fwd": 4}, {"yz_fused": 0}):
+        (got,) = run("rhs", [uh], dtype, nu=NU, variants=v)
+        assert rel_l2(got, ref) < tol(dtype, N), v
+
+
 # -- the x pass fused with the stage update (x_fwd_rk) -----------------------------
 
 @pytest.mark.parametrize("dtype", DTYPES)
