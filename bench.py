@@ -86,15 +86,22 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, command):
     true_bytes = float(calib_mib) * 2**20
     fs = true_bytes / (fetch[COPY_KERNEL][0] * 1024.0)
     ws = true_bytes / (write[COPY_KERNEL][0] * 1024.0)
-    names = {"k_z_cross": "z_cross", "k_x_inv_curl": "x_inv_curl", "k_rk_stage": "rk_stage",
-             "k_gather": "gather", "k_scatter": "scatter", "y_inv": "y_inv", "k_x_fwd_rk": "x_fwd_rk"}
+    # kernel -> pass; several kernels can serve one pass (the row forms, the
+    # x inverse variants); k_strided forward with compact output rows is the
+    # y forward pass when the x forward pass is fused with the stage update
+    names = {"k_z_cross": "z_cross", "k_z_cross_packed": "z_cross", "k_x_inv_curl": "x_inv_curl",
+             "k_x_inv_curl3": "x_inv_curl", "k_rk_stage": "rk_stage", "k_gather": "gather",
+             "k_scatter": "scatter", "y_inv": "y_inv", "k_y_inv_pack": "y_inv", "k_x_fwd_rk": "x_fwd_rk",
+             "y_or_x_fwd": "y_fwd", "k_y_fwd_unpack": "y_fwd"}
     out = {"fetch_scale": fs, "write_scale": ws, "command": command}
-    for k, pname in names.items():
-        if k in fetch and k in write:
-            f = sum(fetch[k]) / len(fetch[k]) * 1024.0 * fs
-            w = sum(write[k]) / len(write[k]) * 1024.0 * ws
+    for pname in sorted(set(names.values())):
+        fv = [v for k, n in names.items() if n == pname and k in fetch and k in write for v in fetch[k]]
+        wv = [v for k, n in names.items() if n == pname and k in fetch and k in write for v in write[k]]
+        if fv and wv:
+            f = sum(fv) / len(fv) * 1024.0 * fs
+            w = sum(wv) / len(wv) * 1024.0 * ws
             out[pname] = {"fetch_bytes": f, "write_bytes": w, "hbm_bytes_per_launch": f + w,
-                          "dispatches": len(fetch[k]), "source_hash": source_hash()}
+                          "dispatches": len(fv), "source_hash": source_hash()}
     path = os.path.join(ROOT, "profiles", "counters.json")
     d = json.load(open(path)) if os.path.exists(path) else {}
     d[workload] = out

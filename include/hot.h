@@ -19,9 +19,11 @@
  *   element type: double (HOT_F64) or float (HOT_F32).
  *
  * Ownership: the caller allocates inputs, outputs and the workspace (e.g.
- * torch tensors); the library never allocates or frees device memory and
- * never synchronises inside hot_run, which only enqueues kernels on the
- * given stream.  All device pointers must be 256-byte aligned.
+ * torch tensors); the library never allocates or frees device memory, and
+ * hot_run only enqueues kernels on the given stream (two documented
+ * exceptions wait for it: CHECK_FINITE plans, and an IMPLICIT call's looks at
+ * its stopping flags, see HOT_OP_IMPLICIT).  All device pointers must be
+ * 256-byte aligned.
  *
  * Thread safety: a plan may be used from one host thread at a time.  Two
  * hot_run calls that share a workspace must be ordered on one stream.
@@ -83,10 +85,15 @@ extern "C" {
  *       extrapolation 2 d^{n-1} - d^{n-2} after that (or the surrogate's
  *       warm start, see hot_set_surrogate; with HOT_FLAG_KEEP_HISTORY the
  *       history carries over from the previous call).  Each instance stops on
- *       its own: every step enqueues max_iter sweeps, whose kernels return at
- *       once for an instance that has stopped, so the host never waits for
- *       the stopping test.  The sweep counts stay on the device (hot_stats,
- *       hot_implicit_stats).  in == out allowed. */
+ *       its own: the kernels of a sweep return at once for an instance that
+ *       has stopped.  Sweeps are enqueued in rounds of K (hot_set_variant
+ *       pass "imp_decide", default 3); after each round but the last an
+ *       eager call copies the stopping flags to the host, waits for them,
+ *       and enqueues no further sweeps for a size whose instances have all
+ *       stopped (a sweep launches every block even when they all return at
+ *       once).  K = 0, and every call captured by hot_graph_create, enqueue
+ *       all max_iter sweeps and never wait.  The sweep counts stay on the
+ *       device (hot_stats, hot_implicit_stats).  in == out allowed. */
 #define HOT_OP_R2C 0
 #define HOT_OP_C2R 1
 #define HOT_OP_RHS 2
@@ -147,7 +154,8 @@ typedef struct hot_stats {
 int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes);
 
 /* Enqueue the planned operation on stream (a hipStream_t; NULL = default).
- * The call never synchronises (a CHECK_FINITE plan excepted).
+ * The call never synchronises, except for a CHECK_FINITE plan and the looks
+ * at the stopping flags of an IMPLICIT call (HOT_OP_IMPLICIT).
  * in[i], out[i]: device pointers of instance i (layouts above; R2C reads
  * physical and writes spectral, C2R the reverse, RHS/RK4/IMPLICIT spectral
  * both).  Instances must not overlap each other (in[i] == out[i] is allowed).
@@ -228,7 +236,10 @@ int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
  * graphs hot_graph_create captures from then on: 1 (the default) one branch
  * per distinct N, forked from and joined back into the capturing stream, so
  * the passes of small sizes run beside those of large ones; 0 the sizes one
- * after another.  Host only.  Errors: HOT_E_INVALID. */
+ * after another; for "imp_decide" (IMPLICIT plans only) the sweeps per round
+ * between an eager call's looks at the stopping flags, K >= 0 (default 3; 0:
+ * never look, enqueue max_iter sweeps).  hot_tuned_width reports these
+ * settings for the non-tiled passes.  Host only.  Errors: HOT_E_INVALID. */
 int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant);
 
 /* IMPLICIT statistics of the plan's last hot_run (or graph capture), per

@@ -279,19 +279,47 @@ struct Stages<T, DIR, N, R, Ns, OFF, r, Rs...> {
   static constexpr int NEXT_OFF = Ns > 1 ? OFF + (r - 1) * Ns : OFF;
   static_assert(R % r == 0, "each radix must divide the per-thread count");
 
+  // Butterfly jj = j + m Tl (0 <= j < Tl) splits as jj = blk Ns + res.  With
+  // Tl and Ns compile-time, most splits need no division: when the m-th
+  // range [m Tl, (m+1) Tl) lies inside one Ns-block, blk is a constant and
+  // res = j + constant; when Ns divides Tl, res = j mod Ns for every m and
+  // blk = j / Ns + m Tl / Ns, split once per stage.  (Divisions by the
+  // constant non-powers of two of the radix-6 and radix-3 lengths cost about
+  // as much as their butterflies.)
+  template <int m>
+  static constexpr bool in_one_block() {
+    return (m * Tl) / Ns == (m * Tl + Tl - 1) / Ns;
+  }
   template <class L, class TW>
   __device__ __forceinline__ static void run(cx<T>* v, int j, L& lds, const TW& tw) {
+    constexpr bool hoist = Ns > 1 && Tl % Ns == 0;
+    const int j_blk = hoist ? j / Ns : 0;
+    const int j_res = hoist ? j - j_blk * Ns : 0;
     static_for<0, nb>([&](auto m) {
       const int jj = j + m * Tl;
+      int blk, res;
+      if constexpr (Ns == 1) {
+        blk = jj;
+        res = 0;
+      } else if constexpr (in_one_block<decltype(m)::value>()) {
+        constexpr int b0 = (decltype(m)::value * Tl) / Ns;
+        blk = b0;
+        res = jj - b0 * Ns;
+      } else if constexpr (hoist) {
+        blk = j_blk + m * (Tl / Ns);
+        res = j_res;
+      } else {
+        blk = jj / Ns;
+        res = jj - blk * Ns;
+      }
       cx<T> b[r];
       static_for<0, r>([&](auto q) { b[q] = v[m + q * nb]; });
       if constexpr (Ns > 1) {
-        const int res = jj % Ns;
         static_for<1, r>([&](auto q) { b[q] = twmul<DIR>(b[q], tw(OFF + (q - 1) * Ns + res)); });
       }
       Dft<r, DIR, T>::run(b);
       if constexpr (!last) {
-        const int ob = (jj / Ns) * (Ns * r) + (jj % Ns);
+        const int ob = blk * (Ns * r) + res;
         static_for<0, r>([&](auto q) { lds.put(ob + q * Ns, b[q]); });
       } else {
         static_for<0, r>([&](auto q) { v[m + q * nb] = b[q]; });

@@ -176,6 +176,8 @@ struct hot_plan_s {
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> side_ev;
   bool graph_branches = true;  // hot_set_variant(graph_branches): 1 branch per group, 0 one chain
+  int imp_check = 3;           // implicit step: sweeps between the host's looks at the flags (0: never)
+  std::vector<int> act_host;   // implicit step: the flags read back, per instance
 };
 
 struct hot_graph_s {
@@ -287,6 +289,7 @@ int hot_plan(const hot_desc* d, hot_plan_t* out, size_t* workspace_bytes) {
   p->elem = d->dtype == HOT_F64 ? 16 : 8;
   p->batch = d->batch;
   p->n.assign(d->n, d->n + d->batch);
+  p->act_host.assign(d->batch, 0);
   p->last_hip = 0;
   p->prof = false;
   p->ws_bytes = 0;
@@ -782,14 +785,22 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
   return r.rc;
 }
 
-// The implicit step, group by group and step by step.  Each step: the
-// predictor, then max_iter Picard sweeps (the right-hand-side passes on the
-// midpoint, the update of d, the stopping test); every pass kernel returns at
-// once for an instance whose stopping flag is clear, so each instance stops on
-// its own and the host never waits for the flags.  The counters of the call
-// (sweeps, steps stopped at max_iter) stay on the device.  The iterate d lives
-// in Acc and the two increment histories in H1, H2; the three buffers rotate
-// at the end of a step (d becomes the newest history).
+// The implicit step, step by step over every group.  Each step: the
+// predictor, then up to max_iter Picard sweeps (the right-hand-side passes on
+// the midpoint, the update of d, the stopping test); every pass kernel returns
+// at once for an instance whose stopping flag is clear, so each instance stops
+// on its own.  The counters of the call (sweeps, steps stopped at max_iter)
+// stay on the device.  The iterate d lives in Acc and the two increment
+// histories in H1, H2; the three buffers rotate at the end of a step (d
+// becomes the newest history).
+//
+// Sweeps go out in rounds of imp_check over every group still iterating
+// (each group on its own stream with branches).  Between rounds an eager call
+// copies the flags of those groups to the host and waits for their streams:
+// once no instance of a group iterates, its remaining sweeps are not enqueued
+// (a sweep whose flags are all clear still launches every block of every
+// pass).  A captured call (record == false) or imp_check == 0 enqueues all
+// max_iter sweeps and never waits.
 int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t s,
                  bool record, StatsRec* stats, bool branches = false) {
   Runner r{p, s, record};
@@ -802,64 +813,134 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
       return HOT_E_HIP;
     }
   }
-  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+  const size_t ng = p->groups.size();
+  auto stream_of = [&](size_t gi) { return br ? p->side[gi] : s; };
+  std::vector<GroupPtrs> qs(ng);
+  for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {
     Group& G = p->groups[gi];
-    if (r.rc != HOT_OK) break;
-    r.s = br ? p->side[gi] : s;
+    r.s = stream_of(gi);
     if (!keep) {
       G.rot = 0;
       G.hist = 0;
     }
-    const GroupPtrs q = group_ptrs(G, workspace);
-    const Ops& o = G.ops;
-    const Geo& g = G.g;
-    const int nb = G.B();
-    const long isU = 3 * G.C;
-    const void* in0 = in[G.members[0]];
-    void* out0 = out[G.members[0]];
+    const GroupPtrs& q = qs[gi] = group_ptrs(G, workspace);
     write_tables(r, G, q, in, out);
     r.pass(PASS_IMP_DECIDE, [&] {  // the call's counters start at zero
-      hipLaunchKernelGGL(k_fill_int<>, dim3(grid_1d(2 * nb, 256)), dim3(256), 0, r.s, q.cnt, 2L * nb, 0);
+      hipLaunchKernelGGL(k_fill_int<>, dim3(grid_1d(2 * G.B(), 256)), dim3(256), 0, r.s, q.cnt, 2L * G.B(), 0);
       return hipGetLastError();
     });
-    r.pass(PASS_GATHER, [&] { return o.gather(r.s, in0, q.in_tab, q.U0, G.C, isU, nb, g); });
+    r.pass(PASS_GATHER,
+           [&] { return G.ops.gather(r.s, in[G.members[0]], q.in_tab, q.U0, G.C, 3 * G.C, G.B(), G.g); });
+  }
+  const int every = record ? p->imp_check : 0;
+  std::vector<char> live(ng);
+  for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
     // the iterate d and the histories H1 (newest), H2 rotate through three buffers
-    char* buf[3] = {q.Acc, q.H[0], q.H[1]};
-    for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
-      char *D = buf[G.rot], *H1 = buf[(G.rot + 1) % 3], *H2 = buf[(G.rot + 2) % 3];
-      const int hist = G.hist;
-      if (hist == 2 && p->surrogate)
+    auto bufs = [&](size_t gi, char*& D, char*& H1, char*& H2) {
+      const Group& G = p->groups[gi];
+      char* buf[3] = {qs[gi].Acc, qs[gi].H[0], qs[gi].H[1]};
+      D = buf[G.rot];
+      H1 = buf[(G.rot + 1) % 3];
+      H2 = buf[(G.rot + 2) % 3];
+    };
+    for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {
+      const Group& G = p->groups[gi];
+      const GroupPtrs& q = qs[gi];
+      r.s = stream_of(gi);
+      char *D, *H1, *H2;
+      bufs(gi, D, H1, H2);
+      const long isU = 3 * G.C;
+      const int nb = G.B();
+      if (G.hist == 2 && p->surrogate)
         r.pass(PASS_IMP_PREDICT, [&] {
           return p->dtype == HOT_F64
-                     ? mlp_predict<double>(r.s, p->surrogate, q.U0, H1, H2, D, q.U1, q.act, G.C, isU, nb, g, p->nu,
+                     ? mlp_predict<double>(r.s, p->surrogate, q.U0, H1, H2, D, q.U1, q.act, G.C, isU, nb, G.g, p->nu,
                                            p->dt)
-                     : mlp_predict<float>(r.s, p->surrogate, q.U0, H1, H2, D, q.U1, q.act, G.C, isU, nb, g, p->nu,
+                     : mlp_predict<float>(r.s, p->surrogate, q.U0, H1, H2, D, q.U1, q.act, G.C, isU, nb, G.g, p->nu,
                                           p->dt);
         });
       else
         r.pass(PASS_IMP_PREDICT,
-               [&] { return o.imp_predict(r.s, q.U0, D, q.U1, H1, H2, G.C, isU, nb, g, hist, q.act); });
-      for (int sw = 0; sw < p->max_iter && r.rc == HOT_OK; ++sw) {
-        rhs_passes(r, G, q, q.U1, q.act);
-        r.pass(PASS_IMP_UPDATE, [&] {
-          return o.imp_update(r.s, q.Nh, q.U0, D, q.U1, q.part, G.C, isU, nb, g, p->nu, p->dt, q.act);
-        });
-        r.pass(PASS_IMP_DECIDE, [&] {
-          hipLaunchKernelGGL(k_imp_decide<>, dim3(nb), dim3(64), 0, r.s, (const double*)q.part, G.nparts, q.act,
-                             p->tol * p->tol, q.cnt);
-          return hipGetLastError();
-        });
+               [&] { return G.ops.imp_predict(r.s, q.U0, D, q.U1, H1, H2, G.C, isU, nb, G.g, G.hist, q.act); });
+      live[gi] = 1;
+    }
+    for (int done = 0; done < p->max_iter && r.rc == HOT_OK;) {
+      const int k = every > 0 && every < p->max_iter - done ? every : p->max_iter - done;
+      for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {
+        if (!live[gi]) continue;
+        const Group& G = p->groups[gi];
+        const GroupPtrs& q = qs[gi];
+        r.s = stream_of(gi);
+        char *D, *H1, *H2;
+        bufs(gi, D, H1, H2);
+        for (int sw = 0; sw < k && r.rc == HOT_OK; ++sw) {
+          rhs_passes(r, G, q, q.U1, q.act);
+          r.pass(PASS_IMP_UPDATE, [&] {
+            return G.ops.imp_update(r.s, q.Nh, q.U0, D, q.U1, q.part, G.C, 3 * G.C, G.B(), G.g, p->nu, p->dt,
+                                    q.act);
+          });
+          r.pass(PASS_IMP_DECIDE, [&] {
+            hipLaunchKernelGGL(k_imp_decide<>, dim3(G.B()), dim3(64), 0, r.s, (const double*)q.part, G.nparts, q.act,
+                               p->tol * p->tol, q.cnt);
+            return hipGetLastError();
+          });
+        }
       }
+      done += k;
+      if (every <= 0 || done >= p->max_iter || r.rc != HOT_OK) break;
+      // which groups still iterate: their flags, after their streams finish
+      hipError_t e = hipSuccess;
+      size_t off = 0;
+      for (size_t gi = 0; gi < ng && e == hipSuccess; ++gi) {
+        if (live[gi])
+          e = hipMemcpyAsync(p->act_host.data() + off, qs[gi].act, p->groups[gi].B() * sizeof(int),
+                             hipMemcpyDeviceToHost, stream_of(gi));
+        off += p->groups[gi].B();
+      }
+      for (size_t gi = 0; gi < ng && e == hipSuccess; ++gi)
+        if (live[gi]) e = hipStreamSynchronize(stream_of(gi));
+      if (e != hipSuccess) {
+        p->last_hip = (int)e;
+        r.rc = HOT_E_HIP;
+        break;
+      }
+      bool any = false;
+      off = 0;
+      for (size_t gi = 0; gi < ng; ++gi) {
+        const int nb = p->groups[gi].B();
+        if (live[gi]) {
+          bool a = false;
+          for (int m = 0; m < nb; ++m) a = a || p->act_host[off + m] != 0;
+          live[gi] = a;
+          any = any || a;
+        }
+        off += nb;
+      }
+      if (!any) break;
+    }
+    for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {
+      Group& G = p->groups[gi];
+      const GroupPtrs& q = qs[gi];
+      r.s = stream_of(gi);
+      char *D, *H1, *H2;
+      bufs(gi, D, H1, H2);
       r.pass(PASS_IMP_DECIDE, [&] {  // instances still active stopped at max_iter
-        hipLaunchKernelGGL(k_imp_close<>, dim3(grid_1d(nb, 256)), dim3(256), 0, r.s, (const int*)q.act, q.cnt + nb,
-                           nb);
+        hipLaunchKernelGGL(k_imp_close<>, dim3(grid_1d(G.B(), 256)), dim3(256), 0, r.s, (const int*)q.act,
+                           q.cnt + G.B(), G.B());
         return hipGetLastError();
       });
-      r.pass(PASS_IMP_ADVANCE, [&] { return o.imp_advance(r.s, q.U0, D, G.C, isU, nb, g); });
+      r.pass(PASS_IMP_ADVANCE, [&] { return G.ops.imp_advance(r.s, q.U0, D, G.C, 3 * G.C, G.B(), G.g); });
       G.rot = (G.rot + 2) % 3;  // d becomes H1, H1 becomes H2, H2's buffer the next d
       if (G.hist < 2) ++G.hist;
     }
-    r.pass(PASS_SCATTER, [&] { return o.scatter(r.s, q.U0, out0, q.out_tab, G.C, isU, nb, g); });
+  }
+  for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {
+    const Group& G = p->groups[gi];
+    const GroupPtrs& q = qs[gi];
+    r.s = stream_of(gi);
+    r.pass(PASS_SCATTER, [&] {
+      return G.ops.scatter(r.s, q.U0, out[G.members[0]], q.out_tab, G.C, 3 * G.C, G.B(), G.g);
+    });
     if (stats) state_stats(r, p, G, q, q.U0, stats, true);
   }
   if (br) {
@@ -1295,6 +1376,11 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
     for (auto& G : p->groups) G.fused = variant;
     return HOT_OK;
   }
+  if (pass == PASS_IMP_DECIDE) {  // implicit step: sweeps between looks at the flags, 0: never look
+    if (p->op != HOT_OP_IMPLICIT || variant < 0) return HOT_E_INVALID;
+    p->imp_check = variant;
+    return HOT_OK;
+  }
   if (pass == PASS_GRAPH) {  // 1: one branch per size (default), 0: the sizes one after another
     if (variant < 0 || variant > 1) return HOT_E_INVALID;
     p->graph_branches = variant == 1;
@@ -1327,6 +1413,7 @@ extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
       if (pass == PASS_YZ_FUSED) return G.yz < 0 ? 0 : 1;
       if (pass == PASS_Z_CROSS) return G.zpack;
       if (pass == PASS_GRAPH) return p->graph_branches ? 1 : 0;
+      if (pass == PASS_IMP_DECIDE) return p->op == HOT_OP_IMPLICIT ? p->imp_check : HOT_E_INVALID;
       return G.ops.strided_width[G.variant[pass] % 3];
     }
   return HOT_E_INVALID;

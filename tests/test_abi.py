@@ -299,6 +299,26 @@ def test_set_variant_rules_without_the_gpu():
         binding.hot_destroy(h)
 
 
+def test_implicit_flag_check_rules_without_the_gpu():
+    lib = binding.library()
+    names = binding.pass_names()
+    h, _ = binding.hot_plan(16, "implicit", "f32", nu=0.01, dt=1e-3)
+    try:
+        assert binding.hot_tuned_width(h, 0, "imp_decide") == 3  # default: look every 3 sweeps
+        for k in (0, 1, 7):
+            binding.hot_set_variant(h, "imp_decide", k)
+            assert binding.hot_tuned_width(h, 0, "imp_decide") == k
+        assert lib.hot_set_variant(h, names.index("imp_decide"), -1) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    h, _ = binding.hot_plan(16, "rk4", "f32", nu=0.01, dt=1e-3)
+    try:
+        assert lib.hot_set_variant(h, names.index("imp_decide"), 2) == binding.HOT_E_INVALID
+        assert lib.hot_tuned_width(h, 0, names.index("imp_decide")) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+
+
 def test_fused_yz_variant_rules_without_the_gpu():
     lib = binding.library()
     names = binding.pass_names()

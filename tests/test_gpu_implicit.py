@@ -97,6 +97,25 @@ def test_uneven_batch_matches_single_instances():
     assert len(set(sw)) > 1
 
 
+@pytest.mark.parametrize("check", [0, 1, 2, 5])
+def test_flag_checks_change_nothing_but_the_launches(check):
+    # sweeps go out in rounds of `check` between the host's looks at the
+    # stopping flags (0: never look): results and sweep counts are the same
+    # bit for bit, with uneven sizes on their own graph branches or streams,
+    # and with a cap (max_iter 4) that some steps reach
+    dt = 0.02
+    fields = [inputs.rough_random(16, 11) * 4, inputs.smooth_random(24, 12) * 4, inputs.rough_random(32, 13),
+              inputs.smooth_random(16, 14) * 0.5, inputs.rough_random(24, 15) * 8]
+    for tol, max_iter in ((1e-10, 50), (1e-13, 4)):
+        ref, sw_ref, nc_ref, rc_ref = run_implicit(fields, "f64", NU, dt, 3, tol, max_iter,
+                                                   variants={"imp_decide": 3})
+        got, sw, nc, rc = run_implicit(fields, "f64", NU, dt, 3, tol, max_iter, variants={"imp_decide": check})
+        assert (sw, nc, rc) == (sw_ref, nc_ref, rc_ref)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    assert any(nc_ref)  # the capped run did stop some steps at max_iter
+
+
 def test_max_iter_stop_reports_and_keeps_the_last_iterate():
     N, dt = 16, 0.05
     u0 = inputs.rough_random(N, 6) * 4.0

@@ -1,0 +1,56 @@
+"""How fast the Picard sweeps of the implicit-midpoint oracle converge, and
+what a warm start must achieve to save one sweep (CPU, oracle only).
+
+Setting of the implicit batch: R1 fields, Re = 1600 (nu = 1/1600, Sec. 4),
+dt = 1e-2, two steps of history, then the step under study.  The reference
+increment comes from the oracle's step converged to 1e-14; e_k is the error
+of the k-th iterate relative to the increment (e_0: the extrapolation
+2 D1 - D2), in the norm of the stopping test.  The sweep map contracts by
+rho_k = e_{k+1} / e_k, a few hundredths here, so the stopping test
+||d_k - d_{k-1}|| <= tau ||d_k|| passes at the first sweep k with
+e_{k-1} <~ tau: with e_0 ~ 1e-3 and tau = 1e-5 that is the third sweep.
+Stopping at the second sweep instead needs e_1 = rho_0 e_0 <= tau, i.e. a
+predictor whose error is at most tau / (rho_0 e_0) of the extrapolation's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.implicit_midpoint import extrapolation_predictor, half_norm, midpoint_sweep
+from paper_1607_00850_amd import inputs
+
+NU, DT, TAU = 1.0 / 1600.0, 1e-2, 1e-5
+
+
+def _errors(N, seed, sweeps=5):
+    u0 = inputs.smooth_random(N, seed)
+    u, _, incs, _ = oracle.implicit_midpoint(u0, NU, DT, 2, 1e-13)
+    pred = extrapolation_predictor(u, incs)
+    ref, _, ok, _ = oracle.implicit_midpoint_step(u, NU, DT, 1e-14, 80, pred)
+    assert ok
+    inc = half_norm(ref - u)
+    w = pred * oracle.retained_mask(N)
+    errs = [half_norm(w - ref) / inc]
+    for _ in range(sweeps):
+        w, _ = midpoint_sweep(u, w, NU, DT)
+        errs.append(half_norm(w - ref) / inc)
+    return np.array(errs)
+
+
+@pytest.mark.parametrize("N,seed", [(32, 20002), (64, 20000)])
+def test_sweeps_contract_and_the_gain_one_sweep_needs(N, seed):
+    e = _errors(N, seed)
+    rho = e[1:] / e[:-1]
+    # the extrapolation is good to about 1e-3 of the increment
+    assert 3e-4 < e[0] < 3e-3
+    # the sweeps contract by a few hundredths each (well below 1: the
+    # nonlinear term over dt is small against the increment)
+    assert np.all(rho < 0.1)
+    # three sweeps at tau = 1e-5: the change of sweep k is about e_{k-1}
+    stop = 1 + int(np.argmax(e <= TAU))
+    assert stop == 3
+    # what a warm start must reach to stop after two sweeps
+    need = TAU / (rho[0] * e[0])
+    print(f"N={N}: e_0 = {e[0]:.2e}, rho = {np.round(rho, 3)}, "
+          f"a warm start saves a sweep only with error <= {need:.2f} of the extrapolation's", flush=True)
+    assert 0.2 < need < 0.6
