@@ -68,6 +68,7 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, command):
     from collections import defaultdict
 
     def per_kernel(path, counter):
+        # (dispatch id, KiB) per kernel, in dispatch order
         vals = defaultdict(list)
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
@@ -78,14 +79,14 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, command):
                 m2 = re.search(r"LinePlan<[^>]*>, (-?1), \d+, (true|false), (true|false)", r["Kernel_Name"])
                 name = {("1", "true", "false"): "y_inv", ("-1", "false", "true"): "y_or_x_fwd"}.get(
                     m2.groups() if m2 else None, "k_strided")
-            vals[name].append(float(r["Counter_Value"]))
+            vals[name].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
         return vals
 
     fetch = per_kernel(fetch_csv, "FETCH_SIZE")
     write = per_kernel(write_csv, "WRITE_SIZE")
     true_bytes = float(calib_mib) * 2**20
-    fs = true_bytes / (fetch[COPY_KERNEL][0] * 1024.0)
-    ws = true_bytes / (write[COPY_KERNEL][0] * 1024.0)
+    fs = true_bytes / (fetch[COPY_KERNEL][0][1] * 1024.0)
+    ws = true_bytes / (write[COPY_KERNEL][0][1] * 1024.0)
     # kernel -> pass; several kernels can serve one pass (the row forms, the
     # x inverse variants); k_strided forward with compact output rows is the
     # y forward pass when the x forward pass is fused with the stage update
@@ -94,9 +95,15 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, command):
              "k_scatter": "scatter", "y_inv": "y_inv", "k_y_inv_pack": "y_inv", "k_x_fwd_rk": "x_fwd_rk",
              "y_or_x_fwd": "y_fwd", "k_y_fwd_unpack": "y_fwd"}
     out = {"fetch_scale": fs, "write_scale": ws, "command": command}
+    # only the dispatches of the timed call (its last launches of each pass:
+    # one gather and scatter, four of every other pass for the one RK4 step
+    # of `--steps 1 --warmup 0`), not the autotuner's timing launches of other
+    # variants before it
+    last = {"gather": 1, "scatter": 1}
     for pname in sorted(set(names.values())):
-        fv = [v for k, n in names.items() if n == pname and k in fetch and k in write for v in fetch[k]]
-        wv = [v for k, n in names.items() if n == pname and k in fetch and k in write for v in write[k]]
+        n = last.get(pname, 4)
+        fv = [v for _, v in sorted(d for k, nm in names.items() if nm == pname and k in fetch for d in fetch[k])][-n:]
+        wv = [v for _, v in sorted(d for k, nm in names.items() if nm == pname and k in write for d in write[k])][-n:]
         if fv and wv:
             f = sum(fv) / len(fv) * 1024.0 * fs
             w = sum(wv) / len(wv) * 1024.0 * ws
