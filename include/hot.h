@@ -225,14 +225,20 @@ int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t reps);
 int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
 
 /* Set what hot_tune would choose, for every size of the plan: for a
- * column-tiled pass the width variant 0 (narrow), 1 (default) or 2 (wide);
+ * column-tiled pass the width variant 0 (narrow), 1 (default) or 2 (wide),
+ * and 3..5 the same widths with one output per block for the y forward pass
+ * on packed rows (c0, c1, c2 separated by three blocks) and for the x inverse
+ * with the curl at N > 64 (six blocks per tile instead of three);
  * for x_fwd_rk -1 (separate x_fwd and rk_stage passes), 0, 1 or 2 (fused,
  * at half, the default or a quarter of the default width); for z_cross 1
  * (the default: the y and z passes carry u and w as packed pairs of complex
  * lines), 2 (packed pairs into the z pass, which stores c0, c1, c2 as three
- * component rows for the y forward pass; hot_tune chooses between 1 and 2) or
- * 0 (six separate component rows, the z pass completing the Hermitian halves
- * itself); for "graph" (no kernel of its own) the layout of
+ * component rows for the y forward pass), 3 (six component rows through the
+ * y passes; the z pass packs them into complex lines on load and stores
+ * c0, c1, c2 as component rows) or 0 (six component rows, the z pass
+ * completing the Hermitian halves in LDS), hot_tune timing the four over
+ * the y inverse, z and y forward passes; for "graph" (no kernel of its own)
+ * the layout of
  * graphs hot_graph_create captures from then on: 1 (the default) one branch
  * per distinct N, forked from and joined back into the capturing stream, so
  * the passes of small sizes run beside those of large ones; 0 the sizes one

@@ -130,7 +130,12 @@ struct Group {
   int rot = 0, hist = 0;                      // implicit step: buffer rotation, history depth
   int fused = -1;  // RK4/RHS: x_fwd_rk variant fusing the x pass with the stage update, -1 = separate passes
   int yz = -1;     // 0: the y and z passes fused (k_yz_fused), -1: y_inv, z_cross, y_fwd
-  int zpack = 0;  // z pass rows: 0 six component rows; 1 packed pairs in and out (default); 2 packed in, c0 c1 c2 out
+  // row form of the y and z passes: 0 six component rows (the z pass completes
+  // the Hermitian halves in LDS); 1 packed pairs in and out (default); 2 packed
+  // pairs in, c0 c1 c2 component rows out; 3 component rows in and out, the z
+  // pass packing its lines on load
+  int zpack = 0;
+  bool packed_y_inv() const { return zpack == 1 || zpack == 2; }
   size_t bytes = 0;
   int variant[NUM_PASSES];  // strided column-width variant per pass (autotuned)
   int B() const { return (int)members.size(); }
@@ -506,7 +511,7 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
 void y_inv_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
   const long N = G.N, M = G.g.M, P = G.g.Mzp;
   r.pass(PASS_Y_INV, [&] {
-    if (G.zpack > 0)
+    if (G.packed_y_inv())
       return G.ops.y_inv_pack(r.s, G.variant[PASS_Y_INV], q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2,
                               6 * G.D1, 6 * G.D2, G.B(), G.g, act);
     return G.ops.strided(r.s, G.variant[PASS_Y_INV], +1, true, false, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1,
@@ -517,7 +522,7 @@ void y_inv_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
 void z_pass(Runner& r, const Group& G, const GroupPtrs& q, const int* act) {
   r.pass(PASS_Z_CROSS, [&] {
     return G.zpack > 0
-               ? G.ops.z_cross_packed(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act, G.zpack == 2)
+               ? G.ops.z_cross_packed(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act, G.zpack - 1)
                : G.ops.z_cross(r.s, q.A2, G.D2, 6 * G.D2, G.N * (long)G.N, G.B(), G.g, act);
   });
 }
@@ -1198,8 +1203,10 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
     for (int pid : pass_ids) {
       float best = 1e30f;
       int best_v = 1;
-      // the packed y forward pass also comes with one output per block (variants 3..5)
-      const int nv = (pid == PASS_Y_FWD && G.zpack == 1) ? 2 * G.ops.strided_variants : G.ops.strided_variants;
+      // the packed y forward pass and the x inverse of the long lines also come
+      // with one output per block (variants 3..5)
+      const bool single = (pid == PASS_Y_FWD && G.zpack == 1) || (pid == PASS_X_INV_CURL && G.N > 64);
+      const int nv = single ? 2 * G.ops.strided_variants : G.ops.strided_variants;
       for (int v = 0; v < nv && rc == HOT_OK; ++v) {
         const int w = v % G.ops.strided_variants;
         if (w != 1 && G.ops.strided_width[w] == G.ops.strided_width[1]) continue;  // same kernel
@@ -1215,7 +1222,7 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
           r.pass(pid, [&] {
             if (pid == PASS_X_INV_CURL)
               return G.ops.x_inv_curl(s, v, q.U0, G.C, isU, q.A1, G.D1, isA1, G.B(), g, nullptr);
-            if (pid == PASS_Y_INV && G.zpack > 0)
+            if (pid == PASS_Y_INV && G.packed_y_inv())
               return G.ops.y_inv_pack(s, v, q.A1, q.A2, N * P, P, P, P, M * P, N * P, G.D1, G.D2, isA1, isA2,
                                       G.B(), g, nullptr);
             if (pid == PASS_Y_INV)
@@ -1283,19 +1290,30 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
       }
       G.yz = best_y;
     }
-    // the z pass storing packed halves (y forward separating c0 and c1) or
-    // separating them itself (component-row y forward); groups whose y and z
-    // passes are not fused
+    // the row form of the y and z passes (groups whose y and z passes are not
+    // fused): six component rows, packed pairs in and out, or packed pairs
+    // into the z pass and component rows out of it, each timed over the y
+    // inverse, z and y forward passes
     if (rc == HOT_OK && G.yz < 0 && G.zpack > 0) {
       float best = 1e30f;
       int best_z = 1;
-      for (int zv = 1; zv <= 2 && rc == HOT_OK; ++zv) {
+      for (int zv = 0; zv <= 3 && rc == HOT_OK; ++zv) {
         G.zpack = zv;
         float t = 0.f;
         for (int rep = 0; rep <= reps && rc == HOT_OK; ++rep) {
           Runner r{p, s, false};
           if (rep == 1) (void)hipEventRecord(a, s);
-          z_pass(r, G, q, nullptr);
+          y_inv_pass(r, G, q, nullptr);
+          if (p->nranks > 1) {  // a z-slab share: its z pass over every retained kz, from the receive buffer
+            const long lines = (long)p->nx * G.N, blk = lines * G.g.Mzp;
+            r.pass(PASS_Z_CROSS, [&] {
+              return G.zpack > 0 ? G.ops.z_cross_packed_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk,
+                                                                G.zpack - 1)
+                                 : G.ops.z_cross_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk);
+            });
+          } else {
+            z_pass(r, G, q, nullptr);
+          }
           y_fwd_pass(r, G, q, nullptr);
           rc = r.rc;
         }
@@ -1386,9 +1404,9 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
     p->graph_branches = variant == 1;
     return HOT_OK;
   }
-  if (pass == PASS_Z_CROSS) {  // 1: packed pair rows (default), 0: six component rows, 2: packed in, split out
+  if (pass == PASS_Z_CROSS) {  // the row form (Group::zpack), 0..3
     const bool plain = p->op == HOT_OP_R2C || p->op == HOT_OP_C2R;
-    if (variant < 0 || variant > 2 || plain) return HOT_E_INVALID;
+    if (variant < 0 || variant > 3 || plain) return HOT_E_INVALID;
     for (auto& G : p->groups) G.zpack = variant;
     return HOT_OK;
   }
@@ -1399,7 +1417,8 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
     return HOT_OK;
   }
   // the y forward pass takes 3..5 too: the same widths, one output per block
-  if (!tiled || variant < 0 || variant > (pass == PASS_Y_FWD ? 5 : 2)) return HOT_E_INVALID;
+  if (!tiled || variant < 0 || variant > ((pass == PASS_Y_FWD || pass == PASS_X_INV_CURL) ? 5 : 2))
+    return HOT_E_INVALID;
   for (auto& G : p->groups) G.variant[pass] = variant;
   return HOT_OK;
 }
@@ -1509,7 +1528,7 @@ extern "C" int hot_slab_run(hot_plan_t p, int32_t phase, int32_t stage, const vo
     case HOT_SLAB_CROSS: {
       const long lines = (long)p->nx * G.N, blk = lines * G.g.Mzp;
       r.pass(PASS_Z_CROSS, [&] {
-        return G.zpack > 0 ? o.z_cross_packed_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk, G.zpack == 2)
+        return G.zpack > 0 ? o.z_cross_packed_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk, G.zpack - 1)
                            : o.z_cross_blocked(r.s, q.Z, G.D2, lines, p->gz, p->chunk, blk);
       });
       break;

@@ -100,8 +100,10 @@ struct Ops {
   hipError_t (*y_inv_pack)(hipStream_t, int variant, const void* in, void* out, long ncols, long Qp, long ld_in,
                            long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, long is_in, long is_out,
                            int nb, const Geo&, const int* act);
+  // form: 0 packed rows in and out, 1 packed in and component rows out, 2
+  // component rows in (packed on load) and out
   hipError_t (*z_cross_packed)(hipStream_t, void* A, long csA, long isA, long nlines, int nb, const Geo&,
-                               const int* act, bool split);
+                               const int* act, int form);
   hipError_t (*y_fwd_unpack)(hipStream_t, int variant, const void* in, void* out, long ncols, long Qp, long ld_in,
                              long ld_out, long bs_in, long bs_out, long cs_in, long cs_out, long is_in, long is_out,
                              int nb, const Geo&, const int* act);
@@ -109,7 +111,7 @@ struct Ops {
   // elements apart (the receive buffer of a z-slab all-to-all)
   hipError_t (*z_cross_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk);
   hipError_t (*z_cross_packed_blocked)(hipStream_t, void* A, long csA, long nlines, const Geo&, int chunk, long blk,
-                                       bool split);
+                                       int form);
   // y inverse, z pass and y forward in one kernel, in place on A1 (NULL where
   // the six planes of an x-plane do not fit in LDS)
   hipError_t (*yz_fused)(hipStream_t, void* A, long csA, long isA, int nb, const Geo&, const int* act);
@@ -204,7 +206,9 @@ struct Impl {
   static constexpr bool kCurl6 = std::is_same_v<T, float> && N <= 64;
   // 1/N^3 of the inverse transform (Eq. ffteq), applied to u and w by the x pass
   static constexpr double kUsc = 1.0 / (double(N) * N * N);
-  template <int WW>
+  // SIX (large N): one output per block (k_x_inv_curl, six blocks per tile)
+  // instead of two (k_x_inv_curl3)
+  template <int WW, bool SIX = false>
   static hipError_t x_inv_curl_w(hipStream_t s, const void* U, long csU, long isU, void* A, long csA, long isA,
                                  int nb, const Geo& g, const int* act) {
     const T usc = T(kUsc);
@@ -214,6 +218,9 @@ struct Impl {
     const unsigned ngrp = (unsigned)((ntiles + 8 * pair - 1) / (8 * pair) * pair);
     if constexpr (kCurl6) {
       hipLaunchKernelGGL((k_x_inv_curl6<T, P, WW>), dim3(8u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
+                         (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
+    } else if constexpr (SIX) {
+      hipLaunchKernelGGL((k_x_inv_curl<T, P, WW>), dim3(8u * 6u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
                          (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
     } else {
       // registers that can hold a retained row: the 2/3-rule count, or all
@@ -229,9 +236,13 @@ struct Impl {
   }
   static hipError_t x_inv_curl(hipStream_t s, int variant, const void* U, long csU, long isU, void* A, long csA,
                                long isA, int nb, const Geo& g, const int* act) {
+    // variants 0..2: widths W/2, W, 2W; 3..5: the same with one output per block
     switch (variant) {
       case 0: return x_inv_curl_w<WV0>(s, U, csU, isU, A, csA, isA, nb, g, act);
       case 2: return x_inv_curl_w<WV2>(s, U, csU, isU, A, csA, isA, nb, g, act);
+      case 3: return x_inv_curl_w<WV0, true>(s, U, csU, isU, A, csA, isA, nb, g, act);
+      case 4: return x_inv_curl_w<W, true>(s, U, csU, isU, A, csA, isA, nb, g, act);
+      case 5: return x_inv_curl_w<WV2, true>(s, U, csU, isU, A, csA, isA, nb, g, act);
       default: return x_inv_curl_w<W>(s, U, csU, isU, A, csA, isA, nb, g, act);
     }
   }
@@ -258,27 +269,30 @@ struct Impl {
                             const int* act) {
     return z_cross_za(s, A, csA, isA, nlines, nb, g, act, ZContig{});
   }
-  template <class ZA, bool SPLIT>
+  template <class ZA, int FORM>
   static hipError_t z_cross_packed_za(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
                                       const int* act, ZA za) {
     const unsigned nblk = (unsigned)((nlines + lines_per_block() - 1) / lines_per_block());
     const dim3 grid(nblk, (unsigned)nb);
     constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
     if (g.Mz <= KL23 * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KL23, ZA, SPLIT>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA,
+      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KL23, ZA, FORM>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA,
                          nlines, g, act, za);
     else if (g.Mz <= KLall * PZ::Tl)
-      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KLall, ZA, SPLIT>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA,
+      hipLaunchKernelGGL((k_z_cross_packed<T, PZ, KLall, ZA, FORM>), grid, dim3(256), 0, s, (cx<T>*)A, csA, isA,
                          nlines, g, act, za);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
-  // split: c0, c1, c2 stored as half-spectrum rows (for the component-row y forward pass)
+  // form 0: packed rows in and out; 1: c0, c1, c2 stored as half-spectrum rows
+  // (for the component-row y forward pass); 2: component rows in as well
+  // (from the component-row y inverse pass), packed on load
   static hipError_t z_cross_packed(hipStream_t s, void* A, long csA, long isA, long nlines, int nb, const Geo& g,
-                                   const int* act, bool split) {
-    return split ? z_cross_packed_za<ZContig, true>(s, A, csA, isA, nlines, nb, g, act, ZContig{})
-                 : z_cross_packed_za<ZContig, false>(s, A, csA, isA, nlines, nb, g, act, ZContig{});
+                                   const int* act, int form) {
+    if (form == 2) return z_cross_packed_za<ZContig, 2>(s, A, csA, isA, nlines, nb, g, act, ZContig{});
+    return form == 1 ? z_cross_packed_za<ZContig, 1>(s, A, csA, isA, nlines, nb, g, act, ZContig{})
+                     : z_cross_packed_za<ZContig, 0>(s, A, csA, isA, nlines, nb, g, act, ZContig{});
   }
   // the y passes on packed rows: a grid like k_strided's, with blockIdx.y
   // the component pair (3 for the inverse, 2 for the forward)
@@ -332,11 +346,12 @@ struct Impl {
     return z_cross_za(s, A, csA, 0, nlines, 1, g, nullptr, ZBlocked{chunk, 1.0f / (float)chunk, blk});
   }
   static hipError_t z_cross_packed_blocked(hipStream_t s, void* A, long csA, long nlines, const Geo& g, int chunk,
-                                           long blk, bool split) {
+                                           long blk, int form) {
     if (chunk < 1) return hipErrorInvalidValue;
     const ZBlocked za{chunk, 1.0f / (float)chunk, blk};
-    return split ? z_cross_packed_za<ZBlocked, true>(s, A, csA, 0, nlines, 1, g, nullptr, za)
-                 : z_cross_packed_za<ZBlocked, false>(s, A, csA, 0, nlines, 1, g, nullptr, za);
+    if (form == 2) return z_cross_packed_za<ZBlocked, 2>(s, A, csA, 0, nlines, 1, g, nullptr, za);
+    return form == 1 ? z_cross_packed_za<ZBlocked, 1>(s, A, csA, 0, nlines, 1, g, nullptr, za)
+                     : z_cross_packed_za<ZBlocked, 0>(s, A, csA, 0, nlines, 1, g, nullptr, za);
   }
   static constexpr bool kYz = N <= 64 && YzShape<T, PZ>::kFits;
   static hipError_t yz_fused(hipStream_t s, void* A, long csA, long isA, int nb, const Geo& g, const int* act) {

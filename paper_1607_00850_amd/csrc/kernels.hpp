@@ -885,12 +885,19 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_y_fwd_unpack3(const cx<T>* __re
 // 0, 1) and of c2 (component 2).  In place.  KL: coefficients per lane; ZA
 // places coefficient k of a row (ZContig, or ZBlocked for the receive buffer
 // of a z-slab all-to-all).  Three waves per SIMD: at 168 VGPRs nothing spills
-// for the 2/3 rule.  SPLIT: store c0, c1 and c2 as three half-spectrum rows
-// instead (the two real transforms packed in c0 + i c1 separated here, through
-// the line's LDS region), for the component-row y forward pass.
-template <typename T, class Plan, int KL, class ZA, bool SPLIT>
+// for the 2/3 rule.  FORM 0: packed rows in and out.  FORM 1 (SPLIT): store
+// c0, c1 and c2 as three half-spectrum rows instead (the two real transforms
+// packed in c0 + i c1 separated here, through the line's LDS region), for the
+// component-row y forward pass.  FORM 2: also read component rows a, b (the
+// six half spectra u_x .. w_z, from the component-row y inverse pass) and pack
+// them on load: Z_p = a_p + i b_p for p < Mz, Z_p = conj a_{N-p} + i conj
+// b_{N-p} for N - p < Mz, and Z_0 = Re a_0 + i Re b_0 (a real inverse
+// transform drops the imaginary part at k = 0); two loads per position, the
+// same bytes as the packed rows.
+template <typename T, class Plan, int KL, class ZA, int FORM>
 __global__ __launch_bounds__(256, 3) void k_z_cross_packed(cx<T>* __restrict__ A, long csA, long isA, long nlines, Geo g,
                                                         const int* __restrict__ act, ZA za) {
+  constexpr bool SPLIT = FORM >= 1, CIN = FORM == 2;
   if (act && !act[blockIdx.y]) return;  // instance no longer iterating
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int LPB = ZShape<Plan>::LPB;
@@ -919,8 +926,16 @@ __global__ __launch_bounds__(256, 3) void k_z_cross_packed(cx<T>* __restrict__ A
         const int p = j + s * Tl;
         const bool ina = lo && valid && p < Mz;
         const bool inb = hi && !ina && valid && p > 0 && N - p < Mz;
-        const cx<T> x = ina ? ra[za(p)] : rb[za(inb ? N - p : 0)];
-        ph[pr][s] = (ina || inb) ? x : cx<T>{T(0), T(0)};
+        if constexpr (CIN) {
+          const long o = za(ina ? p : (inb ? N - p : 0));
+          const cx<T> a = ra[o], b = rb[o];
+          const cx<T> zl = p == 0 ? cx<T>{a.x, b.x} : cx<T>{a.x - b.y, a.y + b.x};  // a + i b
+          const cx<T> zh = {a.x + b.y, b.x - a.y};                                  // conj a + i conj b
+          ph[pr][s] = ina ? zl : (inb ? zh : cx<T>{T(0), T(0)});
+        } else {
+          const cx<T> x = ina ? ra[za(p)] : rb[za(inb ? N - p : 0)];
+          ph[pr][s] = (ina || inb) ? x : cx<T>{T(0), T(0)};
+        }
       } else {
         ph[pr][s] = cx<T>{T(0), T(0)};
       }

@@ -280,7 +280,7 @@ def test_set_variant_rules_without_the_gpu():
             assert (binding.hot_tuned_width(h, 0, "x_fwd_rk") == 0) == (v < 0)
         assert lib.hot_set_variant(h, names.index("x_fwd_rk"), 3) == binding.HOT_E_INVALID
         assert lib.hot_set_variant(h, names.index("y_inv"), 3) == binding.HOT_E_INVALID
-        assert lib.hot_set_variant(h, names.index("z_cross"), 3) == binding.HOT_E_INVALID
+        assert lib.hot_set_variant(h, names.index("z_cross"), 4) == binding.HOT_E_INVALID
         assert binding.hot_tuned_width(h, 0, "z_cross") == 1  # packed pair rows by default
         binding.hot_set_variant(h, "z_cross", 0)
         assert binding.hot_tuned_width(h, 0, "z_cross") == 0

@@ -236,9 +236,24 @@ def test_row_forms_drop_the_imaginary_part_at_kz0(N, dtype):
     pert = (rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))) * np.abs(uh).max()
     uh[:, :, :, 0] += np.where(M[:, :, 0], pert, 0)
     ref = oracle.rhs(ref_input(uh, dtype), NU)
-    for v in ({"z_cross": 1}, {"z_cross": 2}, {"z_cross": 0}, {"z_cross": 1, "y_fwd": 4}, {"yz_fused": 0}):
+    for v in ({"z_cross": 1}, {"z_cross": 2}, {"z_cross": 0}, {"z_cross": 3}, {"z_cross": 1, "y_fwd": 4},
+              {"yz_fused": 0}):
         (got,) = run("rhs", [uh], dtype, nu=NU, variants=v)
         assert rel_l2(got, ref) < tol(dtype, N), v
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_x_inverse_with_six_blocks_per_tile(dtype):
+    # x_inv_curl variants 3..5 (N > 64): one output per block instead of two
+    N = 128
+    print(f"x_inv_curl six blocks {dtype}", flush=True)
+    uh = inputs.rough_random(N, 600)
+    ref = oracle.rhs(ref_input(uh, dtype), NU)
+    (a,) = run("rhs", [uh], dtype, nu=NU, variants={"x_inv_curl": 1})
+    for v in (3, 4, 5):
+        (b,) = run("rhs", [uh], dtype, nu=NU, variants={"x_inv_curl": v})
+        assert rel_l2(b, ref) < tol(dtype, N), v
+        assert rel_l2(b, a) < (1e-14 if dtype == "f64" else 1e-6), v  # the same arithmetic up to contraction
 
 
 # -- the x pass fused with the stage update (x_fwd_rk) -----------------------------
@@ -287,10 +302,12 @@ def test_packed_and_component_rows_agree(N, dtype):
     (c,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 1, "y_fwd": 4})
     # packed rows into the z pass, c0 c1 c2 component rows out of it (variant 2)
     (d,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 2})
+    # component rows through the y passes, packed by the z pass on load (variant 3)
+    (e,) = run("rk4", [uh], dtype, nu=NU, dt=DT, nsteps=1, variants={"z_cross": 3})
     ref = oracle.rk4(ref_input(uh, dtype), NU, DT, 1)
-    for x in (a, b, c, d):
+    for x in (a, b, c, d, e):
         assert rel_l2(x, ref) < tol(dtype, N)
         assert rel_l2(a, x) < tol(dtype, N)
     M = oracle.retained_mask(N)
-    for x in (a, b, c, d):
+    for x in (a, b, c, d, e):
         assert np.all(x[:, ~M] == 0)
