@@ -202,6 +202,13 @@ struct Impl {
                                    cs_out, ncomp, is_in, is_out, otw, nb, g, act);
     }
   }
+  // g is the 2/3-rule geometry of N with no row padding (geo_two_thirds):
+  // kernels instantiated for it take the geometry at compile time
+  static bool is_g23(const Geo& g) {
+    constexpr int K = (N - 1) / 3;
+    return g.N == N && g.lo == K + 1 && g.hi == K && g.M == 2 * K + 1 && g.Mz == K + 1 && g.Mzp == K + 1 &&
+           g.kz0 == 0 && g.tw == g.M * g.Mzp;
+  }
   // short FP32 lines: all six outputs of a tile in one block (k_x_inv_curl6)
   static constexpr bool kCurl6 = std::is_same_v<T, float> && N <= 64;
   // 1/N^3 of the inverse transform (Eq. ffteq), applied to u and w by the x pass
@@ -217,8 +224,12 @@ struct Impl {
     constexpr int pair = (WW * (int)sizeof(cx<T>) < 128) ? 128 / (WW * (int)sizeof(cx<T>)) : 1;
     const unsigned ngrp = (unsigned)((ntiles + 8 * pair - 1) / (8 * pair) * pair);
     if constexpr (kCurl6) {
-      hipLaunchKernelGGL((k_x_inv_curl6<T, P, WW>), dim3(8u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
-                         (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
+      if (is_g23(g))
+        hipLaunchKernelGGL((k_x_inv_curl6<T, P, WW, true>), dim3(8u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
+                           (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
+      else
+        hipLaunchKernelGGL((k_x_inv_curl6<T, P, WW>), dim3(8u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
+                           (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
     } else if constexpr (SIX) {
       hipLaunchKernelGGL((k_x_inv_curl<T, P, WW>), dim3(8u * 6u * ngrp, (unsigned)nb), dim3(WW * Tl), 0, s,
                          (const cx<T>*)U, csU, isU, (cx<T>*)A, csA, isA, ntiles, g, usc, act);
@@ -358,15 +369,23 @@ struct Impl {
     if constexpr (kYz) {
       const size_t lds = (size_t)YzShape<T, PZ>::lds_bytes(g.Mz);
       const dim3 grid((unsigned)N, (unsigned)nb);
-      constexpr int KL23 = z_loads<PZ>((N - 1) / 3 + 1), KLall = z_loads<PZ>(N / 2);
-      if (g.Mz <= KL23 * PZ::Tl) {
-        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KL23>,
+      constexpr int K = (N - 1) / 3;
+      constexpr int KL23 = z_loads<PZ>(K + 1), KLall = z_loads<PZ>(N / 2);
+      if (is_g23(g)) {  // the 2/3 rule: the geometry at compile time
+        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KL23, true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_yz_fused<T, PZ, KL23>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA, isA, g, act);
+        hipLaunchKernelGGL((k_yz_fused<T, PZ, KL23, true>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA,
+                           isA, g, act);
+      } else if (g.Mz <= KL23 * PZ::Tl) {
+        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KL23, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_yz_fused<T, PZ, KL23, false>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA,
+                           isA, g, act);
       } else if (g.Mz <= KLall * PZ::Tl) {
-        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KLall>,
+        (void)hipFuncSetAttribute((const void*)k_yz_fused<T, PZ, KLall, false>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_yz_fused<T, PZ, KLall>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA, isA, g, act);
+        hipLaunchKernelGGL((k_yz_fused<T, PZ, KLall, false>), grid, dim3(YzShape<T, PZ>::NT), lds, s, (cx<T>*)A, csA,
+                           isA, g, act);
       } else {
         return hipErrorInvalidValue;
       }
@@ -405,7 +424,10 @@ struct Impl {
     const dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)nb);
     // registers that can hold a retained row: the 2/3-rule count, or all
     constexpr int KL23 = (((N - 1) / 3 + 1) + TlF - 1) / TlF;
-    if (g.lo <= KL23 * TlF && g.hi <= KL23 * TlF)
+    if (N <= 64 && is_g23(g))  // the batch sizes: the geometry at compile time
+      hipLaunchKernelGGL((k_x_fwd_rk<T, PF, WW, KL23, true>), grid, dim3(WW * TlF), 0, s, (const cx<T>*)A, csA,
+                         isA, (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
+    else if (g.lo <= KL23 * TlF && g.hi <= KL23 * TlF)
       hipLaunchKernelGGL((k_x_fwd_rk<T, PF, WW, KL23>), grid, dim3(WW * TlF), 0, s, (const cx<T>*)A, csA, isA,
                          (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
     else

@@ -41,6 +41,24 @@ __device__ __forceinline__ int cpos(int i, const Geo& g) { return i < g.lo ? i :
 // signed wavenumber (Eq. wavemesh) of FFT position p
 __device__ __forceinline__ int kwave(int p, int N) { return 2 * p <= N ? p : p - N; }
 
+// The 2/3-rule geometry of an N-point plan (|k| <= K = (N-1)/3, no row
+// padding, row-major compact state), as compile-time values: a kernel that
+// the launcher has checked runs on it (G23) gets every index as arithmetic on
+// constants.
+template <int N>
+__device__ __forceinline__ Geo geo_two_thirds(Geo g) {
+  constexpr int K = (N - 1) / 3;
+  g.N = N;
+  g.lo = K + 1;
+  g.hi = K;
+  g.M = 2 * K + 1;
+  g.Mz = K + 1;
+  g.Mzp = K + 1;
+  g.kz0 = 0;
+  g.tw = (2 * K + 1) * (K + 1);
+  return g;
+}
+
 // Compact state arrays (per instance [3][C]: the state, the stage arrays, the
 // nonlinear term and the implicit step's buffers) hold a component as column
 // tiles: column q = (compact ky row) * Mzp + kz of compact kx row ix sits at
@@ -440,10 +458,11 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl3(const cx<T>* __rest
 // fewer blocks than k_x_inv_curl and three component loads per tile instead
 // of nine.  No barrier is needed between two transforms: every exchange ends
 // with one after its reads, and the last stage works in registers.
-template <typename T, class Plan, int W>
+template <typename T, class Plan, int W, bool G23 = false>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __restrict__ U, long csU, long isU,
                                                              cx<T>* __restrict__ A, long csA, long isA,
-                                                             int ntiles, Geo g, T usc, const int* __restrict__ act) {
+                                                             int ntiles, Geo g_in, T usc, const int* __restrict__ act) {
+  const Geo g = G23 ? geo_two_thirds<Plan::N>(g_in) : g_in;
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];
@@ -1226,11 +1245,12 @@ __device__ __forceinline__ void x_rk_tail(const cx<T> (&v)[3][Plan::R], int j, l
 // A[3][N rows (x)][Q = M*Mzp cols (ky, kz)]; the state arrays are compact
 // [3][M][Q].  blockIdx.y is the instance of a batch.
 // ---------------------------------------------------------------------------
-template <typename T, class Plan, int W, int KL>
+template <typename T, class Plan, int W, int KL, bool G23 = false>
 __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restrict__ A, long csA, long isA,
                                                           cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
-                                                          cx<T>* __restrict__ Acc, long C, long isU, Geo g, int mode,
+                                                          cx<T>* __restrict__ Acc, long C, long isU, Geo g_in, int mode,
                                                           T nu, T dt) {
+  const Geo g = G23 ? geo_two_thirds<Plan::N>(g_in) : g_in;
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
   __shared__ cx<T> sm[N * W];

@@ -53,9 +53,11 @@ struct YzShape {
   static constexpr bool kFits = Tl <= 64 && lds_bytes(MZ) <= 163840;
 };
 
-template <typename T, class Plan, int KL>
-__global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __restrict__ A, long csA, long isA, Geo g,
-                                                  const int* __restrict__ act) {
+// G23: the launcher has checked that g is the 2/3-rule geometry of N.
+template <typename T, class Plan, int KL, bool G23>
+__global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __restrict__ A, long csA, long isA,
+                                                  Geo g_in, const int* __restrict__ act) {
+  const Geo g = G23 ? geo_two_thirds<Plan::N>(g_in) : g_in;
   using S = YzShape<T, Plan>;
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, LS = Plan::line_stride;
   if (act && !act[blockIdx.y]) return;  // instance no longer iterating
