@@ -5,9 +5,10 @@
 //          (row pitch Mz | 1: an odd pitch spreads a column over the banks);
 //          the rows outside the retained set are read as zeros
 //   y      inverse transform of every (component, kz) column, in place
-//   z      per y line: the z pass of k_z_cross (inverse real transforms of
-//          u and omega, u x omega, forward real transforms; u and omega
-//          carry the 1/N^3 already), components 0..2 of the row written back
+//   z      per y line: the z pass (u and omega packed in three complex
+//          lines read straight from P, inverse transforms, u x omega, forward
+//          transforms; u and omega carry the 1/N^3 already), components 0..2
+//          of the row written back
 //   y      forward transform of every (component 0..2, kz) column, in place
 //   store  the retained rows of components 0..2 -> A[3][x][M][Mzp]
 // So the (x, y, kz) intermediate never goes to HBM: per x-plane the block
@@ -138,18 +139,33 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
     if (lane_live && lslot < S::ZL && y < N) {
       LdsLine<T, Plan::SH, false> lds{X + (long)lslot * LS};
       const cx<T>* row = P + (long)y * Ps;
-      cx<T> la[KL], lb[KL];
+      // each complex line packs two real ones, a + i b, straight from their
+      // rows of P: Z_p = a_p + i b_p for p < Mz, Z_p = conj a_{N-p} + i conj
+      // b_{N-p} for N - p < Mz (the Hermitian halves of the real lines), the
+      // imaginary parts of a_0, b_0 (and of the Nyquist terms) dropped as a
+      // real inverse transform does; registers that no coefficient reaches
+      // (col_live) stay zero without a read
       cx<T> ph[3][R];
       static_for<0, 3>([&](auto pr) {
-        static_for<0, KL>([&](auto t) {
-          const int k = j + t * Tl;
-          la[t] = k < Mz ? row[(2 * pr) * cs + k] : cx<T>{T(0), T(0)};
-          lb[t] = k < Mz ? row[(2 * pr + 1) * cs + k] : cx<T>{T(0), T(0)};
+        const cx<T>* ra = row + (2 * pr) * cs;
+        const cx<T>* rb = ra + cs;
+        static_for<0, R>([&](auto s) {
+          constexpr bool dead = s * Tl >= KL * Tl && (s + 1) * Tl - 1 <= N - KL * Tl;
+          if constexpr (dead) {
+            ph[pr][s] = cx<T>{T(0), T(0)};
+          } else {
+            const int p = j + s * Tl;
+            const bool lo = p < Mz, hi = !lo && N - p < Mz;
+            const int k = lo ? p : (hi ? N - p : 0);
+            cx<T> a = ra[k], b = rb[k];
+            if (k == 0 || 2 * k == N) {
+              a.y = T(0);
+              b.y = T(0);
+            }
+            ph[pr][s] = lo ? cx<T>{a.x - b.y, a.y + b.x}
+                           : (hi ? cx<T>{a.x + b.y, b.x - a.y} : cx<T>{T(0), T(0)});
+          }
         });
-        put_completed<T, Plan, KL>(lds, la, lb, j, Mz);
-        lds.sync();
-        read_completed<T, Plan, KL>(lds, ph[pr], j, Mz);
-        lds.sync();
         Plan::template fft<T, +1>(ph[pr], j, lds, tw);
       });
       cx<T> z01[R], z2[R];
