@@ -424,10 +424,14 @@ struct Impl {
     const dim3 grid((unsigned)((ntiles + group - 1) / group * group), (unsigned)nb);
     // registers that can hold a retained row: the 2/3-rule count, or all
     constexpr int KL23 = (((N - 1) / 3 + 1) + TlF - 1) / TlF;
-    if (N <= 64 && is_g23(g))  // the batch sizes: the geometry at compile time
-      hipLaunchKernelGGL((k_x_fwd_rk<T, PF, WW, KL23, true>), grid, dim3(WW * TlF), 0, s, (const cx<T>*)A, csA,
-                         isA, (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
-    else if (g.lo <= KL23 * TlF && g.hi <= KL23 * TlF)
+    if constexpr (N <= 64) {  // the batch sizes: the geometry at compile time where it is the 2/3 rule's
+      if (is_g23(g)) {
+        hipLaunchKernelGGL((k_x_fwd_rk<T, PF, WW, KL23, true>), grid, dim3(WW * TlF), 0, s, (const cx<T>*)A, csA,
+                           isA, (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
+        return hipGetLastError();
+      }
+    }
+    if (g.lo <= KL23 * TlF && g.hi <= KL23 * TlF)
       hipLaunchKernelGGL((k_x_fwd_rk<T, PF, WW, KL23>), grid, dim3(WW * TlF), 0, s, (const cx<T>*)A, csA, isA,
                          (cx<T>*)U0, (cx<T>*)U1, (cx<T>*)Acc, C, isU, g, mode, T(nu), T(dt));
     else
