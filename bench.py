@@ -228,6 +228,11 @@ def batch_cpu_baseline(sizes, per_size=2):
     }
 
 
+# batch schedules (hot_set_variant "graph"): one graph branch per size, the
+# sizes chained, or the persistent kernel (one launch for every pass)
+GRAPH_LAYOUTS = {"branches": 1, "chain": 0, "persistent": 2}
+
+
 def bench_batch(a):
     """Many uneven instances: one RK4 step of every instance per call."""
     import numpy as np
@@ -250,7 +255,7 @@ def bench_batch(a):
         try:
             with torch.cuda.stream(s):
                 binding.hot_tune(plan, ws, s)
-                binding.hot_set_variant(plan, "graph", 1 if a.graph_layout == "branches" else 0)
+                binding.hot_set_variant(plan, "graph", GRAPH_LAYOUTS[a.graph_layout])
                 g = binding.hot_graph_create(plan, ins, outs, ws, 1, s)
                 binding.hot_graph_launch(g, s)
                 torch.cuda.synchronize()
@@ -282,7 +287,7 @@ def bench_batch(a):
             prof = binding.hot_profile_read(plan)
             binding.hot_profile_enable(plan, False)
             # graph: the whole batch step as one replayed HIP graph
-            binding.hot_set_variant(plan, "graph", 1 if a.graph_layout == "branches" else 0)
+            binding.hot_set_variant(plan, "graph", GRAPH_LAYOUTS[a.graph_layout])
             g = binding.hot_graph_create(plan, ins, outs, ws, 1, s)
             binding.hot_graph_launch(g, s)
             torch.cuda.synchronize()
@@ -346,7 +351,9 @@ def bench_batch(a):
         "config": {"workload": f"rk4_batch_{B}_uneven_16-64_{a.dtype}", "instances": B, "graph": a.graph_layout,
                    "sizes": {int(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))},
                    "points": int((sizes.astype(np.int64) ** 3).sum()), "nu": NU, "dt": DT,
-                   "launch": "one HIP graph replay per batch step (one launch per pass per size inside)"},
+                   "launch": ("one HIP graph replay per batch step (the pointer tables, a setup kernel and one "
+                              "persistent kernel for every pass inside)" if a.graph_layout == "persistent" else
+                              "one HIP graph replay per batch step (one launch per pass per size inside)")},
         "elements_per_sec": float((sizes.astype(np.float64) ** 3).sum()) / t_graph,
         "eager_instances_per_sec": B / t_eager,
         "one_instance_per_call_instances_per_sec": B / t_single,
@@ -812,8 +819,9 @@ def main():
     ap.add_argument("--ranks", type=int, default=8, help="slab: shares of the field")
     ap.add_argument("--rank", type=int, default=0, help="slab: the share timed")
     ap.add_argument("--batch", type=int, default=4096, help="instances of the batch workload")
-    ap.add_argument("--graph-layout", default="branches", choices=["branches", "chain"],
-                    help="batch: one graph branch per size (default) or the sizes one after another")
+    ap.add_argument("--graph-layout", default="branches", choices=["branches", "chain", "persistent"],
+                    help="batch: one graph branch per size (default), the sizes one after another, or the "
+                         "persistent kernel (every pass of the call in one launch)")
     ap.add_argument("--replays-only", type=int, default=0, metavar="K",
                     help="batch: tune, capture, pause 0.5 s, replay the graph K times and print only that "
                          "(for kernel traces of the replays)")

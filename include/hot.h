@@ -238,11 +238,15 @@ int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
  * c0, c1, c2 as component rows) or 0 (six component rows, the z pass
  * completing the Hermitian halves in LDS), hot_tune timing the four over
  * the y inverse, z and y forward passes; for "graph" (no kernel of its own)
- * the layout of
- * graphs hot_graph_create captures from then on: 1 (the default) one branch
- * per distinct N, forked from and joined back into the capturing stream, so
- * the passes of small sizes run beside those of large ones; 0 the sizes one
- * after another; for "imp_decide" (IMPLICIT plans only) the sweeps per round
+ * the batch schedule: 1 (the default) graphs hot_graph_create captures from
+ * then on have one branch per distinct N, forked from and joined back into
+ * the capturing stream, so the passes of small sizes run beside those of
+ * large ones; 0 the sizes one after another; 2 (RK4 plans in FP32 with the
+ * 2/3 rule and at most 8 distinct N, each of 16, 18, 24, 32, 36, 48, 54 or
+ * 64) every pass of every instance and step of a hot_run or captured call
+ * in one launch of a persistent kernel (pass "persistent": a queue of work
+ * items in the workspace, each pass as in the fused schedule, Sec. 2's RK4
+ * on Eq. NSfinal), eager or captured; for "imp_decide" (IMPLICIT plans only) the sweeps per round
  * between an eager call's looks at the stopping flags, K >= 0 (default 3; 0:
  * never look, enqueue max_iter sweeps).  hot_tuned_width reports these
  * settings for the non-tiled passes.  Host only.  Errors: HOT_E_INVALID. */
@@ -415,7 +419,8 @@ int hot_profile_read(hot_plan_t p, int32_t max_passes, double* ms, int64_t* laun
 
 /* Name of pass id (static storage), and the algorithmic HBM bytes one launch
  * of that pass moves for instance i of the plan (each retained input and
- * output value read or written once; 0 if the pass is unused by the op). */
+ * output value read or written once; 0 if the pass is unused by the op; for
+ * "persistent" the passes of a one-step RK4 call). */
 const char* hot_pass_name(int32_t pass);
 int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes);
 

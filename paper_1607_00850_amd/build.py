@@ -45,7 +45,7 @@ def sizes():
 
 def _units():
     os.makedirs(BUILD, exist_ok=True)
-    units = [os.path.join(CSRC, "hot.hip"), os.path.join(CSRC, "mlp.hip")]
+    units = [os.path.join(CSRC, "hot.hip"), os.path.join(CSRC, "mlp.hip"), os.path.join(CSRC, "persist.hip")]
     for t, ty in (("f32", "float"), ("f64", "double")):
         for n in sizes():
             path = os.path.join(BUILD, f"ops_{t}_{n}.hip")

@@ -14,6 +14,7 @@
 #include "checks.hpp"
 #include "impl.hpp"
 #include "mlp_launch.hpp"
+#include "persist.hpp"
 
 namespace hot {
 
@@ -37,13 +38,15 @@ enum Pass : int {
   PASS_YZ_FUSED,
   PASS_TABLES,
   PASS_STATS,
-  PASS_GRAPH,  // no kernel: the layout of captured graphs (hot_set_variant)
+  PASS_GRAPH,  // no kernel: the batch schedule (hot_set_variant)
+  PASS_PERSIST,  // the persistent batch kernel (every pass of an RK4 call)
   NUM_PASSES
 };
 
 static const char* kPassNames[NUM_PASSES] = {
     "gather", "x_inv_curl", "y_inv", "z_cross", "y_fwd", "x_fwd", "rk_stage", "scatter", "z_r2c", "z_c2r", "x_inv",
     "imp_predict", "imp_update", "imp_decide", "imp_advance", "x_fwd_rk", "yz_fused", "tables", "stats", "graph",
+    "persistent",
 };
 
 template <typename T>
@@ -158,6 +161,7 @@ struct hot_plan_s {
   int nranks = 1, rank = 0, chunk = 0, nx = 0;
   Geo gz{};  // geometry of the exchanged z lines (all retained kz, pitch of the blocks)
   size_t o_finite = 0;              // HOT_FLAG_CHECK_FINITE: byte offset of the flag in the workspace
+  size_t o_persist = 0;             // FP32 RK4 with the 2/3 rule: the persistent kernel's control block
   const void* surrogate = nullptr;  // packed MLP for the implicit warm start
   void* hist_ws = nullptr;          // workspace holding the kept history
   void* cnt_ws = nullptr;           // implicit step: workspace and stream of the last call (its counters)
@@ -180,7 +184,8 @@ struct hot_plan_s {
   // graph each) and the events of the fork and the join
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> side_ev;
-  bool graph_branches = true;  // hot_set_variant(graph_branches): 1 branch per group, 0 one chain
+  bool graph_branches = true;  // hot_set_variant(graph): 1 branch per group, 0 one chain
+  bool persistent = false;     // hot_set_variant(graph) 2: the persistent kernel (RK4)
   int imp_check = 3;           // implicit step: sweeps between the host's looks at the flags (0: never)
   std::vector<int> act_host;   // implicit step: the flags read back, per instance
 };
@@ -258,6 +263,10 @@ static int layout_groups(hot_plan_s* p, int op) {
   if (p->flags & HOT_FLAG_CHECK_FINITE) {
     p->o_finite = p->ws_bytes;
     p->ws_bytes += kAlign;
+  }
+  if (op == HOT_OP_RK4 && p->elem == 8 && p->dealias == HOT_DEALIAS_TWO_THIRDS && !p->slab) {
+    p->o_persist = p->ws_bytes;
+    p->ws_bytes += align_up(kPersistAreaBytes);
   }
   return HOT_OK;
 }
@@ -419,6 +428,11 @@ int hot_pass_bytes(hot_plan_t p, int32_t instance, int32_t pass, double* bytes) 
     case PASS_TABLES: b = 0; break;  // a few pointers per instance
     case PASS_STATS: b = plain ? 0 : 3 * C; break;  // reads the compact state once
     case PASS_GRAPH: b = 0; break;
+    // the persistent kernel over a one-step RK4 call: the gather, four stages
+    // of the x inverse, the fused y-z pass and the fused x forward, the scatter
+    case PASS_PERSIST:
+      b = p->op == HOT_OP_RK4 ? 6 * C + 4 * ((3 * C + 6 * D1) + 9 * D1 + (3 * D1 + 12 * C)) + 3 * C + canon : 0;
+      break;
     default: return HOT_E_INVALID;
   }
   *bytes = b * e;
@@ -706,6 +720,68 @@ int check_run_args(hot_plan_s* p, void* const* in, void* const* out, void* works
   return HOT_OK;
 }
 
+// Whether the persistent kernel has every size of the plan: FP32 RK4 with
+// the 2/3 rule, at most kPersistMaxGroups sizes, each a batch size of the
+// fused y-z pass in its compile-time geometry.
+bool persist_ok(const hot_plan_s* p) {
+  if (p->op != HOT_OP_RK4 || p->elem != 8 || p->dealias != HOT_DEALIAS_TWO_THIRDS || p->slab) return false;
+  if (p->groups.empty() || p->groups.size() > (size_t)kPersistMaxGroups) return false;
+  for (const auto& G : p->groups) {
+    PersistGroup t{};
+    t.N = G.N;
+    t.nb = G.B();
+    t.C = G.C;
+    t.D1 = G.D1;
+    t.g = G.g;
+    if (persist_fill(t) == 0) return false;
+  }
+  return true;
+}
+
+// An RK4 call as one persistent launch (hot_set_variant(graph, 2)): the
+// pointer tables, a fill of the control block, the kernel, then the
+// statistics.
+int enqueue_persistent(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps,
+                       hipStream_t stream, bool record, StatsRec* stats) {
+  Runner r{p, stream, record};
+  PersistArgs a{};
+  a.ng = (int)p->groups.size();
+  a.nsteps = nsteps;
+  a.nu = (float)p->nu;
+  a.dt = (float)p->dt;
+  a.ctl = nullptr;  // set on the device by persist_launch
+  size_t lds = 0;
+  for (size_t gi = 0; gi < p->groups.size() && r.rc == HOT_OK; ++gi) {
+    const Group& G = p->groups[gi];
+    const GroupPtrs q = group_ptrs(G, workspace);
+    write_tables(r, G, q, in, out);
+    PersistGroup& P = a.G[gi];
+    P.N = G.N;
+    P.nb = G.B();
+    P.C = G.C;
+    P.D1 = G.D1;
+    P.g = G.g;
+    P.in0 = in[G.members[0]];
+    P.in_tab = q.in_tab;
+    P.out0 = out[G.members[0]];
+    P.out_tab = q.out_tab;
+    P.U0 = q.U0;
+    P.U1 = q.U1;
+    P.Acc = q.Acc;
+    P.A1 = q.A1;
+    const size_t b = persist_fill(P);
+    if (b == 0) return HOT_E_INVALID;  // hot_set_variant checked every size
+    if (b > lds) lds = b;
+  }
+  r.pass(PASS_PERSIST, [&] { return persist_launch(r.s, a, (char*)workspace + p->o_persist, lds); });
+  if (stats)
+    for (const auto& G : p->groups) {
+      const GroupPtrs q = group_ptrs(G, workspace);
+      state_stats(r, p, G, q, q.U0, stats, false);
+    }
+  return r.rc;
+}
+
 // Enqueue the whole operation (the pointer tables are already in place).
 int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, int32_t nsteps, hipStream_t stream,
             bool record, StatsRec* stats, bool branches = false) {
@@ -745,6 +821,8 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
     }
     return r.rc;
   }
+  if (p->persistent && p->op == HOT_OP_RK4)
+    return enqueue_persistent(p, in, out, workspace, nsteps, stream, record, stats);
   // right-hand side / RK4: group by group (a small group's working set can
   // stay in the device's last-level cache between its passes), or one branch
   // per group
@@ -1399,9 +1477,11 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
     p->imp_check = variant;
     return HOT_OK;
   }
-  if (pass == PASS_GRAPH) {  // 1: one branch per size (default), 0: the sizes one after another
-    if (variant < 0 || variant > 1) return HOT_E_INVALID;
+  if (pass == PASS_GRAPH) {  // 1: one branch per size (default), 0: the sizes one after another,
+                             // 2: the persistent kernel (RK4)
+    if (variant < 0 || variant > 2 || (variant == 2 && !persist_ok(p))) return HOT_E_INVALID;
     p->graph_branches = variant == 1;
+    p->persistent = variant == 2;
     return HOT_OK;
   }
   if (pass == PASS_Z_CROSS) {  // the row form (Group::zpack), 0..3
@@ -1431,7 +1511,7 @@ extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
         return G.fused < 0 ? 0 : G.ops.fused_width[G.fused];
       if (pass == PASS_YZ_FUSED) return G.yz < 0 ? 0 : 1;
       if (pass == PASS_Z_CROSS) return G.zpack;
-      if (pass == PASS_GRAPH) return p->graph_branches ? 1 : 0;
+      if (pass == PASS_GRAPH) return p->persistent ? 2 : (p->graph_branches ? 1 : 0);
       if (pass == PASS_IMP_DECIDE) return p->op == HOT_OP_IMPLICIT ? p->imp_check : HOT_E_INVALID;
       return G.ops.strided_width[G.variant[pass] % 3];
     }

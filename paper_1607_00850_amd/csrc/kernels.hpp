@@ -458,21 +458,18 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl3(const cx<T>* __rest
 // fewer blocks than k_x_inv_curl and three component loads per tile instead
 // of nine.  No barrier is needed between two transforms: every exchange ends
 // with one after its reads, and the last stage works in registers.
+// One tile of instance `inst`, run by the W * Tl threads of a block (tid)
+// with sm = N * W + N values of LDS (the exchange tile, then the stage
+// twiddles).  k_x_inv_curl6 runs one tile per block; the persistent batch
+// kernel calls it for its work items.
 template <typename T, class Plan, int W, bool G23 = false>
-__global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __restrict__ U, long csU, long isU,
-                                                             cx<T>* __restrict__ A, long csA, long isA,
-                                                             int ntiles, Geo g_in, T usc, const int* __restrict__ act) {
+__device__ __forceinline__ void x_inv_curl6_tile(const cx<T>* __restrict__ U, long csU, long isU,
+                                                 cx<T>* __restrict__ A, long csA, long isA, int tile, int inst,
+                                                 int tid, const Geo& g_in, T usc, cx<T>* sm) {
   const Geo g = G23 ? geo_two_thirds<Plan::N>(g_in) : g_in;
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
   constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
-  __shared__ cx<T> sm[N * W];
-  __shared__ cx<T> tws[N];
-  const int blk = blockIdx.x;
-  const int xcd = blk & 7, rest = blk >> 3;
-  const int tile = ((rest / PAIR) * 8 + xcd) * PAIR + rest % PAIR;
-  if (tile >= ntiles) return;           // whole block leaves together
-  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
-  const int tid = threadIdx.x;
+  cx<T>* tws = sm + N * W;
   TwStage<T, Plan, W * Tl> tw;  // to LDS, ordered before use by the first exchange barrier
   tw.fetch(tid);
   const int c = tid % W, j = tid / W;
@@ -484,8 +481,8 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __rest
   const T ky = T(kwave(cpos(valid ? iy : 0, g), N));
   const T kzf = T(kz + g.kz0);
   const long qq = valid ? q : 0;
-  U += blockIdx.y * isU;
-  A += blockIdx.y * isA;
+  U += inst * isU;
+  A += inst * isA;
   const long ub = cbase(qq, g);
   cx<T> u[3][R];
   static_for<0, 3>([&](auto comp) {
@@ -517,6 +514,20 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __rest
       static_for<0, R>([&](auto s) { store_out<PAIR == 1>(dst + (long)(j + s * Tl) * Q, v[s]); });
     }
   });
+}
+
+template <typename T, class Plan, int W, bool G23 = false>
+__global__ __launch_bounds__(W* Plan::Tl) void k_x_inv_curl6(const cx<T>* __restrict__ U, long csU, long isU,
+                                                             cx<T>* __restrict__ A, long csA, long isA,
+                                                             int ntiles, Geo g_in, T usc, const int* __restrict__ act) {
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+  __shared__ cx<T> sm[Plan::N * W + Plan::N];
+  const int blk = blockIdx.x;
+  const int xcd = blk & 7, rest = blk >> 3;
+  const int tile = ((rest / PAIR) * 8 + xcd) * PAIR + rest % PAIR;
+  if (tile >= ntiles) return;           // whole block leaves together
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
+  x_inv_curl6_tile<T, Plan, W, G23>(U, csU, isU, A, csA, isA, tile, blockIdx.y, threadIdx.x, g_in, usc, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1245,30 +1256,29 @@ __device__ __forceinline__ void x_rk_tail(const cx<T> (&v)[3][Plan::R], int j, l
 // A[3][N rows (x)][Q = M*Mzp cols (ky, kz)]; the state arrays are compact
 // [3][M][Q].  blockIdx.y is the instance of a batch.
 // ---------------------------------------------------------------------------
-template <typename T, class Plan, int W, int KL, bool G23 = false>
-__global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restrict__ A, long csA, long isA,
-                                                          cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
-                                                          cx<T>* __restrict__ Acc, long C, long isU, Geo g_in, int mode,
-                                                          T nu, T dt) {
+// One tile of instance `inst` (tile * W < M * Mzp), run by the W * Tl
+// threads of a block (tid) with sm = N * W + N values of LDS (the exchange
+// tile, then the stage twiddles).  k_x_fwd_rk runs one tile per block; the
+// persistent batch kernel calls it for its work items.
+template <typename T, class Plan, int W, int KL, bool G23 = false, int GL = 2>
+__device__ __forceinline__ void x_fwd_rk_tile(const cx<T>* __restrict__ A, long csA, long isA,
+                                              cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
+                                              cx<T>* __restrict__ Acc, long C, long isU, const Geo& g_in, int mode,
+                                              T nu, T dt, long tile, int inst, int tid, cx<T>* sm) {
   const Geo g = G23 ? geo_two_thirds<Plan::N>(g_in) : g_in;
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl;
-  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
-  __shared__ cx<T> sm[N * W];
-  __shared__ cx<T> tws[N];
+  cx<T>* tws = sm + N * W;
   const long Q = (long)g.M * g.Mzp;
-  const long tile = tile_of_block<PAIR>(blockIdx.x);
-  if (tile * W >= Q) return;  // whole block leaves together
-  const int tid = threadIdx.x;
   const int c = tid % W, j = tid / W;
   const long q = tile * W + c;
   const int iy = (int)(q / g.Mzp);
   const int kz = (int)(q - (long)iy * g.Mzp);
   const bool valid = q < Q && kz < g.Mz;
   const long qq = valid ? q : 0;
-  A += blockIdx.y * isA;
-  U0 += blockIdx.y * isU;
-  U1 += blockIdx.y * isU;
-  Acc += blockIdx.y * isU;
+  A += inst * isA;
+  U0 += inst * isU;
+  U1 += inst * isU;
+  Acc += inst * isU;
   TwStage<T, Plan, W * Tl> tw;
   tw.fetch(tid);
   // every component's loads in flight together (their registers hold the
@@ -1290,12 +1300,26 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restric
   const int kyi = kwave(cpos(iy, g), N);
   const long cb = cbase(q, g);
   switch (mode) {
-    case 0: x_rk_tail<T, Plan, KL, 0>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
-    case 1: x_rk_tail<T, Plan, KL, 1>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
-    case 2: x_rk_tail<T, Plan, KL, 2>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
-    case 3: x_rk_tail<T, Plan, KL, 3>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
-    default: x_rk_tail<T, Plan, KL, 4>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 0: x_rk_tail<T, Plan, KL, 0, GL>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 1: x_rk_tail<T, Plan, KL, 1, GL>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 2: x_rk_tail<T, Plan, KL, 2, GL>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    case 3: x_rk_tail<T, Plan, KL, 3, GL>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
+    default: x_rk_tail<T, Plan, KL, 4, GL>(v, j, cb, kyi, kz, g, U0, U1, Acc, C, nu, dt); break;
   }
+}
+
+template <typename T, class Plan, int W, int KL, bool G23 = false>
+__global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restrict__ A, long csA, long isA,
+                                                          cx<T>* __restrict__ U0, cx<T>* __restrict__ U1,
+                                                          cx<T>* __restrict__ Acc, long C, long isU, Geo g_in, int mode,
+                                                          T nu, T dt) {
+  constexpr int PAIR = (W * (int)sizeof(cx<T>) < 128) ? 128 / (W * (int)sizeof(cx<T>)) : 1;
+  __shared__ cx<T> sm[Plan::N * W + Plan::N];
+  const long tile = tile_of_block<PAIR>(blockIdx.x);
+  // whole block leaves together (the launcher's g has the row count M * Mzp)
+  if (tile * W >= (long)g_in.M * g_in.Mzp) return;
+  x_fwd_rk_tile<T, Plan, W, KL, G23>(A, csA, isA, U0, U1, Acc, C, isU, g_in, mode, nu, dt, tile, blockIdx.y,
+                                     threadIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1641,15 +1665,13 @@ __global__ __launch_bounds__(256) void k_write_tab(const void** __restrict__ dst
   if (i < n) dst[i] = c.p[i];
 }
 
+// The elements e0, e0 + stride, ... of one instance (st: stride in the
+// digits of the loop).  k_gather runs it as a grid-stride loop; the
+// persistent batch kernel as a block-stride loop per work item.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in0, const cx<T>* const* __restrict__ in_tab,
-                                                cx<T>* __restrict__ out, long C, long is, Geo g, Pos4 st) {
-  // instance blockIdx.y: its canonical input from the table (or in0 alone)
-  const cx<T>* __restrict__ in = in_tab ? in_tab[blockIdx.y] : in0;
-  out += blockIdx.y * is;
-  const long stride = (long)gridDim.x * blockDim.x;
+__device__ __forceinline__ void gather_part(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const Geo& g,
+                                            Pos4 st, long e, long stride) {
   const long Nh = g.czp;  // canonical z extent; its kz 0 is local column 0
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g.tw == g.M * g.Mzp) {
     // row-major compact [3][M][M][Mzp]; st: the grid stride in the same digits
     Pos4 p = pos4_first((unsigned)e, g.M, g.M, g.Mzp);
@@ -1674,14 +1696,21 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in0, c
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, cx<T>* out0, cx<T>* const* __restrict__ out_tab,
-                                                 long C, long is, Geo g, Pos4 st) {
-  cx<T>* __restrict__ out = out_tab ? out_tab[blockIdx.y] : out0;
-  in += blockIdx.y * is;
-  const long stride = (long)gridDim.x * blockDim.x;
+__global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ in0, const cx<T>* const* __restrict__ in_tab,
+                                                cx<T>* __restrict__ out, long C, long is, Geo g, Pos4 st) {
+  // instance blockIdx.y: its canonical input from the table (or in0 alone)
+  const cx<T>* __restrict__ in = in_tab ? in_tab[blockIdx.y] : in0;
+  gather_part(in, out + blockIdx.y * is, g, st, (long)blockIdx.x * blockDim.x + threadIdx.x,
+              (long)gridDim.x * blockDim.x);
+}
+
+// The elements e0, e0 + stride, ... of one instance's canonical output, as
+// gather_part.
+template <typename T>
+__device__ __forceinline__ void scatter_part(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long C,
+                                             const Geo& g, Pos4 st, long e, long stride) {
   const int Nh = g.czp;
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  // canonical [3][N][N][Nh]; st: the grid stride in the same digits
+  // canonical [3][N][N][Nh]; st: the stride in the same digits
   Pos4 p = pos4_first((unsigned)e, g.N, g.N, Nh);
   for (; p.c < 3; e += stride, pos4_add(p, st, g.N, g.N, Nh)) {
     cx<T> v = {T(0), T(0)};
@@ -1689,6 +1718,14 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, c
       v = in[(long)p.c * C + cbase((long)crow(p.b, g) * g.Mzp + p.z, g) + (long)crow(p.a, g) * g.tw];
     store_stream(out + e, v);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, cx<T>* out0, cx<T>* const* __restrict__ out_tab,
+                                                 long C, long is, Geo g, Pos4 st) {
+  cx<T>* __restrict__ out = out_tab ? out_tab[blockIdx.y] : out0;
+  scatter_part(in + blockIdx.y * is, out, C, g, st, (long)blockIdx.x * blockDim.x + threadIdx.x,
+               (long)gridDim.x * blockDim.x);
 }
 
 }  // namespace hot

@@ -35,12 +35,13 @@ struct LdsColumn {
 };
 
 // Block shape: enough waves for all N z lines of the plane in one round
-// (at most 8), so that the lanes stay busy at every size.
-template <typename T, class Plan>
+// (at most 8), so that the lanes stay busy at every size; NWF > 0 sets the
+// number of waves instead (the persistent batch kernel's block).
+template <typename T, class Plan, int NWF = 0>
 struct YzShape {
   static constexpr int N = Plan::N, Tl = Plan::Tl;
   static constexpr int LPW = Tl <= 64 ? 64 / Tl : 1;  // lines per wave (leftover lanes idle)
-  static constexpr int NW = (N + LPW - 1) / LPW < 8 ? (N + LPW - 1) / LPW : 8;
+  static constexpr int NW = NWF > 0 ? NWF : ((N + LPW - 1) / LPW < 8 ? (N + LPW - 1) / LPW : 8);
   static constexpr int NT = 64 * NW;
   static constexpr int LPR = NW * LPW;  // lines per round
   static constexpr int ZL = LPR < N ? LPR : N;  // z lines in flight (exchange slots)
@@ -54,16 +55,16 @@ struct YzShape {
   static constexpr bool kFits = Tl <= 64 && lds_bytes(MZ) <= 163840;
 };
 
-// G23: the launcher has checked that g is the 2/3-rule geometry of N.
-template <typename T, class Plan, int KL, bool G23>
-__global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __restrict__ A, long csA, long isA,
-                                                  Geo g_in, const int* __restrict__ act) {
+// x-plane x of instance `inst`, run by the S::NT threads of a block (tid)
+// with S::lds_bytes(g.Mz) of LDS at sm.  G23: the caller has checked that g
+// is the 2/3-rule geometry of N.  k_yz_fused runs one plane per block; the
+// persistent batch kernel calls it for its work items.
+template <typename T, class Plan, int KL, bool G23, int NWF = 0>
+__device__ __forceinline__ void yz_fused_plane(cx<T>* __restrict__ A, long csA, long isA, const Geo& g_in, long x,
+                                               int inst, int tid, cx<T>* sm) {
   const Geo g = G23 ? geo_two_thirds<Plan::N>(g_in) : g_in;
-  using S = YzShape<T, Plan>;
+  using S = YzShape<T, Plan, NWF>;
   constexpr int N = Plan::N, R = Plan::R, Tl = Plan::Tl, LS = Plan::line_stride;
-  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
-  extern __shared__ unsigned char smem_raw[];
-  cx<T>* sm = reinterpret_cast<cx<T>*>(smem_raw);
   constexpr int NT = S::NT;
   const int Mz = g.Mz, M = g.M;
   const int Ps = S::pitch(Mz);         // row pitch of P
@@ -71,13 +72,11 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
   cx<T>* P = sm;                       // [6][N][Ps]
   cx<T>* X = P + 6 * cs;               // z-line exchange slots [ZL][LS]
   cx<T>* tws = X + (long)S::ZL * LS;   // stage twiddles [N]
-  const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
   const bool lane_live = lane / Tl < S::LPW;
   const int lslot = w * S::LPW + lane / Tl;  // line of this lane within a round
   const int j = lane % Tl;
-  const long x = blockIdx.x;
-  A += blockIdx.y * isA;
+  A += inst * isA;
   const long plane = (long)M * g.Mzp;  // one x-plane of one component
   TwStage<T, Plan, NT> twst;
   twst.fetch(tid);
@@ -228,6 +227,15 @@ __global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __re
       }
     }
   }
+}
+
+template <typename T, class Plan, int KL, bool G23>
+__global__ __launch_bounds__((YzShape<T, Plan>::NT)) void k_yz_fused(cx<T>* __restrict__ A, long csA, long isA,
+                                                  Geo g_in, const int* __restrict__ act) {
+  if (act && !act[blockIdx.y]) return;  // instance no longer iterating
+  extern __shared__ unsigned char smem_raw[];
+  yz_fused_plane<T, Plan, KL, G23>(A, csA, isA, g_in, blockIdx.x, blockIdx.y, threadIdx.x,
+                                   reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 }  // namespace hot

@@ -115,8 +115,11 @@ def test_workspace_size_formula(N, dtype, elem):
     C, D1, D2 = M * M * P, N * M * P, N * N * P
     h, ws = binding.hot_plan(N, "rk4", dtype, nu=0.01, dt=1e-3)
     binding.hot_destroy(h)
-    # + the partial sums of the per-instance statistics: 64 blocks x (E, eps) in FP64
-    assert ws == 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem) + _align(64 * 2 * 8)
+    # + the partial sums of the per-instance statistics: 64 blocks x (E, eps) in FP64,
+    # + for FP32 the persistent batch kernel's control block and arguments (4096 bytes)
+    persist = 4096 if dtype == "f32" else 0
+    assert ws == (4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem) + _align(64 * 2 * 8)
+                  + persist)
     h, ws = binding.hot_plan(N, "r2c", dtype)
     binding.hot_destroy(h)
     assert ws == 2 * _align(3 * N * N * (N // 2 + 1) * elem)
@@ -165,6 +168,9 @@ def test_batched_workspace_is_the_sum_over_sizes():
     _, w16 = binding.hot_plan([16], "rk4", "f32", nu=0.01, dt=1e-3)
     _, w24 = binding.hot_plan([24], "rk4", "f32", nu=0.01, dt=1e-3)
     _, wb = binding.hot_plan([16, 24, 16, 16], "rk4", "f32", nu=0.01, dt=1e-3)
+    # every FP32 RK4 plan holds one persistent-kernel area (4096 bytes) once
+    per = 4096
+    w16, w24, wb = w16 - per, w24 - per, wb - per
     assert wb >= 3 * w16 + w24 - 4 * 256 * 8 and wb <= 3 * w16 + w24 + 2 * 256 * 8
 
 
@@ -323,7 +329,7 @@ def test_fused_yz_variant_rules_without_the_gpu():
     lib = binding.library()
     names = binding.pass_names()
     yz = names.index("yz_fused")
-    assert names[-4:] == ["yz_fused", "tables", "stats", "graph"]
+    assert names[-5:] == ["yz_fused", "tables", "stats", "graph", "persistent"]
     # the fused y-z pass exists for small N only: a batch switches the sizes that have it
     h, _ = binding.hot_plan([16, 64, 128, 1024], "rk4", "f32", nu=0.01, dt=1e-3)
     try:
@@ -465,3 +471,31 @@ def test_slab_plan_and_run_rules_without_the_gpu():
         assert lib.hot_slab_run(h, 0, 0, None, None, ctypes.c_void_p(256), None) == binding.HOT_E_INVALID
     finally:
         binding.hot_destroy(h)
+
+
+def test_persistent_schedule_rules_without_the_gpu():
+    """The persistent batch kernel (graph variant 2) takes FP32 RK4 plans with
+    the 2/3 rule whose sizes all have its bodies (N <= 64 of the batch sizes),
+    at most eight sizes; everything else is refused on the host."""
+    lib = binding.library()
+    names = binding.pass_names()
+    graph = names.index("graph")
+    ok = [([16, 18, 24, 32, 36, 48, 54, 64], "rk4", "f32", "two_thirds"), ([32], "rk4", "f32", "two_thirds")]
+    bad = [([16, 128], "rk4", "f32", "two_thirds"), ([16, 8], "rk4", "f32", "two_thirds"),
+           ([16, 32], "rk4", "f64", "two_thirds"), ([16, 32], "rhs", "f32", "two_thirds"),
+           ([16, 32], "implicit", "f32", "two_thirds"), ([16, 32], "rk4", "f32", "none")]
+    for n, op, dt, de in ok + bad:
+        h, _ = binding.hot_plan(n, op, dt, de, nu=0.01, dt=1e-3)
+        try:
+            rc = lib.hot_set_variant(h, graph, 2)
+            if (n, op, dt, de) in ok:
+                assert rc == binding.HOT_OK
+                assert binding.hot_tuned_width(h, 0, "graph") == 2
+                binding.hot_set_variant(h, "graph", 1)
+                assert binding.hot_tuned_width(h, 0, "graph") == 1
+            else:
+                assert rc == binding.HOT_E_INVALID, (n, op, dt, de)
+                assert binding.hot_tuned_width(h, 0, "graph") == 1
+        finally:
+            binding.hot_destroy(h)
+    assert lib.hot_set_variant(None, graph, 2) == binding.HOT_E_INVALID
