@@ -246,7 +246,11 @@ int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
  * 64) every pass of every instance and step of a hot_run or captured call
  * in one launch of a persistent kernel (pass "persistent": a queue of work
  * items in the workspace, each pass as in the fused schedule, Sec. 2's RK4
- * on Eq. NSfinal), eager or captured; for "imp_decide" (IMPLICIT plans only) the sweeps per round
+ * on Eq. NSfinal), eager or captured; for "persistent" (the plans of
+ * schedule 2) the bound of the kernel's waits in polls, 0 (the default) for
+ * about a second: a wait past it raises an error flag, no wait follows and
+ * the call's outputs from then on are NaN (a small bound forces that path for
+ * tests); for "imp_decide" (IMPLICIT plans only) the sweeps per round
  * between an eager call's looks at the stopping flags, K >= 0 (default 3; 0:
  * never look, enqueue max_iter sweeps).  hot_tuned_width reports these
  * settings for the non-tiled passes.  Host only.  Errors: HOT_E_INVALID. */

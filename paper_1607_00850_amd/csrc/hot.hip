@@ -186,6 +186,7 @@ struct hot_plan_s {
   std::vector<hipEvent_t> side_ev;
   bool graph_branches = true;  // hot_set_variant(graph): 1 branch per group, 0 one chain
   bool persistent = false;     // hot_set_variant(graph) 2: the persistent kernel (RK4)
+  int persist_spin = 0;        // hot_set_variant(persistent): polls of a wait before its error path (0: default)
   int imp_check = 3;           // implicit step: sweeps between the host's looks at the flags (0: never)
   std::vector<int> act_host;   // implicit step: the flags read back, per instance
 };
@@ -749,6 +750,7 @@ int enqueue_persistent(hot_plan_s* p, void* const* in, void* const* out, void* w
   a.nsteps = nsteps;
   a.nu = (float)p->nu;
   a.dt = (float)p->dt;
+  a.spin = p->persist_spin;
   a.ctl = nullptr;  // set on the device by persist_launch
   size_t lds = 0;
   for (size_t gi = 0; gi < p->groups.size() && r.rc == HOT_OK; ++gi) {
@@ -1484,6 +1486,11 @@ extern "C" int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant) {
     p->persistent = variant == 2;
     return HOT_OK;
   }
+  if (pass == PASS_PERSIST) {  // the bound of the persistent kernel's waits, in polls (0: the default)
+    if (variant < 0 || !persist_ok(p)) return HOT_E_INVALID;
+    p->persist_spin = variant;
+    return HOT_OK;
+  }
   if (pass == PASS_Z_CROSS) {  // the row form (Group::zpack), 0..3
     const bool plain = p->op == HOT_OP_R2C || p->op == HOT_OP_C2R;
     if (variant < 0 || variant > 3 || plain) return HOT_E_INVALID;
@@ -1512,6 +1519,7 @@ extern "C" int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass) {
       if (pass == PASS_YZ_FUSED) return G.yz < 0 ? 0 : 1;
       if (pass == PASS_Z_CROSS) return G.zpack;
       if (pass == PASS_GRAPH) return p->persistent ? 2 : (p->graph_branches ? 1 : 0);
+      if (pass == PASS_PERSIST) return p->persist_spin;
       if (pass == PASS_IMP_DECIDE) return p->op == HOT_OP_IMPLICIT ? p->imp_check : HOT_E_INVALID;
       return G.ops.strided_width[G.variant[pass] % 3];
     }

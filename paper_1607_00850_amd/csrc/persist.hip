@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kPersistNT) void k_persist_rk4(const PersistArgs* _
   // loop into two exec-masked levels, with lane 0's dequeue on the outer one,
   // so that the other lanes re-enter the barrier and re-read the slot before
   // lane 0 has taken the next item.
+  const int spin_max = a.spin > 0 ? a.spin : kPersistSpin;
   const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < 64;
   const int lane0 = tid == 0 ? 1 : 0;
   if (tid < kPersistMaxGroups) s_seen[tid] = 0;
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(kPersistNT) void k_persist_rk4(const PersistArgs* _
           for (int spins = 0;; ++spins) {
             d = __builtin_amdgcn_readfirstlane(__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             if (d >= need) break;
-            if (spins >= kPersistSpin) {
+            if (spins >= spin_max) {
               __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               break;
             }

@@ -36,6 +36,7 @@ struct PersistGroup {
 struct PersistArgs {
   int ng, nsteps;
   float nu, dt;
+  int spin;  // polls of a wait before the error flag (0: the default bound)
   int* ctl;  // the control block: queue head, error flag, items of size g completed
   PersistGroup G[kPersistMaxGroups];
 };

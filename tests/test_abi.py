@@ -499,3 +499,18 @@ def test_persistent_schedule_rules_without_the_gpu():
         finally:
             binding.hot_destroy(h)
     assert lib.hot_set_variant(None, graph, 2) == binding.HOT_E_INVALID
+    # the bound of the persistent kernel's waits: plans of schedule 2 only, >= 0
+    pers = names.index("persistent")
+    h, _ = binding.hot_plan([16, 32], "rk4", "f32", nu=0.01, dt=1e-3)
+    try:
+        assert binding.hot_tuned_width(h, 0, "persistent") == 0
+        binding.hot_set_variant(h, "persistent", 5)
+        assert binding.hot_tuned_width(h, 0, "persistent") == 5
+        assert lib.hot_set_variant(h, pers, -1) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)
+    h, _ = binding.hot_plan([16, 32], "rk4", "f64", nu=0.01, dt=1e-3)
+    try:
+        assert lib.hot_set_variant(h, pers, 1) == binding.HOT_E_INVALID
+    finally:
+        binding.hot_destroy(h)

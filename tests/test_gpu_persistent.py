@@ -2,8 +2,9 @@
 a batch of uneven FP32 instances in one launch, its passes taken from a work
 queue with per-size completion counters.  Checked per instance against the
 oracle, against the launch-per-pass schedule with the same fused passes,
-for zero steps (the masked input), through graph replays, and on a batch of
-a few hundred instances."""
+for zero steps (the masked input), through graph replays, on a batch of a
+few hundred instances, and on its error path (the bound of its waits forced
+down from the host)."""
 import numpy as np
 import pytest
 
@@ -113,3 +114,37 @@ def test_persistent_large_batch():
     for i in (0, 101, 202, 319):
         N = fields[i].shape[1]
         assert rel_l2(pk[i], oracle.rk4(round32(fields[i]), NU, DT, 1)) < fp32_tol(N), N
+
+
+def test_persistent_wait_bound_ends_the_call():
+    """The error path, forced from the host: with the waits bounded to one
+    poll, the first wait not met at once raises the error flag, no wait
+    follows and the kernel drains (no hang); the scatter items from then on
+    write NaN.  The next call with the default bound is correct again (every
+    call starts from a zeroed control block)."""
+    import torch
+    sizes = inputs.batch_sizes(320, 7)
+    print(f"persistent, waits bounded to one poll, {len(sizes)} instances", flush=True)
+    fields = _fields(sizes, seed0=5000)
+    h, wsb = binding.hot_plan([f.shape[1] for f in fields], "rk4", "f32", "two_thirds", NU, DT)
+    try:
+        binding.hot_set_variant(h, "graph", 2)
+        binding.hot_set_variant(h, "persistent", 1)
+        assert binding.hot_tuned_width(h, 0, "persistent") == 1
+        ws = workspace(wsb)
+        ins = [to_dev(f, "f32") for f in fields]
+        outs = [torch.empty_like(x) for x in ins]
+        binding.hot_run(h, ins, outs, ws, 1)
+        torch.cuda.synchronize()
+        nan = sum(int(torch.isnan(o).any().item()) for o in outs)
+        print(f"instances with NaN output: {nan} of {len(outs)}", flush=True)
+        assert nan > 0
+        binding.hot_set_variant(h, "persistent", 0)
+        binding.hot_run(h, ins, outs, ws, 1)
+        torch.cuda.synchronize()
+        for i in (0, 150, 319):
+            N = fields[i].shape[1]
+            got = outs[i].cpu().numpy()
+            assert rel_l2(got, oracle.rk4(round32(fields[i]), NU, DT, 1)) < fp32_tol(N), N
+    finally:
+        binding.hot_destroy(h)
