@@ -26,9 +26,12 @@ Readings (the paper is silent on all of them):
   * norm: the L2 norm of the real field, written over the half-spectrum with
     weight 1 on the kz = 0 and kz = N/2 planes and 2 elsewhere (Parseval);
   * predictor ("plain"): the state when there is no history, u^n + D1 after
-    one step, and the linear extrapolation u^n + 2 D1 - D2 after two, where
-    D1 and D2 are the two previous increments u^n - u^{n-1} and
-    u^{n-1} - u^{n-2};
+    one step, the linear extrapolation u^n + 2 D1 - D2 of the increments
+    after two, and the quadratic one u^n + 3 D1 - 3 D2 + D3 after three or
+    more, where D1, D2, D3 are the previous increments u^n - u^{n-1},
+    u^{n-1} - u^{n-2}, u^{n-2} - u^{n-3} (the polynomial through the last
+    increments, evaluated one step ahead: exact when the state is a
+    polynomial in time of one degree more);
   * the state is projected onto the retained set first, as in the RK4 oracle.
 
 Pins (tests marked "not gpu"):
@@ -91,12 +94,15 @@ def midpoint_sweep(u0: np.ndarray, w: np.ndarray, nu: float, dt: float, dealias:
 
 def extrapolation_predictor(u0: np.ndarray, history) -> np.ndarray:
     """Plain predictor from the increments of the previous steps (oldest
-    first): u0, u0 + D1, or u0 + 2 D1 - D2."""
+    first): u0, u0 + D1, u0 + 2 D1 - D2, or with three or more increments
+    u0 + 3 D1 - 3 D2 + D3."""
     if len(history) == 0:
         return u0.copy()
     if len(history) == 1:
         return u0 + history[-1]
-    return u0 + 2.0 * history[-1] - history[-2]
+    if len(history) == 2:
+        return u0 + 2.0 * history[-1] - history[-2]
+    return u0 + 3.0 * history[-1] - 3.0 * history[-2] + history[-3]
 
 
 def implicit_midpoint_step(u0: np.ndarray, nu: float, dt: float, tau: float = 1e-10, max_iter: int = 50,
@@ -133,7 +139,7 @@ def implicit_midpoint(u0: np.ndarray, nu: float, dt: float, nsteps: int, tau: fl
     u = u0 * retained_mask(N, dealias)
     sweeps, incs, fnls = [], [], []
     for _ in range(nsteps):
-        pred = extrapolation_predictor(u, incs[-2:])
+        pred = extrapolation_predictor(u, incs[-3:])
         u1, s, ok, fnl = implicit_midpoint_step(u, nu, dt, tau, max_iter, pred, dealias)
         if not ok:
             raise RuntimeError(f"Picard iteration did not reach tau={tau} in {max_iter} sweeps")

@@ -1,5 +1,6 @@
-"""How fast the Picard sweeps of the implicit-midpoint oracle converge, and
-what a warm start must achieve to save one sweep (CPU, oracle only).
+"""How fast the Picard sweeps of the implicit-midpoint oracle converge, what
+a warm start must achieve to save one sweep, and that the three-increment
+(quadratic) extrapolation achieves it (CPU, oracle only).
 
 Setting of the implicit batch: R1 fields, Re = 1600 (nu = 1/1600, Sec. 4),
 dt = 1e-2, two steps of history, then the step under study.  The reference
@@ -54,3 +55,35 @@ def test_sweeps_contract_and_the_gain_one_sweep_needs(N, seed):
     print(f"N={N}: e_0 = {e[0]:.2e}, rho = {np.round(rho, 3)}, "
           f"a warm start saves a sweep only with error <= {need:.2f} of the extrapolation's", flush=True)
     assert 0.2 < need < 0.6
+
+
+@pytest.mark.parametrize("N,seed", [(32, 20002), (64, 20000)])
+def test_three_increment_predictor_saves_a_sweep(N, seed):
+    """With three steps of history the plain predictor is the quadratic
+    extrapolation 3 D1 - 3 D2 + D3: its error is about a fifteenth of the
+    linear one's, well inside the bound above, and the sweeps stop at the
+    second instead of the third."""
+    u0 = inputs.smooth_random(N, seed)
+    u, _, incs, _ = oracle.implicit_midpoint(u0, NU, DT, 3, 1e-13)
+    lin = u + 2.0 * incs[-1] - incs[-2]
+    ref, _, ok, _ = oracle.implicit_midpoint_step(u, NU, DT, 1e-14, 80, lin)
+    assert ok
+    inc = half_norm(ref - u)
+    m = oracle.retained_mask(N)
+    errs = {}
+    for name, pred in (("linear", lin), ("quadratic", extrapolation_predictor(u, incs))):
+        w = pred * m
+        e = [half_norm(w - ref) / inc]
+        for _ in range(3):
+            w, _ = midpoint_sweep(u, w, NU, DT)
+            e.append(half_norm(w - ref) / inc)
+        errs[name] = np.array(e)
+    ratio = errs["quadratic"][0] / errs["linear"][0]
+    print(f"N={N}: e_0 linear {errs['linear'][0]:.2e}, quadratic {errs['quadratic'][0]:.2e} (ratio {ratio:.3f})",
+          flush=True)
+    assert ratio < 0.2
+    assert 1 + int(np.argmax(errs["linear"] <= TAU)) == 3
+    assert 1 + int(np.argmax(errs["quadratic"] <= TAU)) == 2
+    # the oracle's own step from that predictor stops there too
+    _, sweeps, ok, _ = oracle.implicit_midpoint_step(u, NU, DT, TAU, 20, extrapolation_predictor(u, incs))
+    assert ok and sweeps == 2

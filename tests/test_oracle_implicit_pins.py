@@ -93,7 +93,7 @@ def test_picard_stops_at_tolerance_and_extrapolation_saves_sweeps():
     u0 = inputs.smooth_random(N, 8) * 4.0
     u, sweeps, incs, _ = oracle.implicit_midpoint(u0, NU, dt, 4, tau=1e-10)
     # the stopping test is met by the returned iterate of the last step
-    pred = oracle.extrapolation_predictor(u - incs[-1], incs[-3:-1])
+    pred = oracle.extrapolation_predictor(u - incs[-1], incs[-4:-1])
     _, s_plain, _, _ = oracle.implicit_midpoint_step(u - incs[-1], NU, dt, 1e-10, 50, None)
     _, s_pred, _, _ = oracle.implicit_midpoint_step(u - incs[-1], NU, dt, 1e-10, 50, pred)
     assert s_pred == sweeps[-1]
@@ -128,6 +128,22 @@ def test_extrapolation_predictor_is_exact_on_quadratic_trajectories():
     # one increment of history: exact on linear trajectories
     pred1 = oracle.extrapolation_predictor(A + B, [B])
     assert np.allclose(pred1, A + 2 * B, rtol=0, atol=1e-12)
+
+
+def test_three_increment_predictor_is_exact_on_cubic_trajectories():
+    # u(t) = A + B t + C t^2 + E t^3 at t = 0..3: three increments give u(4);
+    # the two-increment form misses it by the third difference, 6 E
+    rng = np.random.default_rng(2)
+    A, B, C, E = (rng.standard_normal((3, 4, 4, 3)) for _ in range(4))
+    u = [A + B * t + C * t * t + E * t ** 3 for t in range(5)]
+    incs = [u[1] - u[0], u[2] - u[1], u[3] - u[2]]
+    pred = oracle.extrapolation_predictor(u[3], incs)
+    assert np.allclose(pred, u[4], rtol=0, atol=1e-11)
+    pred2 = oracle.extrapolation_predictor(u[3], incs[1:])
+    assert np.allclose(u[4] - pred2, 6 * E, rtol=0, atol=1e-11)
+    # only the last three increments count
+    pred4 = oracle.extrapolation_predictor(u[3], [rng.standard_normal(A.shape)] + incs)
+    assert np.array_equal(pred4, pred)
 
 
 def test_stopping_rule_is_update_over_increment():
