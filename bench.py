@@ -468,9 +468,10 @@ def bench_surrogate(a):
     res = {}
     ws = None
     # plain and assisted: the third step (two increments of history: the
-    # linear extrapolation, or the surrogate's correction of it); plain_h3:
-    # the fourth step, whose plain predictor extrapolates three increments
-    for mode in ("plain", "assisted", "plain_h3"):
+    # linear extrapolation, or the surrogate's correction of it); plain_h3,
+    # plain_h4: the fourth and fifth steps, whose plain predictor extrapolates
+    # three and four increments
+    for mode in ("plain", "assisted", "plain_h3", "plain_h4"):
         plan, wsb = binding.hot_plan([int(x) for x in sizes], "implicit", "f32", "two_thirds", nu, dt, tol, 50,
                                      keep_history=True)
         if ws is None:
@@ -479,7 +480,8 @@ def bench_surrogate(a):
             for i in range(B):
                 mids[i].copy_(ins[i])
             binding.hot_tune(plan, ws)
-            binding.hot_run(plan, mids, mids, ws, 3 if mode == "plain_h3" else 2)  # history: plain steps
+            hist = {"plain_h3": 3, "plain_h4": 4}.get(mode, 2)
+            binding.hot_run(plan, mids, mids, ws, hist)  # history: plain steps
             if mode == "assisted":
                 binding.hot_set_surrogate(plan, pk)
             pre = [mids[i].clone() for i in sample]
@@ -502,8 +504,9 @@ def bench_surrogate(a):
             binding.hot_destroy(plan)
     pre = res["plain"].pop("pre")
     res["assisted"].pop("pre")
-    res["plain_h3"].pop("pre")
-    res["plain_h3"].pop("state")
+    for mode in ("plain_h3", "plain_h4"):
+        res[mode].pop("pre")
+        res[mode].pop("state")
     diffs = [float(torch.linalg.vector_norm(p - q) / max(float(torch.linalg.vector_norm(p - u)), 1e-300))
              for p, q, u in zip(res["plain"].pop("state"), res["assisted"].pop("state"), pre)]
     # rows the fused MLP kernel runs: every compact slot (no row padding for N <= 64 in FP32)
@@ -530,8 +533,10 @@ def bench_surrogate(a):
         "plain": res["plain"],
         "assisted": res["assisted"],
         "plain_h3": res["plain_h3"],
+        "plain_h4": res["plain_h4"],
         "speedup_assisted_over_plain": res["plain"]["seconds"] / res["assisted"]["seconds"],
         "speedup_plain_h3_over_plain": res["plain"]["seconds"] / res["plain_h3"]["seconds"],
+        "speedup_plain_h4_over_plain": res["plain"]["seconds"] / res["plain_h4"]["seconds"],
         "sweeps_saved_per_instance": res["plain"]["mean_sweeps"] - res["assisted"]["mean_sweeps"],
         "assisted_vs_plain_diff_rel_to_increment": {"max": max(diffs), "mean": float(np.mean(diffs)),
                                                     "sampled_instances": len(diffs)},

@@ -80,11 +80,12 @@ extern "C" {
  *         d <- [dt F_NL(u^n + d/2) - 2a u^n] / (1 + a),  a = dt nu |k|^2 / 2,
  *       F_NL the projected, dealiased nonlinear term, until
  *       ||d_new - d|| <= tol ||d_new|| (L2 norms of the real field) or
- *       max_iter sweeps.  The first sweep starts from the predictor 0 at the
- *       first step of a call, the previous increment at the second, the
- *       extrapolation 2 d^{n-1} - d^{n-2} at the third and the quadratic one
- *       3 d^{n-1} - 3 d^{n-2} + d^{n-3} after that (or, from the third step,
- *       the surrogate's warm start, see hot_set_surrogate; with
+ *       max_iter sweeps.  The first sweep starts from the polynomial
+ *       through the last m = min(4, steps so far) increments, one step
+ *       ahead: 0, d^{n-1}, 2 d^{n-1} - d^{n-2},
+ *       3 d^{n-1} - 3 d^{n-2} + d^{n-3}, then
+ *       4 d^{n-1} - 6 d^{n-2} + 4 d^{n-3} - d^{n-4} (or, from the third
+ *       step, the surrogate's warm start, see hot_set_surrogate; with
  *       HOT_FLAG_KEEP_HISTORY the history carries over from the previous
  *       call).  Each instance stops on
  *       its own: the kernels of a sweep return at once for an instance that
@@ -273,9 +274,10 @@ int hot_implicit_stats(hot_plan_t p, int32_t* sweeps, int32_t* nonconv);
  * guess).  Once two earlier increments D1 (newest) and D2 exist, the first
  * sweep of a step starts from
  *     d = 2 D1 - D2 + s MLP(f),   s = ||D1_k|| over the 3 complex components,
- * instead of the plain predictor (2 D1 - D2, or 3 D1 - 3 D2 + D3 once three
- * increments exist: the network corrects the linear extrapolation it was
- * trained on, whatever the history depth).  MLP: 32 -> 256 -> 256 ->
+ * instead of the plain predictor (2 D1 - D2, or the extrapolation of three
+ * or four increments once they exist: the network corrects the linear
+ * extrapolation it was trained on, whatever the history depth).  MLP: 32 ->
+ * 256 -> 256 ->
  * 256 -> 6, tanh hidden layers, BF16 MFMA operands with FP32 accumulation.
  * Features f of mode k, a = dt nu |k|^2 / 2 (all 0 when s = 0):
  *   f[0:6] D1/s, f[6:12] D2/s, f[12:18] ((1 - a) D1 + 2 a u)/s,

@@ -25,13 +25,11 @@ with ||w_{j+1} - w_j|| <= tau ||w_{j+1} - u^n||, or after max_iter sweeps.
 Readings (the paper is silent on all of them):
   * norm: the L2 norm of the real field, written over the half-spectrum with
     weight 1 on the kz = 0 and kz = N/2 planes and 2 elsewhere (Parseval);
-  * predictor ("plain"): the state when there is no history, u^n + D1 after
-    one step, the linear extrapolation u^n + 2 D1 - D2 of the increments
-    after two, and the quadratic one u^n + 3 D1 - 3 D2 + D3 after three or
-    more, where D1, D2, D3 are the previous increments u^n - u^{n-1},
-    u^{n-1} - u^{n-2}, u^{n-2} - u^{n-3} (the polynomial through the last
-    increments, evaluated one step ahead: exact when the state is a
-    polynomial in time of one degree more);
+  * predictor ("plain"): u^n plus the polynomial through the last m =
+    min(4, steps so far) increments D1 (newest) ... Dm, evaluated one step
+    ahead: sum_j (-1)^(j+1) binom(m, j) D_j, i.e. u^n, u^n + D1,
+    u^n + 2 D1 - D2, u^n + 3 D1 - 3 D2 + D3, u^n + 4 D1 - 6 D2 + 4 D3 - D4
+    (exact when the state is a polynomial in time of degree m);
   * the state is projected onto the retained set first, as in the RK4 oracle.
 
 Pins (tests marked "not gpu"):
@@ -45,6 +43,8 @@ Pins (tests marked "not gpu"):
   * second-order convergence against a fine RK4 reference.
 """
 from __future__ import annotations
+
+from math import comb
 
 import numpy as np
 
@@ -92,17 +92,19 @@ def midpoint_sweep(u0: np.ndarray, w: np.ndarray, nu: float, dt: float, dealias:
     return ((1.0 - a) * u0 + dt * fnl) / (1.0 + a), fnl
 
 
+PREDICTOR_DEPTH = 4  # increments the plain predictor extrapolates at most
+
+
 def extrapolation_predictor(u0: np.ndarray, history) -> np.ndarray:
     """Plain predictor from the increments of the previous steps (oldest
-    first): u0, u0 + D1, u0 + 2 D1 - D2, or with three or more increments
-    u0 + 3 D1 - 3 D2 + D3."""
-    if len(history) == 0:
-        return u0.copy()
-    if len(history) == 1:
-        return u0 + history[-1]
-    if len(history) == 2:
-        return u0 + 2.0 * history[-1] - history[-2]
-    return u0 + 3.0 * history[-1] - 3.0 * history[-2] + history[-3]
+    first): u0 plus the polynomial through the last m = min(4, len(history))
+    increments one step ahead, sum_j (-1)^(j+1) binom(m, j) D_j with D1 the
+    newest."""
+    m = min(PREDICTOR_DEPTH, len(history))
+    pred = u0.copy()
+    for j in range(1, m + 1):
+        pred = pred + (-1) ** (j + 1) * comb(m, j) * history[-j]
+    return pred
 
 
 def implicit_midpoint_step(u0: np.ndarray, nu: float, dt: float, tau: float = 1e-10, max_iter: int = 50,
@@ -139,7 +141,7 @@ def implicit_midpoint(u0: np.ndarray, nu: float, dt: float, nsteps: int, tau: fl
     u = u0 * retained_mask(N, dealias)
     sweeps, incs, fnls = [], [], []
     for _ in range(nsteps):
-        pred = extrapolation_predictor(u, incs[-3:])
+        pred = extrapolation_predictor(u, incs[-PREDICTOR_DEPTH:])
         u1, s, ok, fnl = implicit_midpoint_step(u, nu, dt, tau, max_iter, pred, dealias)
         if not ok:
             raise RuntimeError(f"Picard iteration did not reach tau={tau} in {max_iter} sweeps")

@@ -126,7 +126,7 @@ struct Group {
   double lC = 0, lD1 = 0, lD2 = 0;  // live values per component (Mz)
   size_t off = 0;                   // byte offset of the group's region
   size_t oU0 = 0, oU1 = 0, oAcc = 0, oNh = 0, oA1 = 0, oA2 = 0, oTab = 0;
-  size_t oH[3] = {0, 0, 0}, oAct = 0, oPart = 0, oCnt = 0;  // implicit step only
+  size_t oH[4] = {0, 0, 0, 0}, oAct = 0, oPart = 0, oCnt = 0;  // implicit step only
   size_t oDiag = 0;                                      // statistics partial sums
   size_t oZ = 0;                              // z-slab share: receive buffer of the all-to-all
   int nparts = 0;                             // blocks of the implicit update
@@ -254,7 +254,8 @@ static int layout_groups(hot_plan_s* p, int op) {
       G.oH[0] = G.bytes;
       G.oH[1] = G.oH[0] + sC;
       G.oH[2] = G.oH[1] + sC;
-      G.oAct = G.oH[2] + sC;
+      G.oH[3] = G.oH[2] + sC;
+      G.oAct = G.oH[3] + sC;
       G.oPart = G.oAct + align_up(B * sizeof(int));
       G.oCnt = G.oPart + align_up(B * (size_t)G.nparts * 2 * sizeof(double));
       G.bytes = G.oCnt + align_up(2 * B * sizeof(int));
@@ -490,7 +491,7 @@ struct Runner {
 
 struct GroupPtrs {
   char *U0, *U1, *Acc, *Nh, *A1, *A2, *Z;
-  char* H[3];  // implicit step: increment histories
+  char* H[4];  // implicit step: increment histories
   int* act;
   double* part;
   int* cnt;  // implicit step: sweeps[B], then nonconv[B]
@@ -513,6 +514,7 @@ GroupPtrs group_ptrs(const Group& G, void* workspace) {
   q.H[0] = base + G.oH[0];
   q.H[1] = base + G.oH[1];
   q.H[2] = base + G.oH[2];
+  q.H[3] = base + G.oH[3];
   q.act = (int*)(base + G.oAct);
   q.part = (double*)(base + G.oPart);
   q.cnt = (int*)(base + G.oCnt);
@@ -877,8 +879,8 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
 // the midpoint, the update of d, the stopping test); every pass kernel returns
 // at once for an instance whose stopping flag is clear, so each instance stops
 // on its own.  The counters of the call (sweeps, steps stopped at max_iter)
-// stay on the device.  The iterate d and the increment histories H1 (newest),
-// H2, H3 rotate through four buffers (Acc and the three history regions) at
+// stay on the device.  The iterate d and the increment histories H1 (newest)
+// to H4 rotate through five buffers (Acc and the four history regions) at
 // the end of a step: d becomes the newest history.
 //
 // Sweeps go out in rounds of imp_check over every group still iterating
@@ -922,21 +924,22 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
   const int every = record ? p->imp_check : 0;
   std::vector<char> live(ng);
   for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
-    // the iterate d and the histories H1 (newest), H2, H3 rotate through four buffers
-    auto bufs = [&](size_t gi, char*& D, char*& H1, char*& H2, char*& H3) {
+    // the iterate d and the histories H1 (newest) to H4 rotate through five buffers
+    auto bufs = [&](size_t gi, char*& D, char*& H1, char*& H2, char*& H3, char*& H4) {
       const Group& G = p->groups[gi];
-      char* buf[4] = {qs[gi].Acc, qs[gi].H[0], qs[gi].H[1], qs[gi].H[2]};
+      char* buf[5] = {qs[gi].Acc, qs[gi].H[0], qs[gi].H[1], qs[gi].H[2], qs[gi].H[3]};
       D = buf[G.rot];
-      H1 = buf[(G.rot + 1) % 4];
-      H2 = buf[(G.rot + 2) % 4];
-      H3 = buf[(G.rot + 3) % 4];
+      H1 = buf[(G.rot + 1) % 5];
+      H2 = buf[(G.rot + 2) % 5];
+      H3 = buf[(G.rot + 3) % 5];
+      H4 = buf[(G.rot + 4) % 5];
     };
     for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {
       const Group& G = p->groups[gi];
       const GroupPtrs& q = qs[gi];
       r.s = stream_of(gi);
-      char *D, *H1, *H2, *H3;
-      bufs(gi, D, H1, H2, H3);
+      char *D, *H1, *H2, *H3, *H4;
+      bufs(gi, D, H1, H2, H3, H4);
       const long isU = 3 * G.C;
       const int nb = G.B();
       // the surrogate corrects the linear extrapolation of the two newest
@@ -951,7 +954,7 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
         });
       else
         r.pass(PASS_IMP_PREDICT,
-               [&] { return G.ops.imp_predict(r.s, q.U0, D, q.U1, H1, H2, H3, G.C, isU, nb, G.g, G.hist, q.act); });
+               [&] { return G.ops.imp_predict(r.s, q.U0, D, q.U1, H1, H2, H3, H4, G.C, isU, nb, G.g, G.hist, q.act); });
       live[gi] = 1;
     }
     for (int done = 0; done < p->max_iter && r.rc == HOT_OK;) {
@@ -961,8 +964,8 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
         const Group& G = p->groups[gi];
         const GroupPtrs& q = qs[gi];
         r.s = stream_of(gi);
-        char *D, *H1, *H2, *H3;
-        bufs(gi, D, H1, H2, H3);
+        char *D, *H1, *H2, *H3, *H4;
+        bufs(gi, D, H1, H2, H3, H4);
         for (int sw = 0; sw < k && r.rc == HOT_OK; ++sw) {
           rhs_passes(r, G, q, q.U1, q.act);
           r.pass(PASS_IMP_UPDATE, [&] {
@@ -1012,17 +1015,17 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
       Group& G = p->groups[gi];
       const GroupPtrs& q = qs[gi];
       r.s = stream_of(gi);
-      char *D, *H1, *H2, *H3;
-      bufs(gi, D, H1, H2, H3);
-      (void)H1, (void)H2, (void)H3;
+      char *D, *H1, *H2, *H3, *H4;
+      bufs(gi, D, H1, H2, H3, H4);
+      (void)H1, (void)H2, (void)H3, (void)H4;
       r.pass(PASS_IMP_DECIDE, [&] {  // instances still active stopped at max_iter
         hipLaunchKernelGGL(k_imp_close<>, dim3(grid_1d(G.B(), 256)), dim3(256), 0, r.s, (const int*)q.act,
                            q.cnt + G.B(), G.B());
         return hipGetLastError();
       });
       r.pass(PASS_IMP_ADVANCE, [&] { return G.ops.imp_advance(r.s, q.U0, D, G.C, 3 * G.C, G.B(), G.g); });
-      G.rot = (G.rot + 3) % 4;  // d becomes H1, H1 becomes H2, H2 becomes H3, H3's buffer the next d
-      if (G.hist < 3) ++G.hist;
+      G.rot = (G.rot + 4) % 5;  // d becomes H1, H1 becomes H2, ..., H4's buffer the next d
+      if (G.hist < 4) ++G.hist;
     }
   }
   for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {

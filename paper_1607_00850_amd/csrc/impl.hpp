@@ -128,7 +128,7 @@ struct Ops {
                         const Geo&);
   // implicit midpoint step
   hipError_t (*imp_predict)(hipStream_t, const void* U0, void* D, void* U1, const void* H1, const void* H2,
-                            const void* H3, long C, long is, int nb, const Geo&, int hist, int* act);
+                            const void* H3, const void* H4, long C, long is, int nb, const Geo&, int hist, int* act);
   hipError_t (*imp_update)(hipStream_t, const void* Nh, const void* U0, void* D, void* U1, double* part, long C,
                            long is, int nb, const Geo&, double nu, double dt, const int* act);
   hipError_t (*imp_advance)(hipStream_t, void* U0, const void* D, long C, long is, int nb, const Geo&);
@@ -472,10 +472,11 @@ struct Impl {
     return hipGetLastError();
   }
   static hipError_t imp_predict(hipStream_t s, const void* U0, void* D, void* U1, const void* H1, const void* H2,
-                                const void* H3, long C, long is, int nb, const Geo& g, int hist, int* act) {
+                                const void* H3, const void* H4, long C, long is, int nb, const Geo& g, int hist,
+                                int* act) {
     hipLaunchKernelGGL((k_imp_predict<T>), dim3(grid_1d(C, 256), (unsigned)nb), dim3(256), 0, s, (const cx<T>*)U0,
-                       (cx<T>*)D, (cx<T>*)U1, (const cx<T>*)H1, (const cx<T>*)H2, (const cx<T>*)H3, C, is, g, hist,
-                       act);
+                       (cx<T>*)D, (cx<T>*)U1, (const cx<T>*)H1, (const cx<T>*)H2, (const cx<T>*)H3,
+                       (const cx<T>*)H4, C, is, g, hist, act);
     return hipGetLastError();
   }
   static hipError_t imp_update(hipStream_t s, const void* Nh, const void* U0, void* D, void* U1, double* part, long C,

@@ -1337,15 +1337,16 @@ __global__ __launch_bounds__(W* Plan::Tl) void k_x_fwd_rk(const cx<T>* __restric
 // ---------------------------------------------------------------------------
 
 
-// Predictor from the increments of earlier steps (H1 newest): hist = 0: d = 0;
-// 1: d = H1; 2: d = 2 H1 - H2; 3: d = 3 H1 - 3 H2 + H3 (the polynomial
-// through the last increments, one step ahead).  Writes d and the midpoint
-// U1 = U0 + d/2, and marks the instance active.
+// Predictor from the increments of earlier steps (H1 newest), the polynomial
+// through the last hist of them one step ahead: hist = 0: d = 0; 1: d = H1;
+// 2: d = 2 H1 - H2; 3: d = 3 H1 - 3 H2 + H3; 4: d = 4 H1 - 6 H2 + 4 H3 - H4.
+// Writes d and the midpoint U1 = U0 + d/2, and marks the instance active.
 template <typename T>
 __global__ __launch_bounds__(256) void k_imp_predict(const cx<T>* __restrict__ U0, cx<T>* __restrict__ D,
                                                      cx<T>* __restrict__ U1, const cx<T>* __restrict__ H1,
                                                      const cx<T>* __restrict__ H2, const cx<T>* __restrict__ H3,
-                                                     long C, long is, Geo g, int hist, int* __restrict__ act) {
+                                                     const cx<T>* __restrict__ H4, long C, long is, Geo g, int hist,
+                                                     int* __restrict__ act) {
   const long ib = blockIdx.y * is;
   if (blockIdx.x == 0 && threadIdx.x == 0) act[blockIdx.y] = 1;
   const long stride = (long)gridDim.x * blockDim.x;
@@ -1357,7 +1358,8 @@ __global__ __launch_bounds__(256) void k_imp_predict(const cx<T>* __restrict__ U
       cx<T> d = {T(0), T(0)};
       if (hist == 1) d = H1[i];
       if (hist == 2) d = H1[i] * T(2) - H2[i];
-      if (hist >= 3) d = (H1[i] - H2[i]) * T(3) + H3[i];
+      if (hist == 3) d = (H1[i] - H2[i]) * T(3) + H3[i];
+      if (hist >= 4) d = (H1[i] + H3[i]) * T(4) - H2[i] * T(6) - H4[i];
       D[i] = d;
       U1[i] = U0[i] + d * T(0.5);
     }

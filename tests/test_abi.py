@@ -187,8 +187,8 @@ def test_implicit_plan_validation_and_workspace():
     binding.hot_destroy(h)
     nparts = -(-C // 256)
     base = 4 * _align(3 * C * elem) + _align(6 * D1 * elem) + _align(6 * D2 * elem) + _align(64 * 2 * 8)
-    # + three histories, the flag, the partial sums and the two counters
-    assert ws == base + 3 * _align(3 * C * elem) + _align(4) + _align(nparts * 16) + _align(2 * 4)
+    # + four histories, the flag, the partial sums and the two counters
+    assert ws == base + 4 * _align(3 * C * elem) + _align(4) + _align(nparts * 16) + _align(2 * 4)
 
 
 def test_implicit_stats_and_graph_rules_without_the_gpu():

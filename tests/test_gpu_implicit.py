@@ -44,11 +44,14 @@ def test_one_step_fp64_matches_oracle(N, kind):
     assert np.all(got[:, ~M] == 0)
 
 
-def test_four_steps_fp64_use_the_extrapolation_predictor():
+@pytest.mark.parametrize("nsteps", [4, 7])
+def test_several_steps_fp64_use_the_extrapolation_predictor(nsteps):
+    # 7 steps: every predictor depth (0 to 4 increments) and the rotation of
+    # the five buffers past one full turn
     N, dt, tol = 24, 0.02, 1e-10
     u0 = inputs.smooth_random(N, 3) * 4.0
-    (got,), sw, nc, rc = run_implicit([u0], "f64", NU, dt, 4, tol)
-    ref, s_ref, incs, _ = oracle.implicit_midpoint(u0, NU, dt, 4, tol)
+    (got,), sw, nc, rc = run_implicit([u0], "f64", NU, dt, nsteps, tol)
+    ref, s_ref, incs, _ = oracle.implicit_midpoint(u0, NU, dt, nsteps, tol)
     err, nu_, _ = _state_err(got, ref, u0)
     assert err <= 1e-12 * nu_ + 10 * tol * sum(np.linalg.norm(d) for d in incs)
     assert sw == [sum(s_ref)] and nc == [0] and rc == binding.HOT_OK

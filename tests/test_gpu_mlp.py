@@ -182,20 +182,21 @@ def test_surrogate_warm_started_steps_converge_to_the_oracle():
     assert err <= 1e-12 * np.linalg.norm(ref) + 10 * tol * sum(np.linalg.norm(d) for d in incs)
 
 
-def test_keep_history_continues_bitwise():
+@pytest.mark.parametrize("first,second", [(2, 2), (3, 4)])
+def test_keep_history_continues_bitwise(first, second):
     N, nu, dt = 24, 1.0 / 1600, 0.02
     u0 = inputs.rough_random(N, 31) * 3.0
     torch = _torch()
-    (one,), s_one, _, _ = run_implicit([u0], "f64", nu, dt, 4, 1e-10)
+    (one,), s_one, _, _ = run_implicit([u0], "f64", nu, dt, first + second, 1e-10)
     h, wsb = binding.hot_plan(N, "implicit", "f64", nu=nu, dt=dt, tol=1e-10, max_iter=50, keep_history=True)
     try:
         ws = workspace(wsb)
         x = to_dev(u0, "f64")
         y = torch.empty_like(x)
-        binding.hot_run(h, [x], [y], ws, 2)
+        binding.hot_run(h, [x], [y], ws, first)
         s_a, _ = binding.hot_implicit_stats(h, 1)
         z = torch.empty_like(x)
-        binding.hot_run(h, [y], [z], ws, 2)
+        binding.hot_run(h, [y], [z], ws, second)
         s_b, _ = binding.hot_implicit_stats(h, 1)
         torch.cuda.synchronize()
         two = z.cpu().numpy()

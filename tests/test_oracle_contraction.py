@@ -87,3 +87,25 @@ def test_three_increment_predictor_saves_a_sweep(N, seed):
     # the oracle's own step from that predictor stops there too
     _, sweeps, ok, _ = oracle.implicit_midpoint_step(u, NU, DT, TAU, 20, extrapolation_predictor(u, incs))
     assert ok and sweeps == 2
+
+
+@pytest.mark.parametrize("N,seed", [(32, 20002), (64, 20000)])
+def test_four_increment_predictor_meets_tau_at_once(N, seed):
+    """With four steps of history the plain predictor is the cubic
+    extrapolation 4 D1 - 6 D2 + 4 D3 - D4: its error is below tau itself, so
+    the change of the first sweep already passes the stopping test, and the
+    iterate it returns is within a few hundredths of tau of the fixed point."""
+    u0 = inputs.smooth_random(N, seed)
+    u, _, incs, _ = oracle.implicit_midpoint(u0, NU, DT, 4, 1e-13)
+    pred = extrapolation_predictor(u, incs)
+    ref, _, ok, _ = oracle.implicit_midpoint_step(u, NU, DT, 1e-14, 80, pred)
+    assert ok
+    inc = half_norm(ref - u)
+    m = oracle.retained_mask(N)
+    e0 = half_norm(pred * m - ref) / inc
+    w1, _ = midpoint_sweep(u, pred * m, NU, DT)
+    e1 = half_norm(w1 - ref) / inc
+    print(f"N={N}: cubic extrapolation e_0 = {e0:.2e}, after one sweep {e1:.2e}", flush=True)
+    assert e0 < TAU and e1 < 0.1 * TAU
+    _, sweeps, ok, _ = oracle.implicit_midpoint_step(u, NU, DT, TAU, 20, pred)
+    assert ok and sweeps == 1

@@ -93,7 +93,7 @@ def test_picard_stops_at_tolerance_and_extrapolation_saves_sweeps():
     u0 = inputs.smooth_random(N, 8) * 4.0
     u, sweeps, incs, _ = oracle.implicit_midpoint(u0, NU, dt, 4, tau=1e-10)
     # the stopping test is met by the returned iterate of the last step
-    pred = oracle.extrapolation_predictor(u - incs[-1], incs[-4:-1])
+    pred = oracle.extrapolation_predictor(u - incs[-1], incs[:-1])
     _, s_plain, _, _ = oracle.implicit_midpoint_step(u - incs[-1], NU, dt, 1e-10, 50, None)
     _, s_pred, _, _ = oracle.implicit_midpoint_step(u - incs[-1], NU, dt, 1e-10, 50, pred)
     assert s_pred == sweeps[-1]
@@ -141,9 +141,21 @@ def test_three_increment_predictor_is_exact_on_cubic_trajectories():
     assert np.allclose(pred, u[4], rtol=0, atol=1e-11)
     pred2 = oracle.extrapolation_predictor(u[3], incs[1:])
     assert np.allclose(u[4] - pred2, 6 * E, rtol=0, atol=1e-11)
-    # only the last three increments count
-    pred4 = oracle.extrapolation_predictor(u[3], [rng.standard_normal(A.shape)] + incs)
-    assert np.array_equal(pred4, pred)
+
+
+def test_four_increment_predictor_is_exact_on_quartic_trajectories():
+    # degree 4 from four increments; the three-increment form misses it by the
+    # fourth difference, 24 F; a fifth, older increment is not used
+    rng = np.random.default_rng(3)
+    A, B, C, E, F = (rng.standard_normal((3, 4, 4, 3)) for _ in range(5))
+    u = [A + B * t + C * t * t + E * t ** 3 + F * t ** 4 for t in range(6)]
+    incs = [u[t + 1] - u[t] for t in range(4)]
+    pred = oracle.extrapolation_predictor(u[4], incs)
+    assert np.allclose(pred, u[5], rtol=0, atol=1e-9)
+    pred3 = oracle.extrapolation_predictor(u[4], incs[1:])
+    assert np.allclose(u[5] - pred3, 24 * F, rtol=0, atol=1e-9)
+    pred5 = oracle.extrapolation_predictor(u[4], [rng.standard_normal(A.shape)] + incs)
+    assert np.array_equal(pred5, pred)
 
 
 def test_stopping_rule_is_update_over_increment():
