@@ -8,14 +8,16 @@
 //
 // Work items are (pass, size, instance, tile or plane), numbered pass-level
 // by pass-level (every size's items of one level before the next level's).
-// A block takes the next number from a queue head in the control block and
-// runs that item; before it starts, it waits until every item of the same
-// size in earlier levels has completed (one completion counter per size: a
-// level-l item needs the counter at the number of items in levels < l).  An
-// item waits only on lower numbers, which running blocks already hold, so
-// the wait always ends.  A wait is still bounded: past the bound the kernel
-// raises the error flag, no item waits any more, and every scatter item from
-// then on writes NaN.
+// A block takes the next kPersistChunk numbers from a queue head in the
+// control block and runs those items in order; before an item starts, the
+// block waits until every item of the same size in earlier levels has
+// completed (one completion counter per size: a level-l item needs the
+// counter at the number of items in levels < l).  A block adds its completed
+// items to the counters before it waits and at the end of each chunk, so a
+// waiting block holds none back.  An item waits only on lower numbers, which
+// running blocks already hold, so the wait always ends.  A wait is still
+// bounded: past the bound the kernel raises the error flag, no item waits
+// any more, and every scatter item from then on writes NaN.
 //
 // One block shape serves every pass: 576 threads (nine waves), which every
 // line length of the batch sizes divides, so that a tile of the x passes is
