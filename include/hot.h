@@ -90,7 +90,7 @@ extern "C" {
  *       call).  Each instance stops on
  *       its own: the kernels of a sweep return at once for an instance that
  *       has stopped.  Sweeps are enqueued in rounds of K (hot_set_variant
- *       pass "imp_decide", default 3); after each round but the last an
+ *       pass "imp_decide", default 2); after each round but the last an
  *       eager call copies the stopping flags to the host, waits for them,
  *       and enqueues no further sweeps for a size whose instances have all
  *       stopped (a sweep launches every block even when they all return at
@@ -254,7 +254,7 @@ int hot_tuned_width(hot_plan_t p, int32_t instance, int32_t pass);
  * about a second: a wait past it raises an error flag, no wait follows and
  * the call's outputs from then on are NaN (a small bound forces that path for
  * tests); for "imp_decide" (IMPLICIT plans only) the sweeps per round
- * between an eager call's looks at the stopping flags, K >= 0 (default 3; 0:
+ * between an eager call's looks at the stopping flags, K >= 0 (default 2; 0:
  * never look, enqueue max_iter sweeps).  hot_tuned_width reports these
  * settings for the non-tiled passes.  Host only.  Errors: HOT_E_INVALID. */
 int hot_set_variant(hot_plan_t p, int32_t pass, int32_t variant);

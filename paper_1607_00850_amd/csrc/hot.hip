@@ -187,7 +187,7 @@ struct hot_plan_s {
   bool graph_branches = true;  // hot_set_variant(graph): 1 branch per group, 0 one chain
   bool persistent = false;     // hot_set_variant(graph) 2: the persistent kernel (RK4)
   int persist_spin = 0;        // hot_set_variant(persistent): polls of a wait before its error path (0: default)
-  int imp_check = 3;           // implicit step: sweeps between the host's looks at the flags (0: never)
+  int imp_check = 2;           // implicit step: sweeps between the host's looks at the flags (0: never)
   std::vector<int> act_host;   // implicit step: the flags read back, per instance
 };
 

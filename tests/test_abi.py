@@ -310,7 +310,7 @@ def test_implicit_flag_check_rules_without_the_gpu():
     names = binding.pass_names()
     h, _ = binding.hot_plan(16, "implicit", "f32", nu=0.01, dt=1e-3)
     try:
-        assert binding.hot_tuned_width(h, 0, "imp_decide") == 3  # default: look every 3 sweeps
+        assert binding.hot_tuned_width(h, 0, "imp_decide") == 2  # default: look every 2 sweeps
         for k in (0, 1, 7):
             binding.hot_set_variant(h, "imp_decide", k)
             assert binding.hot_tuned_width(h, 0, "imp_decide") == k
