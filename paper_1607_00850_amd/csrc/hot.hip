@@ -642,21 +642,23 @@ void stage_passes(Runner& r, const Group& G, const GroupPtrs& q, const char* src
 void write_tables(Runner& r, const Group& G, const GroupPtrs& q, void* const* in, void* const* out) {
   const int nb = G.B();
   if (nb < 2) return;
-  for (int side = 0; side < 3; ++side) {
-    // in pointers, out pointers, instance indices (as pointer-sized integers)
-    const void** dst = side == 0 ? (const void**)q.in_tab : (side == 1 ? (const void**)q.out_tab : (const void**)q.idx_tab);
-    for (int m0 = 0; m0 < nb && r.rc == HOT_OK; m0 += kTabChunk) {
-      TabChunk c{};
-      const int n = nb - m0 < kTabChunk ? nb - m0 : kTabChunk;
-      for (int m = 0; m < n; ++m) {
-        const int i = G.members[m0 + m];
-        c.p[m] = side == 0 ? in[i] : (side == 1 ? (const void*)out[i] : (const void*)(intptr_t)i);
-      }
-      r.pass(PASS_TABLES, [&] {
-        hipLaunchKernelGGL(k_write_tab<>, dim3(1), dim3(256), 0, r.s, dst + m0, c, n);
-        return hipGetLastError();
-      });
+  // the in pointers, out pointers and instance indices (as pointer-sized
+  // integers) lie nb entries apart from in_tab on
+  static_assert(sizeof(TabChunk) + 2 * sizeof(void*) + sizeof(int) <= 4096, "kernel argument size");
+  const void** tab = (const void**)q.in_tab;
+  for (int m0 = 0; m0 < nb && r.rc == HOT_OK; m0 += kTabChunk) {
+    TabChunk c{};
+    const int n = nb - m0 < kTabChunk ? nb - m0 : kTabChunk;
+    for (int m = 0; m < n; ++m) {
+      const int i = G.members[m0 + m];
+      c.in[m] = in[i];
+      c.out[m] = out[i];
+      c.idx[m] = (const void*)(intptr_t)i;
     }
+    r.pass(PASS_TABLES, [&] {
+      hipLaunchKernelGGL(k_write_tab<>, dim3(1), dim3(256), 0, r.s, tab + m0, (long)nb, c, n);
+      return hipGetLastError();
+    });
   }
 }
 

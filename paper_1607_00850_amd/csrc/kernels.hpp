@@ -1657,16 +1657,25 @@ __device__ __forceinline__ void pos4_add(Pos4& p, const Pos4& s, int na, int nb,
 // Device pointer tables of a batch (the canonical arrays of its instances):
 // the pointers travel as kernel arguments, so the tables are written in
 // stream order with no host synchronisation, and a call captured into a graph
-// records them by value.
-constexpr int kTabChunk = 240;
+// records them by value.  One chunk carries the input pointers, the output
+// pointers and the instance indices of up to kTabChunk members (3840 bytes of
+// the 4096 a kernel's arguments may take); the three tables lie nb entries
+// apart.
+constexpr int kTabChunk = 160;
 struct TabChunk {
-  const void* p[kTabChunk];
+  const void* in[kTabChunk];
+  const void* out[kTabChunk];
+  const void* idx[kTabChunk];
 };
 
 template <int Unused = 0>
-__global__ __launch_bounds__(256) void k_write_tab(const void** __restrict__ dst, TabChunk c, int n) {
+__global__ __launch_bounds__(256) void k_write_tab(const void** __restrict__ tab, long nb, TabChunk c, int n) {
   const int i = threadIdx.x;
-  if (i < n) dst[i] = c.p[i];
+  if (i < n) {
+    tab[i] = c.in[i];
+    tab[nb + i] = c.out[i];
+    tab[2 * nb + i] = c.idx[i];
+  }
 }
 
 // The elements e0, e0 + stride, ... of one instance (st: stride in the
