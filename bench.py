@@ -91,7 +91,7 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, command):
     # x inverse variants); k_strided forward with compact output rows is the
     # y forward pass when the x forward pass is fused with the stage update
     names = {"k_z_cross": "z_cross", "k_z_cross_packed": "z_cross", "k_x_inv_curl": "x_inv_curl",
-             "k_x_inv_curl3": "x_inv_curl", "k_rk_stage": "rk_stage", "k_gather": "gather",
+             "k_x_inv_curl3": "x_inv_curl", "k_rk_stage": "rk_stage", "k_gather": "gather", "k_gather_t": "gather",
              "k_scatter": "scatter", "y_inv": "y_inv", "k_y_inv_pack": "y_inv", "k_x_fwd_rk": "x_fwd_rk",
              "y_or_x_fwd": "y_fwd", "k_y_fwd_unpack": "y_fwd", "k_y_fwd_unpack3": "y_fwd"}
     out = {"fetch_scale": fs, "write_scale": ws, "command": command}

@@ -456,8 +456,22 @@ struct Impl {
     if (g.tw == g.M * g.Mzp) return pos4_of(stride, g.M, g.M, g.Mzp);
     return pos4_of(stride, g.M * (g.Mzp / g.tw), g.M, g.tw);
   }
+  // compact rows per block of the transposing gather: about 22 KB of LDS
+  // at N = 1024
+  static constexpr int kRX = std::is_same_v<T, float> ? 8 : 4;
+  static size_t transpose_lds(const Geo& g) { return (size_t)kRX * (g.Mzp + 1) * sizeof(cx<T>); }
   static hipError_t gather(hipStream_t s, const void* in0, const void* const* in_tab, void* out, long C, long is,
                            int nb, const Geo& g) {
+    if (g.tw < g.M * g.Mzp) {  // column-tiled state: through LDS
+      const size_t lds = transpose_lds(g);
+      hipError_t e = hipFuncSetAttribute((const void*)k_gather_t<T, kRX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds);
+      if (e != hipSuccess) return e;
+      const dim3 grid((unsigned)((g.M + kRX - 1) / kRX), (unsigned)(3 * g.M), (unsigned)nb);
+      hipLaunchKernelGGL((k_gather_t<T, kRX>), grid, dim3(256), lds, s, (const cx<T>*)in0,
+                         (const cx<T>* const*)in_tab, (cx<T>*)out, C, is, g);
+      return hipGetLastError();
+    }
     const unsigned grid = grid_1d((3 * C + 3) / 4, 256);  // a few elements per thread
     hipLaunchKernelGGL((k_gather<T>), dim3(grid, (unsigned)nb), dim3(256), 0, s, (const cx<T>*)in0,
                        (const cx<T>* const*)in_tab, (cx<T>*)out, C, is, g, gather_step(256L * grid, g));

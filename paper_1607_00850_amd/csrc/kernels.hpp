@@ -1741,4 +1741,49 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ in, c
                (long)gridDim.x * blockDim.x);
 }
 
+// Canonical -> column-tiled compact state through LDS (tw < M * Mzp).  A
+// block takes RX consecutive compact kx rows of one compact ky row iy
+// (blockIdx.y = component * M + iy) and holds them as [RX][Mzp + 1] values
+// in LDS: the canonical rows (kx, ky, all retained kz) are read whole, and
+// each compact tile of the ky row (tw kz columns, rows kx contiguous) is
+// written as RX * tw consecutive values.  k_gather reads the canonical rows
+// in 64-byte pieces instead (measured at 1024^3: 2.0 against 1.4 ms).  A
+// scatter of the same shape (with the zero rows) measured 4.4 ms against
+// 3.9 ms for k_scatter, whose canonical writes are already whole rows.
+// blockIdx.z is the instance of a batch.
+template <typename T, int RX>
+__global__ __launch_bounds__(256) void k_gather_t(const cx<T>* __restrict__ in0, const cx<T>* const* __restrict__ in_tab,
+                                                  cx<T>* __restrict__ out, long C, long is, Geo g) {
+  extern __shared__ unsigned char gt_smem[];
+  cx<T>* sm = reinterpret_cast<cx<T>*>(gt_smem);
+  const cx<T>* __restrict__ in = in_tab ? in_tab[blockIdx.z] : in0;
+  out += blockIdx.z * is;
+  const int tid = threadIdx.x;
+  const int c = blockIdx.y / g.M, iy = blockIdx.y - c * g.M;
+  const int x0 = blockIdx.x * RX, nr = g.M - x0 < RX ? g.M - x0 : RX;
+  const int ky = cpos(iy, g), Nh = g.czp, P = g.Mzp + 1, tpr = g.Mzp / g.tw, Mz = g.Mz;
+  // eight loads in flight per thread before their LDS stores
+  for (int f0 = 0; f0 < nr * Mz; f0 += 8 * 256) {
+    cx<T> v[8];
+    int at[8];
+    static_for<0, 8>([&](auto k) {
+      const int f = f0 + k * 256 + tid;
+      const bool ok = f < nr * Mz;
+      const int r = ok ? f / Mz : 0, kz = ok ? f - r * Mz : 0;
+      v[k] = in[(((long)c * g.N + cpos(x0 + r, g)) * g.N + ky) * Nh + kz];
+      at[k] = ok ? r * P + kz : -1;
+    });
+    static_for<0, 8>([&](auto k) {
+      if (at[k] >= 0) sm[at[k]] = v[k];
+    });
+  }
+  __syncthreads();
+  const int tile = nr * g.tw;
+  for (int f = tid; f < tpr * tile; f += 256) {
+    const int t = f / tile, rem = f - t * tile, r = rem / g.tw, zz = rem - r * g.tw;
+    const int kz = t * g.tw + zz;
+    if (kz < Mz) store_stream(out + c * C + ((long)(iy * tpr + t) * g.M + x0 + r) * g.tw + zz, sm[r * P + kz]);
+  }
+}
+
 }  // namespace hot
