@@ -1723,13 +1723,28 @@ template <typename T>
 __device__ __forceinline__ void scatter_part(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long C,
                                              const Geo& g, Pos4 st, long e, long stride) {
   const int Nh = g.czp;
-  // canonical [3][N][N][Nh]; st: the stride in the same digits
+  // canonical [3][N][N][Nh]; st: the stride in the same digits.  Four
+  // elements per round, their loads issued before any store (an element
+  // outside the retained set loads slot 0 and stores zero).
   Pos4 p = pos4_first((unsigned)e, g.N, g.N, Nh);
-  for (; p.c < 3; e += stride, pos4_add(p, st, g.N, g.N, Nh)) {
-    cx<T> v = {T(0), T(0)};
-    if (p.z < g.Mz && kept(p.a, g) && kept(p.b, g))
-      v = in[(long)p.c * C + cbase((long)crow(p.b, g) * g.Mzp + p.z, g) + (long)crow(p.a, g) * g.tw];
-    store_stream(out + e, v);
+  while (p.c < 3) {
+    cx<T> v[4];
+    long eo[4];
+    bool ok[4];
+    static_for<0, 4>([&](auto k) {
+      ok[k] = p.c < 3;
+      const bool live = ok[k] && p.z < g.Mz && kept(p.a, g) && kept(p.b, g);
+      const long src =
+          live ? (long)p.c * C + cbase((long)crow(p.b, g) * g.Mzp + p.z, g) + (long)crow(p.a, g) * g.tw : 0;
+      const cx<T> x = in[src];
+      v[k] = live ? x : cx<T>{T(0), T(0)};
+      eo[k] = e;
+      e += stride;
+      pos4_add(p, st, g.N, g.N, Nh);
+    });
+    static_for<0, 4>([&](auto k) {
+      if (ok[k]) store_stream(out + eo[k], v[k]);
+    });
   }
 }
 
