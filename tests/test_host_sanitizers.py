@@ -1,8 +1,8 @@
 """The host side of libhot (planning, workspace layout, argument checks,
 variants, error paths) under AddressSanitizer and UndefinedBehaviorSanitizer.
 
-hot.hip and mlp.hip are compiled again with the sanitizers on their host
-pass only (device code is built as usual), linked with the kernel objects of
+hot.hip, mlp.hip and persist.hip are compiled again with the sanitizers on
+their host pass only (device code is built as usual), linked with the kernel objects of
 the last in-tree build, and tests/test_abi.py runs against that library in a
 child process with the ASan runtime preloaded.  Any report fails the test:
 UBSan does not recover, ASan halts on the first error.  Leak detection is off
@@ -25,7 +25,7 @@ SAN_FLAGS = ["-O1", "-g",
              "-Xarch_host", "-fsanitize=undefined",
              "-Xarch_host", "-fno-sanitize-recover=undefined",
              "-Xarch_host", "-fno-omit-frame-pointer"]
-HOST_UNITS = ("hot.hip", "mlp.hip")
+HOST_UNITS = ("hot.hip", "mlp.hip", "persist.hip")
 
 
 def _asan_runtime():
