@@ -220,7 +220,10 @@ int hot_graph_destroy(hot_graph_t graph);
  * not touched) and keep the fastest for later hot_run calls.  For RK4 and
  * RHS it also times the x forward pass fused with the stage update (pass
  * "x_fwd_rk": the nonlinear term stays in registers) against the two
- * separate passes and keeps the faster.  Synchronises the stream.
+ * separate passes and keeps the faster, and for the sizes that have it the
+ * fused y-z pass against the separate y and z passes (a plan with several
+ * distinct N keeps the fused pass untimed: its sizes run side by side and
+ * share the HBM, which the fused pass spares).  Synchronises the stream.
  * hot_tuned_width reports the chosen columns per block of a pass for
  * instance i (for x_fwd_rk: 0 when the separate passes were kept), or a
  * negative error code. */

@@ -1347,8 +1347,15 @@ extern "C" int hot_tune(hot_plan_t p, void* workspace, void* stream, int32_t rep
       }
       G.variant[pid] = best_v;
     }
-    // small N: the y and z passes fused, or the three separate passes
-    if (rc == HOT_OK && G.ops.yz_fused && p->nranks == 1) {
+    // small N: the y and z passes fused, or the three separate passes.  With
+    // several sizes the fused pass is kept wherever it exists, untimed: the
+    // sizes run side by side (graph branches) and share the HBM, and the
+    // fused pass moves 9 D1 values against 12 D1 + 18 D2 (4096 uneven
+    // instances: 19.45 ms per graph replay against 20.3 with the per-size
+    // timing's choice, the separate passes for N = 48)
+    if (rc == HOT_OK && G.ops.yz_fused && p->nranks == 1 && p->groups.size() > 1) {
+      G.yz = 0;
+    } else if (rc == HOT_OK && G.ops.yz_fused && p->nranks == 1) {
       float best = 1e30f;
       int best_y = -1;
       for (int yv = -1; yv <= 0 && rc == HOT_OK; ++yv) {
