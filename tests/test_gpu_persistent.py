@@ -148,3 +148,32 @@ def test_persistent_wait_bound_ends_the_call():
             assert rel_l2(got, oracle.rk4(round32(fields[i]), NU, DT, 1)) < fp32_tol(N), N
     finally:
         binding.hot_destroy(h)
+
+
+def test_persistent_stats_match_the_per_pass_schedule():
+    """stats_dev after a persistent call: E and eps of every instance's state
+    equal those after the per-pass schedule to rounding (the states agree to
+    a few ulps)."""
+    import torch
+    print("persistent, stats_dev", flush=True)
+    fields = _fields(SIZES)
+    res = {}
+    for name, variants in (("per_pass", FUSED), ("persistent", {"graph": 2})):
+        h, wsb = binding.hot_plan([f.shape[1] for f in fields], "rk4", "f32", "two_thirds", NU, DT)
+        try:
+            for k, v in variants.items():
+                binding.hot_set_variant(h, k, v)
+            ins = [to_dev(f, "f32") for f in fields]
+            outs = [torch.empty_like(x) for x in ins]
+            st = binding.stats_buffer(len(fields))
+            binding.hot_run(h, ins, outs, workspace(wsb), 2, stats=st)
+            torch.cuda.synchronize()
+            res[name] = binding.stats_view(st)
+        finally:
+            binding.hot_destroy(h)
+    E0, eps0, _, _ = res["per_pass"]
+    E1, eps1, sw, nc = res["persistent"]
+    assert np.all(E0 > 0) and np.all(eps0 > 0)
+    np.testing.assert_allclose(E1, E0, rtol=1e-6)
+    np.testing.assert_allclose(eps1, eps0, rtol=1e-6)
+    assert not np.any(sw) and not np.any(nc)
