@@ -848,7 +848,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}, WORLD_SIZE {world}); "
+        print(f"bench.py: libhot runs on one GPU (asked for --gpus {a.gpus}, WORLD_SIZE {world}); "
               "the multi-GPU slab decomposition is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
 

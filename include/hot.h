@@ -43,7 +43,7 @@ extern "C" {
 /* Return codes. */
 #define HOT_OK 0
 #define HOT_E_INVALID (-1)     /* bad argument (null, odd N, nu < 0, dt <= 0, bad enum, ...) */
-#define HOT_E_UNSUPPORTED (-2) /* valid request this build does not implement (e.g. an N) */
+#define HOT_E_UNSUPPORTED (-2) /* valid request the library does not implement (e.g. an N) */
 #define HOT_E_WORKSPACE (-3)   /* workspace pointer null or misaligned */
 #define HOT_E_HIP (-4)         /* a HIP call failed; hot_last_hip_error() has the code */
 #define HOT_E_NONFINITE (-5)   /* HOT_FLAG_CHECK_FINITE: a result holds a NaN or an infinity */
