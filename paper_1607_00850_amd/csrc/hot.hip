@@ -908,7 +908,7 @@ int enqueue(hot_plan_s* p, void* const* in, void* const* out, void* workspace, i
 // the end of a step: d becomes the newest history.
 //
 // Sweeps go out in rounds of imp_check over every group still iterating
-// (each group on its own stream with branches).  Between rounds an eager call
+// (each group on its own stream with branches, enqueued in branch_order).  Between rounds an eager call
 // copies the flags of those groups to the host and waits for their streams:
 // once no instance of a group iterates, its remaining sweeps are not enqueued
 // (a sweep whose flags are all clear still launches every block of every
@@ -947,6 +947,9 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
   }
   const int every = record ? p->imp_check : 0;
   std::vector<char> live(ng);
+  std::vector<size_t> order(ng);
+  for (size_t i = 0; i < ng; ++i) order[i] = i;
+  if (br) order = branch_order(p);
   for (int step = 0; step < nsteps && r.rc == HOT_OK; ++step) {
     // the iterate d and the histories H1 (newest) to H4 rotate through five buffers
     auto bufs = [&](size_t gi, char*& D, char*& H1, char*& H2, char*& H3, char*& H4) {
@@ -958,7 +961,8 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
       H3 = buf[(G.rot + 3) % 5];
       H4 = buf[(G.rot + 4) % 5];
     };
-    for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {
+    for (const size_t gi : order) {
+      if (r.rc != HOT_OK) break;
       const Group& G = p->groups[gi];
       const GroupPtrs& q = qs[gi];
       r.s = stream_of(gi);
@@ -983,7 +987,8 @@ int run_implicit(hot_plan_s* p, void* const* in, void* const* out, void* workspa
     }
     for (int done = 0; done < p->max_iter && r.rc == HOT_OK;) {
       const int k = every > 0 && every < p->max_iter - done ? every : p->max_iter - done;
-      for (size_t gi = 0; gi < ng && r.rc == HOT_OK; ++gi) {
+      for (const size_t gi : order) {
+        if (r.rc != HOT_OK) break;
         if (!live[gi]) continue;
         const Group& G = p->groups[gi];
         const GroupPtrs& q = qs[gi];
